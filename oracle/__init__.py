@@ -1,0 +1,313 @@
+"""Python face of the FP64 CPU oracle (``dpd_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by
+the benchmark's CPU-baseline leg.  The product package never imports it and
+it imports nothing from the product package.
+
+Each wrapper takes and returns numpy arrays in the library layout
+(``float64[3, N]`` structure of arrays, ``uint32`` tags, ``uint8`` types)
+and calls the C function of the same name; see ``dpd_oracle.c`` for the
+paper passage each one follows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "dpd_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+MAX_TYPES = 8
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle with gcc (no FMA contraction, OpenMP)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math",
+           "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wno-unknown-pragmas",
+           SRC, "-o", LIB + ".tmp", "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        _lib = C.CDLL(LIB)
+        _declare(_lib)
+    return _lib
+
+
+class OrcParams(C.Structure):
+    _fields_ = [
+        ("box", C.c_double * 3),
+        ("r_c", C.c_double),
+        ("r_list", C.c_double),
+        ("s", C.c_double),
+        ("dt", C.c_double),
+        ("lam", C.c_double),
+        ("n_types", C.c_int32),
+        ("a", C.c_double * (MAX_TYPES * MAX_TYPES)),
+        ("gamma", C.c_double * (MAX_TYPES * MAX_TYPES)),
+        ("sigma", C.c_double * (MAX_TYPES * MAX_TYPES)),
+        ("seed", C.c_uint64),
+        ("body_g", C.c_double),
+        ("body_split", C.c_double),
+        ("bond_k", C.c_double),
+        ("bond_r0", C.c_double),
+        ("partner", C.c_void_p),
+    ]
+
+
+P = C.c_void_p
+
+
+def _declare(L):
+    L.orc_philox4x32_10.argtypes = [P, P, P]
+    L.orc_philox_batch.argtypes = [C.c_int64, P, P, P]
+    L.orc_xi.argtypes = [C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint64]
+    L.orc_xi.restype = C.c_double
+    L.orc_xi_batch.argtypes = [C.c_int64, P, P, C.c_uint64, C.c_uint64, P]
+    L.orc_cell_grid.argtypes = [P, C.c_double, P]
+    L.orc_cell_grid.restype = C.c_int
+    L.orc_morton_rank_table.argtypes = [P, P]
+    L.orc_reorder.argtypes = [C.c_int32, P, P, P, C.c_double, P, P]
+    L.orc_reorder.restype = C.c_int
+    L.orc_neighbors_brute.argtypes = [C.c_int32, P, P, C.c_double, C.c_int32, P, P, P, C.c_int64]
+    L.orc_neighbors_brute.restype = C.c_int64
+    L.orc_neighbors_cells.argtypes = [C.c_int32, P, P, C.c_double, P, P, C.c_int64]
+    L.orc_neighbors_cells.restype = C.c_int64
+    L.orc_forces.argtypes = [P, C.c_int32, P, P, P, P, C.c_int32, P, P, P, C.c_uint64, P, P, P]
+    L.orc_forces.restype = C.c_int
+    L.orc_step.argtypes = [P, C.c_int32, P, P, P, P, P, C.c_uint64, C.c_int, P]
+    L.orc_step.restype = C.c_int
+    L.orc_run.argtypes = [P, C.c_int32, P, P, P, P, P, C.c_uint64, C.c_int32, C.c_int,
+                          P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P]
+    L.orc_run.restype = C.c_int
+    L.orc_forces_vjp.argtypes = [P, C.c_int32, P, P, P, P, P, P, C.c_uint64, P, P, P, P, P]
+    L.orc_forces_vjp.restype = C.c_int
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def params(sys_, *, skin: float = 0.0) -> OrcParams:
+    """Oracle parameter block from a ``dpd_inputs.System``."""
+    p = OrcParams()
+    for k in range(3):
+        p.box[k] = float(sys_.box[k])
+    p.r_c = float(sys_.r_c)
+    p.r_list = float(sys_.r_c + skin)
+    p.s = float(sys_.s)
+    p.dt = float(sys_.dt)
+    p.lam = float(sys_.lam)
+    nt = int(sys_.n_types)
+    if nt < 1 or nt > MAX_TYPES:
+        raise ValueError("n_types out of range")
+    p.n_types = nt
+    for name in ("a", "gamma", "sigma"):
+        tab = np.asarray(getattr(sys_, name), dtype=np.float64).reshape(nt, nt)
+        arr = getattr(p, name)
+        for t in range(nt * nt):
+            arr[t] = float(tab.reshape(-1)[t])
+    p.seed = int(sys_.seed) & ((1 << 64) - 1)
+    p.body_g = float(sys_.body_g)
+    p.body_split = float(sys_.body_split)
+    p.bond_k = float(sys_.bond_k)
+    p.bond_r0 = float(sys_.bond_r0)
+    p._partner_keep = None
+    if sys_.partner is not None:
+        part = _c(sys_.partner, np.int32).reshape(-1)
+        p._partner_keep = part
+        p.partner = part.ctypes.data
+    else:
+        p.partner = None
+    return p
+
+
+# ---------------------------------------------------------------- RNG ----
+
+def philox(ctr: np.ndarray, key: np.ndarray) -> np.ndarray:
+    ctr = _c(ctr, np.uint32).reshape(-1, 4)
+    key = _c(key, np.uint32).reshape(-1, 2)
+    out = np.empty_like(ctr)
+    lib().orc_philox_batch(ctr.shape[0], _ptr(ctr), _ptr(key), _ptr(out))
+    return out
+
+
+def xi(ti, tj, step: int, seed: int) -> np.ndarray:
+    ti = _c(np.atleast_1d(ti), np.uint32)
+    tj = _c(np.atleast_1d(tj), np.uint32)
+    out = np.empty(ti.shape[0], dtype=np.float64)
+    lib().orc_xi_batch(ti.shape[0], _ptr(ti), _ptr(tj), int(step), int(seed) & ((1 << 64) - 1), _ptr(out))
+    return out
+
+
+# ------------------------------------------------------ cells, reorder ----
+
+def cell_grid(box, r_list: float):
+    box = _c(box, np.float64)
+    nc = np.zeros(3, dtype=np.int32)
+    rc = lib().orc_cell_grid(_ptr(box), float(r_list), _ptr(nc))
+    if rc != 0:
+        raise ValueError("box too small for the cell grid (need >= 3 cells per side)")
+    return nc
+
+
+def morton_rank_table(nc) -> np.ndarray:
+    nc = _c(nc, np.int32)
+    rank = np.empty(int(np.prod(nc.astype(np.int64))), dtype=np.int32)
+    lib().orc_morton_rank_table(_ptr(nc), _ptr(rank))
+    return rank
+
+
+def reorder(x, tag, box, r_list: float):
+    """(perm new->old, cell_start) ordered by (Morton rank of cell, tag)."""
+    x = _c(x, np.float64)
+    tag = _c(tag, np.uint32)
+    box = _c(box, np.float64)
+    n = x.shape[1]
+    nc = cell_grid(box, r_list)
+    perm = np.empty(n, dtype=np.int32)
+    cs = np.empty(int(np.prod(nc.astype(np.int64))) + 1, dtype=np.int32)
+    rc = lib().orc_reorder(n, _ptr(x), _ptr(tag), _ptr(box), float(r_list), _ptr(perm), _ptr(cs))
+    if rc != 0:
+        raise ValueError("orc_reorder failed")
+    return perm, cs
+
+
+# ---------------------------------------------------------- neighbours ----
+
+def neighbors(x, box, r_list: float, *, mode: str = "brute", query=None):
+    """CSR (off int64[nq+1], idx int32[nnz]) of ascending neighbour rows."""
+    x = _c(x, np.float64)
+    box = _c(box, np.float64)
+    n = x.shape[1]
+    L = lib()
+    if mode == "brute":
+        q = None if query is None else _c(query, np.int32)
+        nq = n if q is None else q.shape[0]
+        count = np.empty(nq, dtype=np.int32)
+        total = L.orc_neighbors_brute(n, _ptr(x), _ptr(box), float(r_list), nq, _ptr(q), _ptr(count), None, 0)
+        idx = np.empty(max(total, 1), dtype=np.int32)
+        L.orc_neighbors_brute(n, _ptr(x), _ptr(box), float(r_list), nq, _ptr(q), _ptr(count), _ptr(idx), total)
+    elif mode == "cells":
+        if query is not None:
+            raise ValueError("cells mode builds all rows")
+        count = np.empty(n, dtype=np.int32)
+        total = L.orc_neighbors_cells(n, _ptr(x), _ptr(box), float(r_list), _ptr(count), None, 0)
+        if total < 0:
+            raise ValueError("cell grid invalid")
+        idx = np.empty(max(total, 1), dtype=np.int32)
+        L.orc_neighbors_cells(n, _ptr(x), _ptr(box), float(r_list), _ptr(count), _ptr(idx), total)
+    else:
+        raise ValueError(mode)
+    off = np.zeros(count.shape[0] + 1, dtype=np.int64)
+    np.cumsum(count, out=off[1:])
+    return off, idx[:total]
+
+
+# -------------------------------------------------------------- forces ----
+
+def forces(sys_, x, v, tag, typ, step: int, *, nbr=None, query=None, skin: float = 0.0,
+           mode: str = "brute"):
+    """Forces (float64[3, nq]), per-row PE halves and per-row pair counts."""
+    p = params(sys_, skin=skin)
+    x = _c(x, np.float64)
+    v = _c(v, np.float64)
+    tag = _c(tag, np.uint32)
+    typ = _c(typ, np.uint8)
+    n = x.shape[1]
+    if nbr is None:
+        nbr = neighbors(x, sys_.box, p.r_list, mode=mode if query is None else "brute", query=query)
+    off, idx = nbr
+    off = _c(off, np.int64)
+    idx = _c(idx, np.int32)
+    q = None if query is None else _c(query, np.int32)
+    nq = n if q is None else q.shape[0]
+    f = np.empty((3, nq), dtype=np.float64)
+    pe = np.empty(nq, dtype=np.float64)
+    npair = np.empty(nq, dtype=np.int32)
+    lib().orc_forces(C.byref(p), n, _ptr(x), _ptr(v), _ptr(tag), _ptr(typ), nq, _ptr(q),
+                     _ptr(off), _ptr(idx), int(step), _ptr(f), _ptr(pe), _ptr(npair))
+    return f, pe, npair
+
+
+def step(sys_, x, v, f, tag, typ, step_next: int, *, use_cells: bool = False, skin: float = 0.0):
+    """One velocity-Verlet step in place on copies; returns (x, v, f, red[8])."""
+    p = params(sys_, skin=skin)
+    x = np.array(x, dtype=np.float64, order="C", copy=True)
+    v = np.array(v, dtype=np.float64, order="C", copy=True)
+    f = np.array(f, dtype=np.float64, order="C", copy=True)
+    tag = _c(tag, np.uint32)
+    typ = _c(typ, np.uint8)
+    red = np.zeros(8, dtype=np.float64)
+    rc = lib().orc_step(C.byref(p), x.shape[1], _ptr(x), _ptr(v), _ptr(f), _ptr(tag), _ptr(typ),
+                        int(step_next), 1 if use_cells else 0, _ptr(red))
+    if rc != 0:
+        raise RuntimeError("orc_step failed")
+    return x, v, f, red
+
+
+def forces_vjp(sys_, x, v, tag, typ, step: int, g, *, nbr=None, skin: float = 0.0, mode="brute"):
+    """(xbar, vbar, abar[nt,nt], gammabar[nt,nt]) for dL/dF = g."""
+    p = params(sys_, skin=skin)
+    x = _c(x, np.float64)
+    v = _c(v, np.float64)
+    g = _c(g, np.float64)
+    tag = _c(tag, np.uint32)
+    typ = _c(typ, np.uint8)
+    n = x.shape[1]
+    if nbr is None:
+        nbr = neighbors(x, sys_.box, p.r_list, mode=mode)
+    off, idx = _c(nbr[0], np.int64), _c(nbr[1], np.int32)
+    nt = int(sys_.n_types)
+    xb = np.empty((3, n)); vb = np.empty((3, n))
+    ab = np.empty(nt * nt); gb = np.empty(nt * nt)
+    lib().orc_forces_vjp(C.byref(p), n, _ptr(x), _ptr(v), _ptr(tag), _ptr(typ), _ptr(off),
+                         _ptr(idx), int(step), _ptr(g), _ptr(xb), _ptr(vb), _ptr(ab), _ptr(gb))
+    return xb, vb, ab.reshape(nt, nt), gb.reshape(nt, nt)
+
+
+def run(sys_, x, v, f, tag, typ, step0: int, n_steps: int, *, use_cells: bool = True,
+        profile=None, skin: float = 0.0):
+    """n_steps oracle steps; returns (x, v, f, red[n_steps, 8], prof_mean or None).
+
+    profile = (axis, component, nbins, from_step) averages that velocity
+    component in slabs along the axis over the steps >= from_step.
+    """
+    p = params(sys_, skin=skin)
+    x = np.array(x, dtype=np.float64, order="C", copy=True)
+    v = np.array(v, dtype=np.float64, order="C", copy=True)
+    f = np.array(f, dtype=np.float64, order="C", copy=True)
+    tag = _c(tag, np.uint32)
+    typ = _c(typ, np.uint8)
+    red = np.zeros((n_steps, 8), dtype=np.float64)
+    prof = cnt = None
+    pa = pc = nb = pf = 0
+    if profile is not None:
+        pa, pc, nb, pf = profile
+        prof = np.zeros(nb); cnt = np.zeros(nb)
+    rc = lib().orc_run(C.byref(p), x.shape[1], _ptr(x), _ptr(v), _ptr(f), _ptr(tag), _ptr(typ),
+                       int(step0), int(n_steps), 1 if use_cells else 0, _ptr(red),
+                       pa, pc, nb, pf, _ptr(prof), _ptr(cnt))
+    if rc != 0:
+        raise RuntimeError("orc_run failed")
+    prof_mean = None if prof is None else prof / np.maximum(cnt, 1.0)
+    return x, v, f, red, prof_mean
