@@ -1,0 +1,245 @@
+/*
+ * dpd.h -- C ABI of the MI355X (gfx950) DPD hot-path library (libdpd.so).
+ *
+ * The library implements one time step of dissipative particle dynamics as
+ * described by Tang & Karniadakis, "Accelerating Dissipative Particle
+ * Dynamics Simulations on GPUs" (arXiv 1311.0402): cell binning and particle
+ * reordering (Sec. 3.2), an ordered neighbour list (Sec. 3.3), the pairwise
+ * conservative + dissipative + random force (Sec. 2, Eqs (2)-(8)) with a
+ * pair Gaussian regenerated from particle tags, step and seed (Sec. 3.5),
+ * and the velocity-Verlet integration phases of Algorithm 1.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory    Every array argument is DEVICE memory owned by the caller; the
+ *           library never allocates or frees device memory.  Scratch space
+ *           is a caller-provided workspace sized by dpd_workspace_bytes().
+ *           Parameter blocks (dpd_params, dpd_state, ...) are HOST memory
+ *           and are read during the call only.
+ * Layout    Positions, velocities and forces are structure of arrays
+ *           double[3][n] (all x, then all y, then all z).  Tags are uint32
+ *           (a particle's identity, invariant under reordering), types
+ *           uint8 (< n_types <= DPD_MAX_TYPES).  Indices are int32 (n and
+ *           the neighbour count must stay below 2^31).
+ * Streams   Every enqueuing call takes a hipStream_t (as void*, NULL = the
+ *           default stream), is asynchronous, performs no host-device
+ *           synchronisation and no allocation, so it may be captured in a
+ *           HIP graph.
+ * Errors    Every call returns a dpd_status.  Argument errors are detected
+ *           before anything is enqueued (nothing is launched).  Conditions
+ *           that only the device can see (neighbour-list overflow,
+ *           non-finite totals, broken bond tables) are OR-ed as
+ *           DPD_STATUS_* bits into the caller's device int32 *d_status,
+ *           which the caller reads after synchronising.  dpd_last_error()
+ *           returns a thread-local message for the last failing call.
+ *           Nothing throws across this boundary and nothing aborts.
+ * Geometry  Periodic box [0, L_x) x [0, L_y) x [0, L_z).  The separation of
+ *           two particles is the minimum image of r_i - r_j, computed by
+ *           subtracting first and then shifting by one box length; the
+ *           squared distance is fma(dz, dz, fma(dy, dy, dx * dx)).  Cells
+ *           have n_c = floor(L / r_list) per side, reduced while the side
+ *           L / n_c is below r_list (1 + 2^-40); n_c must be in [3, 1023].
+ */
+#ifndef DPD_H
+#define DPD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DPD_MAX_TYPES 8
+
+typedef enum dpd_status {
+    DPD_OK = 0,
+    DPD_EINVAL = -1,        /* bad argument (null pointer, size, parameter) */
+    DPD_ECAPACITY = -2,     /* a caller buffer is too small                  */
+    DPD_EHIP = -3,          /* the HIP runtime reported an error             */
+    DPD_EUNSUPPORTED = -4   /* valid request this build does not implement   */
+} dpd_status;
+
+/* bits of the device status word */
+#define DPD_STATUS_NLIST_OVERFLOW 1   /* neighbour list exceeded its capacity   */
+#define DPD_STATUS_NONFINITE      2   /* a step produced non-finite totals      */
+#define DPD_STATUS_BAD_BOND       4   /* a bond partner tag has no particle     */
+
+typedef enum dpd_precision {
+    DPD_FP64 = 0,   /* pair arithmetic in FP64                                 */
+    DPD_MIXED = 1   /* pair arithmetic in FP32 on cell-relative coordinates,
+                       compensated FP32 sums, FP64 forces, state, integration
+                       and reductions                                          */
+} dpd_precision;
+
+/* Physical and numerical parameters (host memory). */
+typedef struct dpd_params {
+    double box[3];          /* periodic box lengths                             */
+    double r_c;             /* force cutoff, Eqs (3)-(6)                         */
+    double skin;            /* neighbour radius is r_c + skin (>= 0)            */
+    double dt;              /* time step; F^R scales as dt^-1/2 (Eq (5))        */
+    double lambda;          /* velocity-prediction factor of the integrator:
+                               F^D sees v + lambda dt F (0.5 = half-step v)     */
+    double s;               /* weight exponent, w_R = (1 - r/r_c)^s (Eq (8))    */
+    int32_t n_types;        /* 1 .. DPD_MAX_TYPES                               */
+    int32_t reserved0;
+    double a[DPD_MAX_TYPES * DPD_MAX_TYPES];      /* a_ij, row-major, symmetric  */
+    double gamma[DPD_MAX_TYPES * DPD_MAX_TYPES];  /* gamma_ij, symmetric         */
+    double sigma[DPD_MAX_TYPES * DPD_MAX_TYPES];  /* sigma_ij, symmetric (Eq (9)
+                                                     ties it to gamma; the ABI
+                                                     takes it as given)         */
+    uint64_t seed;          /* global seed of the pair Gaussian                  */
+    double body_g;          /* body force along x: +g where y < body_split,
+                               -g elsewhere (0 = none)                           */
+    double body_split;
+    double bond_k;          /* harmonic bonds F = -k (r - r0) e                  */
+    double bond_r0;
+    const int32_t* bond_partner;  /* DEVICE int32[2 n] indexed by tag: up to two
+                                     partner tags per particle, -1 = none; NULL
+                                     = no bonds.  Requires tags to be a
+                                     permutation of 0..n-1.                      */
+} dpd_params;
+
+/* One system's particle arrays (device pointers; host struct). */
+typedef struct dpd_state {
+    int32_t n;
+    int32_t reserved0;
+    double* x;              /* [3][n], each component in [0, L)                 */
+    double* v;              /* [3][n]                                            */
+    double* f;              /* [3][n]                                            */
+    uint32_t* tag;          /* [n]                                               */
+    uint8_t* type;          /* [n]                                               */
+} dpd_state;
+
+/* Cell list of a reordered state (device pointers; host struct). */
+typedef struct dpd_cells {
+    int32_t* cell_start;    /* [n_cells + 1]: first particle of every cell, cells
+                               in ascending Morton rank; last entry = n          */
+    uint32_t* cell_xyz;     /* [n]: cell of each sorted particle,
+                               cx | cy << 10 | cz << 20                          */
+    int32_t* perm;          /* [n]: sorted index -> input index                  */
+    int32_t* idx_of_tag;    /* [n]: tag -> sorted index (required with bonds,
+                               else nullable)                                    */
+} dpd_cells;
+
+/* Neighbour list in CSR form (device pointers; host struct). */
+typedef struct dpd_nlist {
+    int64_t capacity;       /* entries available in index[]                     */
+    int32_t* offset;        /* [n + 1]: row i is index[offset[i] .. offset[i+1]) */
+    int32_t* index;         /* [capacity]: neighbours, each row strictly ascending */
+} dpd_nlist;
+
+/* ---------------------------------------------------------------------------
+ * Queries (host only, nothing enqueued)
+ * ------------------------------------------------------------------------- */
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* dpd_last_error(void);
+
+/* Library version string. */
+const char* dpd_version(void);
+
+/* Cells per side for these parameters (rule in the header comment).
+ * Returns DPD_EINVAL when the box holds fewer than 3 or more than 1023 cells
+ * per side. */
+int dpd_cell_grid(const dpd_params* p, int32_t nc[3]);
+
+/* Bytes of workspace needed by any call below for n particles at this
+ * precision (0 on invalid arguments).  One workspace serves every entry
+ * point; it must be 256-byte aligned. */
+size_t dpd_workspace_bytes(const dpd_params* p, int32_t n, int32_t precision);
+
+/* ---------------------------------------------------------------------------
+ * Hot-path calls
+ * ------------------------------------------------------------------------- */
+
+/* Binning and reordering (Sec. 3.2.2 and 3.2.3).
+ * Each particle of `in` is assigned the cell c_k = min(n_c,k - 1,
+ * trunc(x_k * n_c,k / L_k)); cells are ranked along the Morton (Z) curve
+ * with bit b of c_x at 3b, c_y at 3b+1, c_z at 3b+2; particles are written to
+ * `out` in ascending (cell rank, tag) order.  in and out must not overlap.
+ * out->f is not touched.  cells receives cell_start, cell_xyz, perm and
+ * (if non-NULL) idx_of_tag.  When x32 / v32 are non-NULL they receive FP32
+ * copies for the mixed-precision force: x32 = (float)(x - c * L / n_c) (the
+ * offset inside the particle's cell) and v32 = (float)v, both [3][n]. */
+int dpd_bin_reorder(const dpd_params* p, const dpd_state* in, dpd_state* out,
+                    dpd_cells* cells, float* x32, float* v32,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* Ordered neighbour list (Sec. 3.3.2).
+ * For a state produced by dpd_bin_reorder: row i lists every j != i with
+ * |r_ij|^2 < (r_c + skin)^2 in strictly ascending j.  One 64-lane wavefront
+ * per cell scans the 27 surrounding cells in ascending rank; insertion
+ * points come from a wavefront ballot and a lane prefix count (no atomics,
+ * deterministic).  If the rows need more than nl->capacity entries,
+ * DPD_STATUS_NLIST_OVERFLOW is set in *d_status, offset[] still holds the
+ * required row sizes (offset[n] = the total needed) and index[] is not
+ * written. */
+int dpd_build_neighbors(const dpd_params* p, const dpd_state* sorted, const dpd_cells* cells,
+                        dpd_nlist* nl, int32_t* d_status,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/* Pairwise DPD forces (Sec. 2, Eqs (2)-(8)) plus bonds (Sec. 4.5) and the
+ * body force (Sec. 4.2), at time-step counter `step`.
+ * For every listed pair with |r_ij| < r_c:
+ *   F_ij = (a w_C - gamma w_D (e.v_ij) + sigma w_R xi_ij / sqrt(dt)) e_ij,
+ *   w_C = 1 - r/r_c, w_R = w_C^s, w_D = w_R^2, e_ij = r_ij / r, v_ij from
+ *   `v` (the predicted velocity), and
+ *   xi_ij = sqrt(-2 ln u1) cos(2 pi u2), (u1, u2) = ((w0 + 1/2) 2^-32,
+ *   w1 2^-32), (w0..w3) = Philox4x32-10(counter = (min tag, max tag,
+ *   step low word, step high word), key = (seed low word, seed high word)).
+ * f_out[i] = sum over i's row in list order, then bonds, then body force.
+ * DPD_MIXED evaluates the pair terms in FP32 from x32 / v32 / cells->cell_xyz
+ * (as written by dpd_bin_reorder) and sums them with compensated FP32;
+ * DPD_FP64 ignores x32 / v32.  pe_out (nullable, [n]) gets each particle's
+ * half of its pair and bond potential energies (1/2 a r_c w_C^2 per pair,
+ * 1/2 k (r - r0)^2 per bond).  stats (nullable, device double[2]) gets the
+ * total potential energy and the number of unique pairs inside r_c.
+ * d_status may be NULL when no bonds are present. */
+int dpd_forces(const dpd_params* p, int32_t precision, const dpd_state* sorted,
+               const dpd_cells* cells, const float* x32, const float* v32,
+               const dpd_nlist* nl, uint64_t step, double* f_out, double* pe_out,
+               double* stats, int32_t* d_status,
+               void* ws, size_t ws_bytes, void* stream);
+
+/* n_steps time steps of Algorithm 1 on one system, rebuilding the cell list
+ * and neighbour list every step:
+ *   v_h = v + dt/2 F;  x <- x + dt v_h, wrapped into [0, L);
+ *   v~  = v + lambda dt F (= v_h when lambda = 1/2);
+ *   reorder, rebuild the list, F <- F(x, v~, step + 1);
+ *   v   = v_h + dt/2 F;  step <- step + 1.
+ * On entry st->f must hold the forces of the current state (e.g. from
+ * dpd_forces at the current step).  *d_step (device uint64) is the step
+ * counter: read at every step and incremented on the device, so a captured
+ * graph can be replayed.  On exit st holds the reordered state and
+ * cells / nl describe it.  d_reductions (nullable, device double[n_steps][8])
+ * receives per step: P_x, P_y, P_z, sum |v|^2, potential energy, unique
+ * pairs, sum |v - v_mean|^2 / (3 (n - 1)) (k_B T), 0.
+ * phase_events (nullable): hipEvent_t[6 * n_steps], created by the caller;
+ * for step k, events 6k .. 6k+5 are recorded on `stream` before the first
+ * integration phase, after it, after reordering, after the neighbour list,
+ * after the forces and after the second phase and statistics, so the
+ * caller can time each phase of every step. */
+int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_steps,
+             uint64_t* d_step, double* d_reductions, dpd_cells* cells, dpd_nlist* nl,
+             float* x32, float* v32, int32_t* d_status, void* const* phase_events,
+             void* ws, size_t ws_bytes, void* stream);
+
+/* Vector-Jacobian product of the deterministic force map (xi and the pair
+ * set held fixed) for an upstream gradient g = dL/dF ([3][n]):
+ *   x_bar_i = sum_j (df_ij/dr_ij)^T (g_i - g_j)   (plus bond terms),
+ *   v_bar_i = sum_j (df_ij/dv_ij)^T (g_i - g_j),
+ *   a_bar[t][u] = dL/da_tu for the symmetric parameter (both entries equal),
+ *   gamma_bar[t][u] likewise,
+ * evaluated at the same (sorted state, list, step) as dpd_forces (FP64).
+ * a_bar / gamma_bar are device double[n_types * n_types]. */
+int dpd_forces_backward(const dpd_params* p, const dpd_state* sorted, const dpd_cells* cells,
+                        const dpd_nlist* nl, uint64_t step, const double* grad_f,
+                        double* grad_x, double* grad_v, double* grad_a, double* grad_gamma,
+                        void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPD_H */

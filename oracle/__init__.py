@@ -88,7 +88,7 @@ def _declare(L):
     L.orc_neighbors_brute.restype = C.c_int64
     L.orc_neighbors_cells.argtypes = [C.c_int32, P, P, C.c_double, P, P, C.c_int64]
     L.orc_neighbors_cells.restype = C.c_int64
-    L.orc_forces.argtypes = [P, C.c_int32, P, P, P, P, C.c_int32, P, P, P, C.c_uint64, P, P, P]
+    L.orc_forces.argtypes = [P, C.c_int32, P, P, P, P, C.c_int32, P, P, P, C.c_uint64, P, P, P, P]
     L.orc_forces.restype = C.c_int
     L.orc_step.argtypes = [P, C.c_int32, P, P, P, P, P, C.c_uint64, C.c_int, P]
     L.orc_step.restype = C.c_int
@@ -226,8 +226,9 @@ def neighbors(x, box, r_list: float, *, mode: str = "brute", query=None):
 # -------------------------------------------------------------- forces ----
 
 def forces(sys_, x, v, tag, typ, step: int, *, nbr=None, query=None, skin: float = 0.0,
-           mode: str = "brute"):
-    """Forces (float64[3, nq]), per-row PE halves and per-row pair counts."""
+           mode: str = "brute", with_scale: bool = False):
+    """Forces (float64[3, nq]), per-row PE halves and per-row pair counts
+    (plus, with_scale, the per-row sum of term magnitudes)."""
     p = params(sys_, skin=skin)
     x = _c(x, np.float64)
     v = _c(v, np.float64)
@@ -244,8 +245,11 @@ def forces(sys_, x, v, tag, typ, step: int, *, nbr=None, query=None, skin: float
     f = np.empty((3, nq), dtype=np.float64)
     pe = np.empty(nq, dtype=np.float64)
     npair = np.empty(nq, dtype=np.int32)
+    scale = np.empty(nq, dtype=np.float64) if with_scale else None
     lib().orc_forces(C.byref(p), n, _ptr(x), _ptr(v), _ptr(tag), _ptr(typ), nq, _ptr(q),
-                     _ptr(off), _ptr(idx), int(step), _ptr(f), _ptr(pe), _ptr(npair))
+                     _ptr(off), _ptr(idx), int(step), _ptr(f), _ptr(pe), _ptr(npair), _ptr(scale))
+    if with_scale:
+        return f, pe, npair, scale
     return f, pe, npair
 
 

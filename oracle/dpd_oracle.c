@@ -426,12 +426,14 @@ static void bond_force(const orc_params* p, const double d[3], double r2, double
  * within r_c, e.g. the r_list rows); pairs with r^2 >= r_c^2 contribute 0.
  * v is the velocity entering F^D (the predicted velocity of the integrator).
  * f: double[3][nq]; pe (nullable): per-row potential energy (pairs + bonds,
- * halves); npair (nullable): per-row count of pairs inside r_c.
+ * halves); npair (nullable): per-row count of pairs inside r_c; scale
+ * (nullable): per-row sum of the magnitudes of all added terms, the scale
+ * of the summation-order rounding error.
  * Sums run in ascending neighbour order, then bonds, then the body force. */
 int orc_forces(const orc_params* p, int32_t n, const double* x, const double* v,
                const uint32_t* tag, const uint8_t* type, int32_t nq, const int32_t* q,
                const int64_t* off, const int32_t* nb, uint64_t step,
-               double* f, double* pe, int32_t* npair)
+               double* f, double* pe, int32_t* npair, double* scale)
 {
     if (q == NULL) nq = n;
     const double rc2 = p->r_c * p->r_c;
@@ -440,7 +442,7 @@ int orc_forces(const orc_params* p, int32_t n, const double* x, const double* v,
     for (int32_t r = 0; r < nq; ++r) {
         int64_t i = q ? q[r] : r;
         double fi[3] = { 0.0, 0.0, 0.0 };
-        double pei = 0.0;
+        double pei = 0.0, sc = 0.0;
         int32_t np = 0;
         for (int64_t e = off[r]; e < off[r + 1]; ++e) {
             int64_t j = nb[e];
@@ -452,6 +454,7 @@ int orc_forces(const orc_params* p, int32_t n, const double* x, const double* v,
             double fij[3], peij;
             pair_force(p, d, r2, vij, type[i], type[j], tag[i], tag[j], step, fij, &peij);
             for (int k = 0; k < 3; ++k) fi[k] += fij[k];
+            sc += sqrt(fij[0] * fij[0] + fij[1] * fij[1] + fij[2] * fij[2]);
             pei += peij;
             ++np;
         }
@@ -465,13 +468,18 @@ int orc_forces(const orc_params* p, int32_t n, const double* x, const double* v,
                 double fb[3], peb;
                 bond_force(p, d, r2, fb, &peb);
                 for (int k = 0; k < 3; ++k) fi[k] += fb[k];
+                sc += sqrt(fb[0] * fb[0] + fb[1] * fb[1] + fb[2] * fb[2]);
                 pei += peb;
             }
         }
-        if (p->body_g != 0.0) fi[0] += (x[1 * n + i] < p->body_split) ? p->body_g : -p->body_g;
+        if (p->body_g != 0.0) {
+            fi[0] += (x[1 * n + i] < p->body_split) ? p->body_g : -p->body_g;
+            sc += fabs(p->body_g);
+        }
         for (int k = 0; k < 3; ++k) f[k * (int64_t)nq + r] = fi[k];
         if (pe) pe[r] = pei;
         if (npair) npair[r] = np;
+        if (scale) scale[r] = sc;
     }
     free(iot);
     return 0;
@@ -516,7 +524,7 @@ int orc_step(const orc_params* p, int32_t n, double* x, double* v, double* f,
     exclusive_scan(count, n, off);
     double* pe = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     int32_t* np = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-    orc_forces(p, n, x, vt, tag, type, 0, NULL, off, list, step_next, f, pe, np);
+    orc_forces(p, n, x, vt, tag, type, 0, NULL, off, list, step_next, f, pe, np, NULL);
     for (int k = 0; k < 3; ++k)
         for (int64_t i = 0; i < n; ++i) {
             int64_t a = k * (int64_t)n + i;

@@ -1,0 +1,15 @@
+"""MI355X (gfx950) DPD hot path: HIP kernels behind a C ABI (include/dpd.h).
+
+The package holds the HIP sources (``csrc/``), the build step (``build``),
+the ctypes declarations (``_abi``) and the torch binding (``dpd``).  Every
+numerical step runs in libdpd.so; importing the binding raises if the
+library was not built.
+"""
+from .dpd import (FP64, MIXED, Cells, NList, Params, State, System, alloc_workspace, cell_grid,
+                  default_capacity, dpd_bin_reorder, dpd_build_neighbors, dpd_forces,
+                  dpd_forces_backward, dpd_step, workspace_bytes)
+from ._abi import DPDError
+
+__all__ = ["FP64", "MIXED", "Cells", "NList", "Params", "State", "System", "alloc_workspace",
+           "cell_grid", "default_capacity", "dpd_bin_reorder", "dpd_build_neighbors", "dpd_forces",
+           "dpd_forces_backward", "dpd_step", "workspace_bytes", "DPDError"]

@@ -1,0 +1,128 @@
+"""ctypes declarations of the C ABI in include/dpd.h (libdpd.so).
+
+Loading fails loudly when the library has not been built: there is no CPU
+fallback for any entry point.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdpd.so")
+MAX_TYPES = 8
+
+DPD_OK = 0
+DPD_EINVAL = -1
+DPD_ECAPACITY = -2
+DPD_EHIP = -3
+DPD_EUNSUPPORTED = -4
+
+STATUS_NLIST_OVERFLOW = 1
+STATUS_NONFINITE = 2
+STATUS_BAD_BOND = 4
+
+FP64 = 0
+MIXED = 1
+
+
+class dpd_params(C.Structure):
+    _fields_ = [
+        ("box", C.c_double * 3),
+        ("r_c", C.c_double),
+        ("skin", C.c_double),
+        ("dt", C.c_double),
+        ("lam", C.c_double),
+        ("s", C.c_double),
+        ("n_types", C.c_int32),
+        ("reserved0", C.c_int32),
+        ("a", C.c_double * (MAX_TYPES * MAX_TYPES)),
+        ("gamma", C.c_double * (MAX_TYPES * MAX_TYPES)),
+        ("sigma", C.c_double * (MAX_TYPES * MAX_TYPES)),
+        ("seed", C.c_uint64),
+        ("body_g", C.c_double),
+        ("body_split", C.c_double),
+        ("bond_k", C.c_double),
+        ("bond_r0", C.c_double),
+        ("bond_partner", C.c_void_p),
+    ]
+
+
+class dpd_state(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32),
+        ("reserved0", C.c_int32),
+        ("x", C.c_void_p),
+        ("v", C.c_void_p),
+        ("f", C.c_void_p),
+        ("tag", C.c_void_p),
+        ("type", C.c_void_p),
+    ]
+
+
+class dpd_cells(C.Structure):
+    _fields_ = [
+        ("cell_start", C.c_void_p),
+        ("cell_xyz", C.c_void_p),
+        ("perm", C.c_void_p),
+        ("idx_of_tag", C.c_void_p),
+    ]
+
+
+class dpd_nlist(C.Structure):
+    _fields_ = [
+        ("capacity", C.c_int64),
+        ("offset", C.c_void_p),
+        ("index", C.c_void_p),
+    ]
+
+
+P = C.c_void_p
+PP = C.POINTER(dpd_params)
+PS = C.POINTER(dpd_state)
+PC = C.POINTER(dpd_cells)
+PN = C.POINTER(dpd_nlist)
+
+# name -> (restype, argtypes); the exported surface of include/dpd.h
+SIGNATURES = {
+    "dpd_last_error": (C.c_char_p, []),
+    "dpd_version": (C.c_char_p, []),
+    "dpd_cell_grid": (C.c_int, [PP, P]),
+    "dpd_workspace_bytes": (C.c_size_t, [PP, C.c_int32, C.c_int32]),
+    "dpd_bin_reorder": (C.c_int, [PP, PS, PS, PC, P, P, P, C.c_size_t, P]),
+    "dpd_build_neighbors": (C.c_int, [PP, PS, PC, PN, P, P, C.c_size_t, P]),
+    "dpd_forces": (C.c_int, [PP, C.c_int32, PS, PC, P, P, PN, C.c_uint64, P, P, P, P, P, C.c_size_t, P]),
+    "dpd_step": (C.c_int, [PP, C.c_int32, PS, C.c_int32, P, P, PC, PN, P, P, P, P, P, C.c_size_t, P]),
+    "dpd_forces_backward": (C.c_int, [PP, PS, PC, PN, C.c_uint64, P, P, P, P, P, P, C.c_size_t, P]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded libdpd (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -m paper_1311_0402_amd.build)")
+        # torch first, so libdpd binds to the HIP runtime torch already loaded
+        import torch  # noqa: F401
+        handle = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+class DPDError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = lib().dpd_last_error().decode(errors="replace")
+        super().__init__(f"{where} failed with status {code}: {msg}")
+        self.code = code
+
+
+def check(code: int, where: str) -> None:
+    if code != DPD_OK:
+        raise DPDError(code, where)

@@ -1,0 +1,195 @@
+// dpd_common.h -- types and device helpers shared by the DPD kernels.
+//
+// Everything here is written for gfx950 (wave64).  The few functions marked
+// DPD_HD are plain integer/FP arithmetic and also compile for the host, so
+// the host-side library code (and a CPU unit test) can use the exact same
+// cell-ranking rule as the kernels.
+#pragma once
+
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define DPD_HD __host__ __device__ __forceinline__
+#else
+#define DPD_HD inline
+#endif
+
+namespace dpd {
+
+constexpr int kMaxTypes = 8;
+constexpr int kWave = 64;
+
+// Kernel-side parameter block, passed by value.  Derived quantities are
+// computed once on the host (inverse cell sizes, sigma / sqrt(dt), ...).
+struct KParams {
+    double L[3];          // box
+    double halfL[3];      // L / 2 (exact)
+    double inv_cell[3];   // n_c / L  (cell coordinate = trunc(x * inv_cell))
+    double cell_len[3];   // L / n_c  (origin of a cell, mixed-precision offsets)
+    float cell_len32[3];
+    float L32[3];
+    int32_t nc[3];
+    int32_t nbits;        // bits of the largest cell coordinate
+    int32_t n_cells;
+    double rl2;           // (r_c + skin)^2, neighbour test  r^2 < rl2
+    double rc2;           // r_c^2, force test              r^2 < rc2
+    double r_c;
+    double inv_rc;
+    double dt;
+    double half_dt;
+    double lam_dt;        // lambda * dt
+    int32_t lam_half;     // lambda == 1/2: predicted velocity is the half-step one
+    int32_t wmode;        // w_R = w_C^s: 0 = sqrt, 1 = w_C, 2 = w_C^2, 3 = pow
+    double s;
+    int32_t n_types;
+    uint32_t seed_lo, seed_hi;
+    double body_g, body_split;
+    double bond_k, bond_r0;
+    const int32_t* partner;     // device, by tag; nullptr = no bonds
+    // per type pair: a, gamma, sigma / sqrt(dt)
+    double a[kMaxTypes * kMaxTypes];
+    double g[kMaxTypes * kMaxTypes];
+    double srdt[kMaxTypes * kMaxTypes];
+};
+
+// ---------------------------------------------------------------------------
+// Morton rank of a cell on an n_x x n_y x n_z grid, computed by counting:
+// rank(c) = number of grid cells whose Morton code (bit b of x at 3b, of y
+// at 3b+1, of z at 3b+2) is smaller than c's.  Walking the code from its most
+// significant bit, every 1-bit of c adds the number of grid cells that share
+// c's higher bits and have a 0 there; that number factorises into one count
+// per axis of the integers in [0, n) with a given high-bit prefix.
+// ---------------------------------------------------------------------------
+
+DPD_HD int64_t prefix_count(int64_t prefix, int shift, int64_t n)
+{
+    // integers v in [0, n) with (v >> shift) == prefix
+    int64_t lo = prefix << shift;
+    int64_t hi = (prefix + 1) << shift;
+    if (hi > n) hi = n;
+    return hi > lo ? hi - lo : 0;
+}
+
+DPD_HD int32_t morton_rank(int32_t cx, int32_t cy, int32_t cz,
+                           int32_t nx, int32_t ny, int32_t nz, int32_t nbits)
+{
+    int64_t rank = 0;
+    int64_t px = 0, py = 0, pz = 0;  // high bits fixed so far, per axis
+    for (int b = nbits - 1; b >= 0; --b) {
+        const int bz = (cz >> b) & 1;
+        if (bz) rank += prefix_count(2 * pz, b, nz) * prefix_count(py, b + 1, ny) * prefix_count(px, b + 1, nx);
+        pz = 2 * pz + bz;
+        const int by = (cy >> b) & 1;
+        if (by) rank += prefix_count(pz, b, nz) * prefix_count(2 * py, b, ny) * prefix_count(px, b + 1, nx);
+        py = 2 * py + by;
+        const int bx = (cx >> b) & 1;
+        if (bx) rank += prefix_count(pz, b, nz) * prefix_count(py, b, ny) * prefix_count(2 * px, b, nx);
+        px = 2 * px + bx;
+    }
+    return (int32_t)rank;
+}
+
+DPD_HD int32_t bits_for(int32_t nmax)
+{
+    int32_t b = 1;
+    while ((1 << b) < nmax) ++b;
+    return b;
+}
+
+DPD_HD uint32_t pack_cell(int32_t cx, int32_t cy, int32_t cz)
+{
+    return (uint32_t)cx | ((uint32_t)cy << 10) | ((uint32_t)cz << 20);
+}
+
+#if defined(__HIPCC__)
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// number of set bits of `mask` in lanes below this one
+__device__ __forceinline__ int lanes_below(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ int32_t cell_coord(double x, double inv_cell, int32_t n)
+{
+    int32_t c = (int32_t)(x * inv_cell);     // truncation; x >= 0 for a wrapped state
+    c = c < 0 ? 0 : c;
+    return c > n - 1 ? n - 1 : c;
+}
+
+__device__ __forceinline__ double min_image(double d, double L, double halfL)
+{
+    // subtract first, then shift by one box length (no pre-shifted copies)
+    if (d > halfL) d = d - L;
+    else if (d < -halfL) d = d + L;
+    return d;
+}
+
+__device__ __forceinline__ double dist2(double dx, double dy, double dz)
+{
+    return __fma_rn(dz, dz, __fma_rn(dy, dy, __dmul_rn(dx, dx)));
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplies and xors, key bumped by the Weyl constants.
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c.x;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+__device__ __forceinline__ U4 pair_words(uint32_t ti, uint32_t tj, uint64_t step,
+                                         uint32_t seed_lo, uint32_t seed_hi)
+{
+    const uint32_t a = ti < tj ? ti : tj;
+    const uint32_t b = ti < tj ? tj : ti;
+    return philox4x32_10(U4{a, b, (uint32_t)step, (uint32_t)(step >> 32)}, seed_lo, seed_hi);
+}
+
+// xi = sqrt(-2 ln u1) cos(2 pi u2), u1 = (w0 + 1/2) 2^-32, u2 = w1 2^-32 (FP64)
+__device__ __forceinline__ double gauss64(U4 w)
+{
+    const double u1 = ((double)w.x + 0.5) * 0x1p-32;
+    const double u2 = (double)w.y * 0x1p-32;
+    return sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
+}
+
+// Same variate in FP32.  For w0 >= 2^31, u1 is close to 1 and FP32 rounding
+// of u1 itself would dominate ln(u1); there ln(u1) = log1p(-t) with the
+// complement t = (2^32 - 1 - w0 + 1/2) 2^-32 formed in integers first, so t
+// keeps its full relative precision.
+__device__ __forceinline__ float gauss32(U4 w)
+{
+    float lnu;
+    if (w.x >= 0x80000000u) {
+        const float t = ((float)(0xFFFFFFFFu - w.x) + 0.5f) * 0x1p-32f;
+        lnu = log1pf(-t);
+    } else {
+        const float u1 = ((float)w.x + 0.5f) * 0x1p-32f;
+        lnu = __logf(u1);
+    }
+    const float u2 = (float)w.y * 0x1p-32f;
+    return sqrtf(-2.0f * lnu) * cospif(2.0f * u2);
+}
+
+#endif  // __HIPCC__
+
+}  // namespace dpd

@@ -1,0 +1,106 @@
+// dpd_launch.h -- host-side launchers of the DPD kernels (internal to libdpd).
+//
+// Each launcher enqueues its kernel(s) on `stream` and returns the launch
+// status; none of them synchronises or allocates.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "dpd_common.h"
+
+namespace dpd {
+
+constexpr int kBlock = 256;          // threads per block for element-wise kernels
+constexpr int kScanTile = 4096;      // items per block of the device-wide scan
+constexpr int kRedBlocks = 1024;     // fixed grid of the velocity reductions
+
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// ---- workspace layout (one workspace serves every entry point) ----
+struct WsLayout {
+    size_t bx, bv, bvt, btag, btype;   // post-drift, pre-reorder state (step)
+    size_t vt_sorted;                  // reordered predicted velocity (lambda != 1/2)
+    size_t key, slot, cxyz;            // binning: cell rank, slot in cell, cell coords
+    size_t tmp_tag, tmp_src;           // scatter before the in-cell tag order
+    size_t scan_part;                  // partial sums of the device-wide scan
+    size_t red_part;                   // velocity reduction partials
+    size_t fred_part;                  // force-kernel partials (PE, pairs)
+    size_t bwd_part;                   // adjoint partials (type-pair matrices)
+    size_t total;
+};
+
+WsLayout ws_layout(int32_t n, int32_t n_cells, bool need_vt, int32_t n_types);
+
+// ---- reorder (k_reorder.hip) ----
+hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t s);
+hipError_t launch_bin(const KParams& kp, int32_t n, const double* x, int32_t* key, int32_t* slot,
+                      uint32_t* cxyz, int32_t* counts, hipStream_t s);
+// in-place exclusive scan of data[0 .. count); partials needs ceil(count/kScanTile) ints
+hipError_t launch_scan(int32_t* data, int64_t count, int32_t* partials, hipStream_t s);
+hipError_t launch_place(int32_t n, const int32_t* key, const int32_t* slot, const int32_t* cell_start,
+                        const uint32_t* tag, uint32_t* tmp_tag, int32_t* tmp_src, hipStream_t s);
+struct GatherArgs {
+    const double* x_in; const double* v_in; const double* vt_in; const uint8_t* type_in;
+    const uint32_t* cxyz_in;
+    double* x_out; double* v_out; double* vt_out; uint32_t* tag_out; uint8_t* type_out;
+    uint32_t* cell_xyz; int32_t* perm; int32_t* idx_of_tag;
+    float* x32; float* v32;
+};
+hipError_t launch_finalize(const KParams& kp, int32_t n, const int32_t* key, const int32_t* cell_start,
+                           const uint32_t* tmp_tag, const int32_t* tmp_src, const GatherArgs& g,
+                           hipStream_t s);
+
+// ---- neighbour list (k_nlist.hip) ----
+hipError_t launch_nlist_count(const KParams& kp, int32_t n, const double* x, const int32_t* cell_start,
+                              const uint32_t* cell_xyz, int32_t* offset, hipStream_t s);
+hipError_t launch_nlist_check(int32_t n, const int32_t* offset, int64_t capacity, int32_t* status,
+                              hipStream_t s);
+hipError_t launch_nlist_fill(const KParams& kp, int32_t n, const double* x, const int32_t* cell_start,
+                             const uint32_t* cell_xyz, const int32_t* offset, int32_t* index,
+                             int64_t capacity, hipStream_t s);
+
+// ---- forces (k_force.hip) ----
+struct ForceArgs {
+    int32_t n;
+    const double* x; const double* v; const uint32_t* tag; const uint8_t* type;
+    const uint32_t* cell_xyz; const float* x32; const float* v32;
+    const int32_t* offset; const int32_t* index; int64_t capacity;
+    const int32_t* idx_of_tag;
+    const uint64_t* d_step; uint64_t step_add;   // step = (d_step ? *d_step : 0) + step_add
+    double* f; double* pe;                        // pe nullable
+    double* fred_part;                            // [blocks][2]: PE, pair count
+    int32_t* status;                              // nullable
+};
+hipError_t launch_forces(const KParams& kp, int precision, const ForceArgs& a, hipStream_t s);
+int force_blocks(int32_t n);
+
+// ---- integration and reductions (k_integrate.hip) ----
+hipError_t launch_vv1(const KParams& kp, int32_t n, const double* x, const double* v, const double* f,
+                      const uint32_t* tag, const uint8_t* type, double* bx, double* bv, double* bvt,
+                      uint32_t* btag, uint8_t* btype, hipStream_t s);
+hipError_t launch_vv2(const KParams& kp, int32_t n, double* v, const double* f, double* red_part,
+                      hipStream_t s);
+// sums the partials in a fixed order; red (nullable) gets the 8 step totals;
+// stats (nullable) gets (PE, pairs); increments *d_step when non-null
+hipError_t launch_reduce_final(int32_t n, const double* red_part, int n_red, const double* fred_part,
+                               int n_fred, double* red, double* stats, uint64_t* d_step,
+                               int32_t* status, hipStream_t s);
+
+// ---- adjoint (k_adjoint.hip) ----
+struct BackwardArgs {
+    int32_t n;
+    const double* x; const double* v; const uint32_t* tag; const uint8_t* type;
+    const int32_t* offset; const int32_t* index; int64_t capacity;
+    const int32_t* idx_of_tag;
+    uint64_t step;
+    const double* g;
+    double* xbar; double* vbar;
+    double* part;          // [blocks][2 * n_types^2]
+    double* abar; double* gbar;
+};
+hipError_t launch_forces_backward(const KParams& kp, const BackwardArgs& a, hipStream_t s);
+int backward_part_doubles(int32_t n, int32_t n_types);
+
+}  // namespace dpd

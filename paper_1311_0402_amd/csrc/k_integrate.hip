@@ -1,0 +1,149 @@
+// k_integrate.hip -- velocity-Verlet phases (Eq (1) and Algorithm 1 of the
+// paper, in the Groot-Warren form with velocity prediction lambda) and the
+// per-step statistics ("calculate statistics" of Algorithm 1), all FP64.
+//
+// Phase 1 (k_vv1):  v_h = fma(dt/2, F, v);  x' = fma(dt, v_h, x) wrapped
+//                   into [0, L) (add L if negative, then subtract L if >= L);
+//                   v~ = fma(lambda dt, F, v) unless lambda = 1/2 (v~ = v_h).
+// Phase 2 (k_vv2):  v = fma(dt/2, F_new, v_h), plus per-block partial sums
+//                   of momentum and |v|^2 over a fixed grid.
+// k_reduce_final adds all partials in one fixed order (deterministic) and
+// advances the device step counter.
+#include "dpd_launch.h"
+
+namespace dpd {
+
+namespace {
+
+__global__ __launch_bounds__(kBlock) void k_vv1(KParams kp, int32_t n, const double* __restrict__ x,
+                                                const double* __restrict__ v, const double* __restrict__ f,
+                                                const uint32_t* __restrict__ tag,
+                                                const uint8_t* __restrict__ type, double* __restrict__ bx,
+                                                double* __restrict__ bv, double* __restrict__ bvt,
+                                                uint32_t* __restrict__ btag, uint8_t* __restrict__ btype)
+{
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    const int k = blockIdx.y;                       // component
+    if (i >= n) return;
+    const int64_t a = (int64_t)k * n + i;
+    const double L = kp.L[k];
+    const double vh = __fma_rn(kp.half_dt, f[a], v[a]);
+    double xn = __fma_rn(kp.dt, vh, x[a]);
+    if (xn < 0.0) xn = xn + L;
+    if (xn >= L) xn = xn - L;
+    bx[a] = xn;
+    bv[a] = vh;
+    if (bvt) bvt[a] = __fma_rn(kp.lam_dt, f[a], v[a]);
+    if (k == 0) {
+        btag[i] = tag[i];
+        btype[i] = type[i];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_vv2(KParams kp, int32_t n, double* __restrict__ v,
+                                                const double* __restrict__ f, double* __restrict__ part)
+{
+    __shared__ double s_p[kBlock / kWave], s_q[kBlock / kWave];
+    const int k = blockIdx.y;
+    const int64_t base = (int64_t)k * n;
+    double p = 0.0, q = 0.0;
+    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += kRedBlocks * kBlock) {
+        const double vn = __fma_rn(kp.half_dt, f[base + i], v[base + i]);
+        v[base + i] = vn;
+        p += vn;
+        q += vn * vn;
+    }
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        p += __shfl_down(p, d, kWave);
+        q += __shfl_down(q, d, kWave);
+    }
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (lane == 0) { s_p[w] = p; s_q[w] = q; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tp = 0.0, tq = 0.0;
+        for (int m = 0; m < kBlock / kWave; ++m) { tp += s_p[m]; tq += s_q[m]; }
+        part[2 * ((int64_t)k * kRedBlocks + blockIdx.x)] = tp;
+        part[2 * ((int64_t)k * kRedBlocks + blockIdx.x) + 1] = tq;
+    }
+}
+
+// fixed-order block sum: thread t adds entries t, t + 256, ... of a strided
+// array, then a fixed tree over the block
+__device__ double block_sum_strided(const double* __restrict__ src, int count, int stride, int offset)
+{
+    __shared__ double s[kBlock];
+    double acc = 0.0;
+    for (int m = threadIdx.x; m < count; m += kBlock) acc += src[(int64_t)m * stride + offset];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double r = s[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_final(int32_t n, const double* __restrict__ red_part,
+                                                         int n_red, const double* __restrict__ fred_part,
+                                                         int n_fred, double* __restrict__ red,
+                                                         double* __restrict__ stats, uint64_t* d_step,
+                                                         int32_t* status)
+{
+    double P[3] = {0.0, 0.0, 0.0}, v2 = 0.0, pe = 0.0, pairs = 0.0;
+    if (red_part) {
+        for (int k = 0; k < 3; ++k) {
+            P[k] = block_sum_strided(red_part + 2 * (int64_t)k * kRedBlocks, n_red, 2, 0);
+            v2 += block_sum_strided(red_part + 2 * (int64_t)k * kRedBlocks, n_red, 2, 1);
+        }
+    }
+    if (fred_part) {
+        pe = block_sum_strided(fred_part, n_fred, 2, 0);
+        pairs = block_sum_strided(fred_part, n_fred, 2, 1);
+    }
+    if (threadIdx.x == 0) {
+        const double nn = (double)n;
+        const double kbt = n > 1 ? (v2 - (P[0] * P[0] + P[1] * P[1] + P[2] * P[2]) / nn) / (3.0 * (nn - 1.0)) : 0.0;
+        if (red) {
+            red[0] = P[0]; red[1] = P[1]; red[2] = P[2];
+            red[3] = v2; red[4] = pe; red[5] = pairs; red[6] = kbt; red[7] = 0.0;
+        }
+        if (stats) { stats[0] = pe; stats[1] = pairs; }
+        const double chk = P[0] + P[1] + P[2] + v2 + pe;
+        if (status && !(chk - chk == 0.0)) atomicOr(status, 2 /* DPD_STATUS_NONFINITE */);
+        if (d_step) *d_step = *d_step + 1ull;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_vv1(const KParams& kp, int32_t n, const double* x, const double* v, const double* f,
+                      const uint32_t* tag, const uint8_t* type, double* bx, double* bv, double* bvt,
+                      uint32_t* btag, uint8_t* btype, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_vv1, dim3(ceil_div(n, kBlock), 3), dim3(kBlock), 0, s, kp, n, x, v, f, tag, type,
+                       bx, bv, bvt, btag, btype);
+    return hipGetLastError();
+}
+
+hipError_t launch_vv2(const KParams& kp, int32_t n, double* v, const double* f, double* red_part,
+                      hipStream_t s)
+{
+    hipLaunchKernelGGL(k_vv2, dim3(kRedBlocks, 3), dim3(kBlock), 0, s, kp, n, v, f, red_part);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_final(int32_t n, const double* red_part, int n_red, const double* fred_part,
+                               int n_fred, double* red, double* stats, uint64_t* d_step, int32_t* status,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, s, n, red_part, n_red, fred_part, n_fred,
+                       red, stats, d_step, status);
+    return hipGetLastError();
+}
+
+}  // namespace dpd

@@ -1,0 +1,245 @@
+// k_reorder.hip -- cell binning, device-wide scan and particle reordering
+// (Sec. 3.2.2 / 3.2.3 of the paper: particles of one cell get consecutive
+// indices, cells follow a Morton curve; here the order inside a cell is by
+// tag, which makes the permutation a deterministic total order).
+//
+// Pipeline: k_bin (cell rank + slot by atomic count) -> exclusive scan of
+// the counts (= cell_start) -> k_place (scatter to count slots) ->
+// k_finalize (rank by tag inside the cell, gather all particle arrays).
+// The atomics only decide provisional slots; the final position depends on
+// (cell rank, tag) alone.
+#include "dpd_launch.h"
+
+namespace dpd {
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t count, int32_t value)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = value;
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3(ceil_div(count, kBlock)), dim3(kBlock), 0, s, p, count, value);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_bin(KParams kp, int32_t n, const double* __restrict__ x,
+                                                int32_t* __restrict__ key, int32_t* __restrict__ slot,
+                                                uint32_t* __restrict__ cxyz, int32_t* __restrict__ counts)
+{
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int32_t cx = cell_coord(x[i], kp.inv_cell[0], kp.nc[0]);
+    const int32_t cy = cell_coord(x[(int64_t)n + i], kp.inv_cell[1], kp.nc[1]);
+    const int32_t cz = cell_coord(x[2 * (int64_t)n + i], kp.inv_cell[2], kp.nc[2]);
+    const int32_t r = morton_rank(cx, cy, cz, kp.nc[0], kp.nc[1], kp.nc[2], kp.nbits);
+    key[i] = r;
+    cxyz[i] = pack_cell(cx, cy, cz);
+    slot[i] = atomicAdd(&counts[r], 1);
+}
+
+hipError_t launch_bin(const KParams& kp, int32_t n, const double* x, int32_t* key, int32_t* slot,
+                      uint32_t* cxyz, int32_t* counts, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bin, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, kp, n, x, key, slot, cxyz, counts);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Device-wide exclusive scan (three passes: tile sums, scan of the tile
+// sums, tile-local scan plus tile offset).  Tiles of kScanTile items, 256
+// threads x 16 items, wave64 shuffles inside a wave.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int32_t wave_incl_scan(int32_t v)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int32_t t = __shfl_up(v, d, kWave);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// exclusive scan of one value per thread over the block; *total = block sum
+__device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t* s_wave, int32_t* total)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+    const int32_t incl = wave_incl_scan(v);
+    if (lane == kWave - 1) s_wave[w] = incl;
+    __syncthreads();
+    int32_t off = 0, tot = 0;
+    for (int k = 0; k < nw; ++k) {
+        const int32_t t = s_wave[k];
+        off += (k < w) ? t : 0;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + incl - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(const int32_t* __restrict__ data, int64_t count,
+                                                       int32_t* __restrict__ partials)
+{
+    __shared__ int32_t s_wave[kBlock / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int32_t sum = 0;
+    for (int k = threadIdx.x; k < kScanTile; k += kBlock) {
+        const int64_t i = base + k;
+        if (i < count) sum += data[i];
+    }
+    int32_t tot;
+    block_excl_scan(sum, s_wave, &tot);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_partials(int32_t* __restrict__ partials, int32_t n_tiles)
+{
+    __shared__ int32_t s_wave[1024 / kWave];
+    int32_t carry = 0;
+    for (int32_t base = 0; base < n_tiles; base += 1024) {
+        const int32_t i = base + threadIdx.x;
+        const int32_t v = i < n_tiles ? partials[i] : 0;
+        int32_t tot;
+        const int32_t ex = block_excl_scan(v, s_wave, &tot);
+        if (i < n_tiles) partials[i] = carry + ex;
+        carry += tot;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_apply(int32_t* __restrict__ data, int64_t count,
+                                                       const int32_t* __restrict__ partials)
+{
+    constexpr int kItems = kScanTile / kBlock;   // 16
+    // +1 padding per 16 items so the per-thread runs do not share banks
+    __shared__ int32_t s_tile[kScanTile + kScanTile / kItems];
+    __shared__ int32_t s_wave[kBlock / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    for (int k = threadIdx.x; k < kScanTile; k += kBlock) {
+        const int64_t i = base + k;
+        s_tile[k + k / kItems] = i < count ? data[i] : 0;
+    }
+    __syncthreads();
+    const int t0 = threadIdx.x * kItems;
+    int32_t run = 0;
+#pragma unroll
+    for (int q = 0; q < kItems; ++q) run += s_tile[t0 + q + (t0 + q) / kItems];
+    int32_t tot;
+    int32_t ex = block_excl_scan(run, s_wave, &tot) + partials[blockIdx.x];
+#pragma unroll
+    for (int q = 0; q < kItems; ++q) {
+        const int a = t0 + q + (t0 + q) / kItems;
+        const int32_t v = s_tile[a];
+        s_tile[a] = ex;
+        ex += v;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kScanTile; k += kBlock) {
+        const int64_t i = base + k;
+        if (i < count) data[i] = s_tile[k + k / kItems];
+    }
+}
+
+hipError_t launch_scan(int32_t* data, int64_t count, int32_t* partials, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    const int tiles = ceil_div(count, kScanTile);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(kBlock), 0, s, data, count, partials);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials, tiles);
+    hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(kBlock), 0, s, data, count, partials);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Scatter into provisional slots, then the final (cell rank, tag) order.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_place(int32_t n, const int32_t* __restrict__ key,
+                                                  const int32_t* __restrict__ slot,
+                                                  const int32_t* __restrict__ cell_start,
+                                                  const uint32_t* __restrict__ tag,
+                                                  uint32_t* __restrict__ tmp_tag, int32_t* __restrict__ tmp_src)
+{
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int32_t pos = cell_start[key[i]] + slot[i];
+    tmp_tag[pos] = tag[i];
+    tmp_src[pos] = i;
+}
+
+hipError_t launch_place(int32_t n, const int32_t* key, const int32_t* slot, const int32_t* cell_start,
+                        const uint32_t* tag, uint32_t* tmp_tag, int32_t* tmp_src, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_place, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, n, key, slot, cell_start,
+                       tag, tmp_tag, tmp_src);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_finalize(KParams kp, int32_t n, const int32_t* __restrict__ key,
+                                                     const int32_t* __restrict__ cell_start,
+                                                     const uint32_t* __restrict__ tmp_tag,
+                                                     const int32_t* __restrict__ tmp_src, GatherArgs g)
+{
+    const int32_t p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= n) return;
+    const int32_t src = tmp_src[p];
+    const int32_t c = key[src];
+    const int32_t lo = cell_start[c], hi = cell_start[c + 1];
+    const uint32_t t = tmp_tag[p];
+    int32_t below = 0;
+    for (int32_t q = lo; q < hi; ++q) below += (tmp_tag[q] < t) ? 1 : 0;
+    const int32_t dst = lo + below;
+    const int64_t N = n;
+    g.perm[dst] = src;
+    g.tag_out[dst] = t;
+    g.type_out[dst] = g.type_in[src];
+    const uint32_t packed = g.cxyz_in[src];
+    g.cell_xyz[dst] = packed;
+    if (g.idx_of_tag && t < (uint32_t)n) g.idx_of_tag[t] = dst;
+    double xs[3], vs[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        xs[k] = g.x_in[k * N + src];
+        vs[k] = g.v_in[k * N + src];
+        g.x_out[k * N + dst] = xs[k];
+        g.v_out[k * N + dst] = vs[k];
+    }
+    if (g.vt_in) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            vs[k] = g.vt_in[k * N + src];
+            g.vt_out[k * N + dst] = vs[k];
+        }
+    }
+    if (g.x32) {
+        const int32_t cc[3] = {(int32_t)(packed & 1023u), (int32_t)((packed >> 10) & 1023u),
+                               (int32_t)(packed >> 20)};
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            g.x32[k * N + dst] = (float)(xs[k] - (double)cc[k] * kp.cell_len[k]);
+    }
+    if (g.v32) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) g.v32[k * N + dst] = (float)vs[k];
+    }
+}
+
+hipError_t launch_finalize(const KParams& kp, int32_t n, const int32_t* key, const int32_t* cell_start,
+                           const uint32_t* tmp_tag, const int32_t* tmp_src, const GatherArgs& g,
+                           hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finalize, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, kp, n, key, cell_start,
+                       tmp_tag, tmp_src, g);
+    return hipGetLastError();
+}
+
+}  // namespace dpd

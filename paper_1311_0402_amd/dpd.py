@@ -1,0 +1,362 @@
+"""Python binding of libdpd with torch tensors as device memory.
+
+The functions named like the C entry points (``dpd_bin_reorder``,
+``dpd_build_neighbors``, ``dpd_forces``, ``dpd_step``,
+``dpd_forces_backward``) only marshal arguments: every step of the method
+runs in the HIP kernels behind include/dpd.h.  ``System`` owns the device
+buffers one simulation needs and strings the calls together.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import DPDError, check, lib
+
+FP64 = _abi.FP64
+MIXED = _abi.MIXED
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("libdpd takes device tensors only")
+    if not t.is_contiguous():
+        raise ValueError("libdpd takes contiguous tensors only")
+    return t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+@dataclass
+class Params:
+    """Physical and numerical parameters (mirrors dpd_params)."""
+
+    box: tuple
+    r_c: float = 1.0
+    skin: float = 0.0
+    dt: float = 0.01
+    lam: float = 0.5
+    s: float = 0.5
+    n_types: int = 1
+    a: np.ndarray = field(default_factory=lambda: np.array([[25.0]]))
+    gamma: np.ndarray = field(default_factory=lambda: np.array([[4.5]]))
+    sigma: np.ndarray = field(default_factory=lambda: np.array([[3.0]]))
+    seed: int = 0
+    body_g: float = 0.0
+    body_split: float = 0.0
+    bond_k: float = 0.0
+    bond_r0: float = 0.0
+    partner: Optional[torch.Tensor] = None      # device int32 [n, 2] by tag
+
+    @classmethod
+    def like(cls, obj, device="cuda", skin: float = 0.0) -> "Params":
+        """Parameters copied from any object with the same attribute names."""
+        partner = getattr(obj, "partner", None)
+        if partner is not None and not isinstance(partner, torch.Tensor):
+            partner = torch.as_tensor(np.ascontiguousarray(partner, dtype=np.int32), device=device)
+        return cls(box=tuple(float(b) for b in obj.box), r_c=float(obj.r_c), skin=skin,
+                   dt=float(obj.dt), lam=float(obj.lam), s=float(obj.s), n_types=int(obj.n_types),
+                   a=np.asarray(obj.a, dtype=np.float64), gamma=np.asarray(obj.gamma, dtype=np.float64),
+                   sigma=np.asarray(obj.sigma, dtype=np.float64), seed=int(obj.seed),
+                   body_g=float(obj.body_g), body_split=float(obj.body_split),
+                   bond_k=float(obj.bond_k), bond_r0=float(obj.bond_r0), partner=partner)
+
+    def c(self) -> _abi.dpd_params:
+        p = _abi.dpd_params()
+        for k in range(3):
+            p.box[k] = float(self.box[k])
+        p.r_c, p.skin, p.dt, p.lam, p.s = self.r_c, self.skin, self.dt, self.lam, self.s
+        nt = int(self.n_types)
+        p.n_types = nt
+        for name in ("a", "gamma", "sigma"):
+            if not 1 <= nt <= _abi.MAX_TYPES:
+                break                     # the library rejects n_types itself
+            tab = np.asarray(getattr(self, name), dtype=np.float64).reshape(-1)
+            if tab.size != nt * nt:
+                raise ValueError(f"{name} must have n_types^2 entries")
+            arr = getattr(p, name)
+            for t in range(nt * nt):
+                arr[t] = float(tab[t])
+        p.seed = int(self.seed) & ((1 << 64) - 1)
+        p.body_g, p.body_split = self.body_g, self.body_split
+        p.bond_k, p.bond_r0 = self.bond_k, self.bond_r0
+        p.bond_partner = _ptr(self.partner) if self.partner is not None else None
+        return p
+
+    @property
+    def r_list(self) -> float:
+        return self.r_c + self.skin
+
+
+@dataclass
+class State:
+    x: torch.Tensor        # float64 [3, n]
+    v: torch.Tensor        # float64 [3, n]
+    f: torch.Tensor        # float64 [3, n]
+    tag: torch.Tensor      # int32 [n] (read as uint32)
+    type: torch.Tensor     # uint8 [n]
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[1])
+
+    @classmethod
+    def empty(cls, n: int, device="cuda") -> "State":
+        return cls(x=torch.empty((3, n), dtype=torch.float64, device=device),
+                   v=torch.empty((3, n), dtype=torch.float64, device=device),
+                   f=torch.zeros((3, n), dtype=torch.float64, device=device),
+                   tag=torch.empty(n, dtype=torch.int32, device=device),
+                   type=torch.empty(n, dtype=torch.uint8, device=device))
+
+    def c(self) -> _abi.dpd_state:
+        s = _abi.dpd_state()
+        s.n = self.n
+        s.x, s.v, s.f = _ptr(self.x), _ptr(self.v), _ptr(self.f)
+        s.tag, s.type = _ptr(self.tag), _ptr(self.type)
+        return s
+
+
+@dataclass
+class Cells:
+    cell_start: torch.Tensor   # int32 [n_cells + 1]
+    cell_xyz: torch.Tensor     # int32 [n] (packed cx | cy<<10 | cz<<20)
+    perm: torch.Tensor         # int32 [n]
+    idx_of_tag: torch.Tensor   # int32 [n]
+
+    @classmethod
+    def empty(cls, n: int, n_cells: int, device="cuda") -> "Cells":
+        i32 = dict(dtype=torch.int32, device=device)
+        return cls(torch.empty(n_cells + 1, **i32), torch.empty(max(n, 1), **i32),
+                   torch.empty(max(n, 1), **i32), torch.full((max(n, 1),), -1, **i32))
+
+    def c(self) -> _abi.dpd_cells:
+        c = _abi.dpd_cells()
+        c.cell_start, c.cell_xyz = _ptr(self.cell_start), _ptr(self.cell_xyz)
+        c.perm, c.idx_of_tag = _ptr(self.perm), _ptr(self.idx_of_tag)
+        return c
+
+
+@dataclass
+class NList:
+    offset: torch.Tensor       # int32 [n + 1]
+    index: torch.Tensor        # int32 [capacity]
+
+    @property
+    def capacity(self) -> int:
+        return int(self.index.numel())
+
+    @classmethod
+    def empty(cls, n: int, capacity: int, device="cuda") -> "NList":
+        return cls(torch.zeros(n + 1, dtype=torch.int32, device=device),
+                   torch.empty(max(int(capacity), 1), dtype=torch.int32, device=device))
+
+    def c(self) -> _abi.dpd_nlist:
+        c = _abi.dpd_nlist()
+        c.capacity = self.capacity
+        c.offset, c.index = _ptr(self.offset), _ptr(self.index)
+        return c
+
+
+# ----------------------------------------------------------------- queries --
+
+def cell_grid(params: Params):
+    nc = (C.c_int32 * 3)()
+    check(lib().dpd_cell_grid(C.byref(params.c()), nc), "dpd_cell_grid")
+    return tuple(int(v) for v in nc)
+
+
+def workspace_bytes(params: Params, n: int, precision: int = FP64) -> int:
+    nb = lib().dpd_workspace_bytes(C.byref(params.c()), int(n), int(precision))
+    if nb == 0:
+        raise DPDError(_abi.DPD_EINVAL, "dpd_workspace_bytes")
+    return int(nb)
+
+
+def alloc_workspace(params: Params, n: int, precision: int = FP64, device="cuda") -> torch.Tensor:
+    nb = workspace_bytes(params, n, precision)
+    # torch's caching allocator hands out 512-byte aligned blocks
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def default_capacity(params: Params, n: int, slack: float = 1.5) -> int:
+    vol = float(np.prod(params.box))
+    mean = 4.0 / 3.0 * math.pi * (n / vol) * params.r_list ** 3
+    return int(slack * n * mean) + 4096
+
+
+# -------------------------------------------------- entry points (marshal) --
+
+def dpd_bin_reorder(params: Params, src: State, dst: State, cells: Cells, ws: torch.Tensor,
+                    x32=None, v32=None, stream=None) -> None:
+    s_in, s_out, c = src.c(), dst.c(), cells.c()
+    check(lib().dpd_bin_reorder(C.byref(params.c()), C.byref(s_in), C.byref(s_out), C.byref(c),
+                                _ptr(x32), _ptr(v32), _ptr(ws), ws.numel(), _stream(stream)),
+          "dpd_bin_reorder")
+
+
+def dpd_build_neighbors(params: Params, st: State, cells: Cells, nl: NList, status: torch.Tensor,
+                        ws: torch.Tensor, stream=None) -> None:
+    s, c, n = st.c(), cells.c(), nl.c()
+    check(lib().dpd_build_neighbors(C.byref(params.c()), C.byref(s), C.byref(c), C.byref(n),
+                                    _ptr(status), _ptr(ws), ws.numel(), _stream(stream)),
+          "dpd_build_neighbors")
+
+
+def dpd_forces(params: Params, precision: int, st: State, cells: Optional[Cells], nl: NList, step: int,
+               f_out: torch.Tensor, ws: torch.Tensor, *, x32=None, v32=None, pe_out=None, stats=None,
+               status=None, stream=None) -> None:
+    s, n = st.c(), nl.c()
+    c = cells.c() if cells is not None else None
+    check(lib().dpd_forces(C.byref(params.c()), int(precision), C.byref(s),
+                           C.byref(c) if c is not None else None, _ptr(x32), _ptr(v32), C.byref(n),
+                           int(step), _ptr(f_out), _ptr(pe_out), _ptr(stats), _ptr(status),
+                           _ptr(ws), ws.numel(), _stream(stream)),
+          "dpd_forces")
+
+
+def dpd_step(params: Params, precision: int, st: State, n_steps: int, d_step: torch.Tensor,
+             cells: Cells, nl: NList, status: torch.Tensor, ws: torch.Tensor, *, reductions=None,
+             x32=None, v32=None, phase_events=None, stream=None) -> None:
+    """phase_events: optional list of 6 * n_steps recorded torch.cuda.Events."""
+    s, c, n = st.c(), cells.c(), nl.c()
+    ev = None
+    if phase_events is not None:
+        if len(phase_events) != 6 * n_steps:
+            raise ValueError("phase_events needs 6 events per step")
+        handles = [e.cuda_event for e in phase_events]
+        if not all(handles):
+            raise ValueError("record every event once before passing it (torch creates them lazily)")
+        ev = (C.c_void_p * len(handles))(*handles)
+    check(lib().dpd_step(C.byref(params.c()), int(precision), C.byref(s), int(n_steps), _ptr(d_step),
+                         _ptr(reductions), C.byref(c), C.byref(n), _ptr(x32), _ptr(v32), _ptr(status),
+                         ev, _ptr(ws), ws.numel(), _stream(stream)),
+          "dpd_step")
+
+
+def dpd_forces_backward(params: Params, st: State, cells: Optional[Cells], nl: NList, step: int,
+                        grad_f: torch.Tensor, grad_x: torch.Tensor, grad_v: torch.Tensor,
+                        grad_a: torch.Tensor, grad_gamma: torch.Tensor, ws: torch.Tensor,
+                        stream=None) -> None:
+    s, n = st.c(), nl.c()
+    c = cells.c() if cells is not None else None
+    check(lib().dpd_forces_backward(C.byref(params.c()), C.byref(s), C.byref(c) if c is not None else None,
+                                    C.byref(n), int(step), _ptr(grad_f), _ptr(grad_x), _ptr(grad_v),
+                                    _ptr(grad_a), _ptr(grad_gamma), _ptr(ws), ws.numel(), _stream(stream)),
+          "dpd_forces_backward")
+
+
+# ------------------------------------------------------------------ System --
+
+class System:
+    """Device buffers of one DPD system plus the per-step driver.
+
+    After ``load`` the state is reordered, its neighbour list built and the
+    forces of the current step computed, so ``step`` can run immediately.
+    """
+
+    def __init__(self, params: Params, n: int, precision: int = FP64, capacity: Optional[int] = None,
+                 device="cuda"):
+        self.params = params
+        self.n = int(n)
+        self.precision = int(precision)
+        self.device = device
+        self.nc = cell_grid(params)
+        n_cells = self.nc[0] * self.nc[1] * self.nc[2]
+        self.state = State.empty(self.n, device)
+        self.cells = Cells.empty(self.n, n_cells, device)
+        self.nlist = NList.empty(self.n, capacity or default_capacity(params, self.n), device)
+        self.ws = alloc_workspace(params, self.n, self.precision, device)
+        self.x32 = torch.empty((3, max(self.n, 1)), dtype=torch.float32, device=device)
+        self.v32 = torch.empty((3, max(self.n, 1)), dtype=torch.float32, device=device)
+        self.d_step = torch.zeros(1, dtype=torch.int64, device=device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
+        self.stats = torch.zeros(2, dtype=torch.float64, device=device)
+
+    # -- setup ----------------------------------------------------------
+    def load(self, x, v, tag, typ, step: int = 0) -> None:
+        """Copy host arrays in, reorder, build the list and compute F(step)."""
+        src = State.empty(self.n, self.device)
+        src.x.copy_(torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64)))
+        src.v.copy_(torch.as_tensor(np.ascontiguousarray(v, dtype=np.float64)))
+        src.tag.copy_(torch.as_tensor(np.ascontiguousarray(tag).astype(np.uint32).view(np.int32)))
+        src.type.copy_(torch.as_tensor(np.ascontiguousarray(typ, dtype=np.uint8)))
+        self.d_step.fill_(int(step))
+        self.status.zero_()
+        self.reorder_from(src)
+        self.rebuild()
+        self.compute_forces(int(step))
+
+    def restore(self, x, v, f, tag, typ, step: int) -> None:
+        """Resume from a snapshot of the sorted state (as ``host_state``
+        returns it): no reordering and no force evaluation, so the next
+        ``step`` continues the interrupted run bit for bit."""
+        st = self.state
+        st.x.copy_(torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64)))
+        st.v.copy_(torch.as_tensor(np.ascontiguousarray(v, dtype=np.float64)))
+        st.f.copy_(torch.as_tensor(np.ascontiguousarray(f, dtype=np.float64)))
+        st.tag.copy_(torch.as_tensor(np.ascontiguousarray(tag).astype(np.uint32).view(np.int32)))
+        st.type.copy_(torch.as_tensor(np.ascontiguousarray(typ, dtype=np.uint8)))
+        self.d_step.fill_(int(step))
+        self.status.zero_()
+
+    def reorder_from(self, src: State) -> None:
+        mixed = self.precision == MIXED
+        dpd_bin_reorder(self.params, src, self.state, self.cells, self.ws,
+                        self.x32 if mixed else None, self.v32 if mixed else None)
+
+    def rebuild(self) -> None:
+        dpd_build_neighbors(self.params, self.state, self.cells, self.nlist, self.status, self.ws)
+
+    def compute_forces(self, step: int, pe_out=None, precision=None) -> None:
+        prec = self.precision if precision is None else precision
+        dpd_forces(self.params, prec, self.state, self.cells, self.nlist, step, self.state.f, self.ws,
+                   x32=self.x32 if prec == MIXED else None, v32=self.v32 if prec == MIXED else None,
+                   pe_out=pe_out, stats=self.stats, status=self.status)
+
+    # -- time stepping --------------------------------------------------
+    def step(self, n_steps: int, reductions: Optional[torch.Tensor] = None, phase_events=None) -> None:
+        mixed = self.precision == MIXED
+        dpd_step(self.params, self.precision, self.state, n_steps, self.d_step, self.cells, self.nlist,
+                 self.status, self.ws, reductions=reductions,
+                 x32=self.x32 if mixed else None, v32=self.v32 if mixed else None,
+                 phase_events=phase_events)
+
+    def check_status(self) -> int:
+        st = int(self.status.item())
+        if st & _abi.STATUS_NLIST_OVERFLOW:
+            raise DPDError(_abi.DPD_ECAPACITY, "neighbour list overflow (grow the capacity)")
+        if st & _abi.STATUS_BAD_BOND:
+            raise DPDError(_abi.DPD_EINVAL, "bond partner without a particle")
+        if st & _abi.STATUS_NONFINITE:
+            raise DPDError(_abi.DPD_EINVAL, "non-finite totals")
+        return st
+
+    def grow_nlist(self, factor: float = 1.5) -> None:
+        need = int(self.nlist.offset[self.n].item())
+        self.nlist = NList.empty(self.n, int(max(need, self.nlist.capacity) * factor), self.device)
+        self.status.zero_()
+
+    @property
+    def step_count(self) -> int:
+        return int(self.d_step.item())
+
+    # -- host views (tests, checkpoints) ---------------------------------
+    def host_state(self):
+        st = self.state
+        return (st.x.cpu().numpy(), st.v.cpu().numpy(), st.f.cpu().numpy(),
+                st.tag.cpu().numpy().view(np.uint32), st.type.cpu().numpy())
+
+    def host_nlist(self):
+        off = self.nlist.offset.cpu().numpy().astype(np.int64)
+        return off, self.nlist.index[: int(off[-1])].cpu().numpy()

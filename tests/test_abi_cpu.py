@@ -1,0 +1,142 @@
+"""Host-side checks of libdpd that need no GPU: the library loads, exports
+every entry point include/dpd.h declares, validates arguments before
+enqueuing anything, and its cell-ranking rule equals the oracle's."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import dpd_inputs as di
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dpd.h")
+
+P = pytest.importorskip("paper_1311_0402_amd")
+from paper_1311_0402_amd import _abi  # noqa: E402
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dpd_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    names = _declared()
+    assert {"dpd_bin_reorder", "dpd_build_neighbors", "dpd_forces", "dpd_step",
+            "dpd_forces_backward"} <= set(names)
+    lib = _abi.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_abi.SIGNATURES)
+    out = subprocess.run(["nm", "-D", "--defined-only", _abi.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    for n in names:
+        assert re.search(rf"\bT {n}$", out, flags=re.M), n
+
+
+def _params(**kw):
+    s = di.small_fluid(1)
+    p = P.Params.like(s, device="cpu")
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_cell_grid_matches_oracle_rule():
+    for box in [(10.0, 10.0, 10.0), (174.716, 174.716, 174.716), (20.0, 40.0, 20.0),
+                (80.0, 80.0, 80.0 / 3.0), (3.0000001, 5.0, 7.25)]:
+        p = _params(box=box)
+        assert P.cell_grid(p) == tuple(oracle.cell_grid(box, 1.0))
+    with pytest.raises(P.DPDError):
+        P.cell_grid(_params(box=(3.0, 10.0, 10.0)))
+
+
+@pytest.mark.parametrize("bad", [dict(r_c=0.0), dict(dt=-1.0), dict(s=0.0), dict(n_types=0),
+                                 dict(skin=-0.1), dict(box=(10.0, float("nan"), 10.0)),
+                                 dict(n_types=2, a=np.array([[25.0, 30.0], [31.0, 25.0]]),
+                                      gamma=np.full((2, 2), 4.5), sigma=np.full((2, 2), 3.0))])
+def test_invalid_params_rejected(bad):
+    p = _params(**bad)
+    assert _abi.lib().dpd_workspace_bytes(C.byref(p.c()), 100, 0) == 0
+    st = _abi.dpd_state()
+    st.n = 0
+    code = _abi.lib().dpd_forces(C.byref(p.c()), 0, C.byref(st), None, None, None,
+                                 C.byref(_abi.dpd_nlist()), 0, None, None, None, None, None, 0, None)
+    assert code == _abi.DPD_EINVAL
+    assert _abi.lib().dpd_last_error().decode()
+
+
+def test_null_and_size_errors_before_launch():
+    p = _params().c()
+    lib = _abi.lib()
+    assert lib.dpd_step(C.byref(p), 0, None, 1, None, None, None, None, None, None, None, None, None,
+                        0, None) == _abi.DPD_EINVAL
+    st = _abi.dpd_state()
+    st.n = 10                    # arrays missing
+    assert lib.dpd_bin_reorder(C.byref(p), C.byref(st), C.byref(st), None, None, None, None, 0,
+                               None) == _abi.DPD_EINVAL
+    assert b"NULL" in lib.dpd_last_error()
+    assert lib.dpd_forces(C.byref(p), 7, C.byref(st), None, None, None, None, 0, None, None, None,
+                          None, None, 0, None) == _abi.DPD_EINVAL
+    # workspace too small -> ECAPACITY (all other arguments are plausible host
+    # addresses; nothing is launched because validation fails first)
+    n = 10
+    buf = [np.zeros(3 * n) for _ in range(3)]
+    st.x, st.v, st.f = (b.ctypes.data for b in buf)
+    tags = np.zeros(n, dtype=np.uint32); types = np.zeros(n, dtype=np.uint8)
+    st.tag, st.type = tags.ctypes.data, types.ctypes.data
+    cells = _abi.dpd_cells()
+    cs = np.zeros(1000, dtype=np.int32)
+    cells.cell_start = cells.cell_xyz = cells.perm = cs.ctypes.data
+    nl = _abi.dpd_nlist()
+    nl.capacity = 100
+    nl.offset = nl.index = cs.ctypes.data
+    d_step = np.zeros(1, dtype=np.uint64)
+    ws = np.zeros(1024, dtype=np.uint8)
+    wsp = (ws.ctypes.data + 255) // 256 * 256
+    code = lib.dpd_step(C.byref(p), 0, C.byref(st), 1, d_step.ctypes.data, None, C.byref(cells),
+                        C.byref(nl), None, None, None, None, wsp, 256, None)
+    assert code == _abi.DPD_ECAPACITY
+    assert b"workspace" in lib.dpd_last_error()
+
+
+_RANK_PROBE = r"""
+#include <cstdio>
+#include "dpd_common.h"
+int main() {
+  int nx, ny, nz;
+  while (std::scanf("%d %d %d", &nx, &ny, &nz) == 3) {
+    int nmax = nx > ny ? nx : ny; nmax = nmax > nz ? nmax : nz;
+    int nb = dpd::bits_for(nmax);
+    for (int z = 0; z < nz; ++z) for (int y = 0; y < ny; ++y) for (int x = 0; x < nx; ++x)
+      std::printf("%d\n", dpd::morton_rank(x, y, z, nx, ny, nz, nb));
+  }
+}
+"""
+
+
+def test_counting_morton_rank_equals_sorted_rank():
+    """The kernels' counting rank (host build of the same header) equals the
+    oracle's rank by sorting Morton codes, on power-of-two and ragged grids."""
+    grids = [(9, 9, 9), (8, 8, 8), (5, 3, 6), (17, 4, 33), (3, 3, 3), (20, 39, 19)]
+    with tempfile.TemporaryDirectory() as td:
+        src = os.path.join(td, "r.cpp")
+        exe = os.path.join(td, "r")
+        open(src, "w").write(_RANK_PROBE)
+        subprocess.run(["g++", "-O1", "-std=c++17", "-I",
+                        os.path.join(ROOT, "paper_1311_0402_amd", "csrc"), src, "-o", exe], check=True)
+        inp = "\n".join(" ".join(map(str, g)) for g in grids)
+        out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout
+    vals = np.array(out.split(), dtype=np.int64)
+    at = 0
+    for g in grids:
+        cnt = int(np.prod(g))
+        ref = oracle.morton_rank_table(np.array(g, dtype=np.int32))
+        np.testing.assert_array_equal(vals[at:at + cnt], ref)
+        at += cnt

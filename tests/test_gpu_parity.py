@@ -1,0 +1,269 @@
+"""GPU (libdpd) against the CPU oracle, element by element.
+
+Bars: reorder permutations and neighbour sets bit-exact; FP64 forces within
+1e-12 of the per-particle summation scale S_i = sum of the magnitudes of the
+added terms (and 1e-12 globally in L2); the mixed form within 1e-5 of |F| in
+the global L2 norm (and its 99.99th percentile per particle).  Positions
+after a step are bit-exact given the same forces.
+"""
+import numpy as np
+import pytest
+
+import dpd_inputs as di
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_1311_0402_amd")
+
+FP64_TOL = 1e-12
+MIXED_TOL = 1e-5
+
+
+def _device_state(s):
+    st = P.State.empty(s.n)
+    st.x.copy_(torch.as_tensor(s.x))
+    st.v.copy_(torch.as_tensor(s.v))
+    st.tag.copy_(torch.as_tensor(s.tag.view(np.int32)))
+    st.type.copy_(torch.as_tensor(s.type))
+    return st
+
+
+def _sorted_system(s, precision=P.FP64, capacity=None):
+    params = P.Params.like(s)
+    sim = P.System(params, s.n, precision, capacity=capacity)
+    sim.load(s.x, s.v, s.tag, s.type, step=0)
+    torch.cuda.synchronize()
+    return sim
+
+
+def _check_fp64(f_gpu, f_ref, scale):
+    d = np.linalg.norm(f_gpu - f_ref, axis=0)
+    bound = FP64_TOL * np.maximum(scale, 1e-300)
+    bad = np.nonzero(d > bound)[0]
+    assert bad.size == 0, f"{bad.size} particles over 1e-12 S_i, worst ratio {np.max(d / bound):.3g}"
+    assert np.linalg.norm(f_gpu - f_ref) <= FP64_TOL * np.linalg.norm(f_ref)
+
+
+def _systems():
+    return {
+        "fluid3000": di.shuffled(di.small_fluid(1), 3),
+        "edge": di.edge_case_fluid(),
+        "ragged": di.uniform_fluid(2717, (9.3, 7.6, 12.9), 8),
+        "amphiphile": di.amphiphile(n=6000, seed=4),
+        "poiseuille": di.poiseuille(seed=9, box=(6.0, 12.0, 5.0), rho=4.0),
+    }
+
+
+# ---------------------------------------------------------------- reorder --
+
+@pytest.mark.parametrize("name", list(_systems()))
+def test_bin_reorder_bitexact(name):
+    s = _systems()[name]
+    params = P.Params.like(s)
+    nc = P.cell_grid(params)
+    np.testing.assert_array_equal(nc, oracle.cell_grid(s.box, s.r_c))
+    src = _device_state(s)
+    dst = P.State.empty(s.n)
+    cells = P.Cells.empty(s.n, int(np.prod(nc)))
+    ws = P.alloc_workspace(params, s.n)
+    x32 = torch.empty((3, s.n), dtype=torch.float32, device="cuda")
+    v32 = torch.empty_like(x32)
+    P.dpd_bin_reorder(params, src, dst, cells, ws, x32=x32, v32=v32)
+    torch.cuda.synchronize()
+    perm_ref, cs_ref = oracle.reorder(s.x, s.tag, s.box, s.r_c)
+    perm = cells.perm.cpu().numpy()
+    np.testing.assert_array_equal(perm, perm_ref)
+    np.testing.assert_array_equal(cells.cell_start.cpu().numpy(), cs_ref)
+    np.testing.assert_array_equal(dst.x.cpu().numpy(), s.x[:, perm_ref])
+    np.testing.assert_array_equal(dst.v.cpu().numpy(), s.v[:, perm_ref])
+    np.testing.assert_array_equal(dst.tag.cpu().numpy().view(np.uint32), s.tag[perm_ref])
+    np.testing.assert_array_equal(dst.type.cpu().numpy(), s.type[perm_ref])
+    iot = cells.idx_of_tag.cpu().numpy()
+    np.testing.assert_array_equal(iot[s.tag[perm_ref]], np.arange(s.n))
+    # FP32 copies: offset inside the cell, velocities rounded
+    cxyz = cells.cell_xyz.cpu().numpy().view(np.uint32)
+    cc = np.stack([cxyz & 1023, (cxyz >> 10) & 1023, cxyz >> 20]).astype(np.float64)
+    ell = s.box / np.array(nc)
+    xs = s.x[:, perm_ref]
+    np.testing.assert_array_equal(x32.cpu().numpy(), (xs - cc * ell[:, None]).astype(np.float32))
+    np.testing.assert_array_equal(v32.cpu().numpy(), s.v[:, perm_ref].astype(np.float32))
+
+
+def test_bin_reorder_is_deterministic_and_idempotent():
+    s = di.shuffled(di.small_fluid(2), 5)
+    sim = _sorted_system(s)
+    x1, v1, _, t1, _ = sim.host_state()
+    perm1 = sim.cells.perm.cpu().numpy()
+    sim2 = _sorted_system(s)
+    np.testing.assert_array_equal(sim2.cells.perm.cpu().numpy(), perm1)
+    # reordering an already sorted state is the identity
+    again = P.State.empty(s.n)
+    P.dpd_bin_reorder(sim.params, sim.state, again, sim2.cells, sim.ws)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(sim2.cells.perm.cpu().numpy(), np.arange(s.n))
+
+
+# ------------------------------------------------------------ neighbours --
+
+@pytest.mark.parametrize("name", list(_systems()))
+def test_neighbor_rows_bitexact(name):
+    s = _systems()[name]
+    sim = _sorted_system(s)
+    x, _, _, _, _ = sim.host_state()
+    off, idx = sim.host_nlist()
+    off_ref, idx_ref = oracle.neighbors(x, s.box, s.r_c)
+    np.testing.assert_array_equal(off, off_ref)
+    np.testing.assert_array_equal(idx, idx_ref)      # same sets, same ascending order
+    assert sim.check_status() == 0
+
+
+def test_neighbor_overflow_flags_and_recovers():
+    s = di.small_fluid(3)
+    sim = _sorted_system(s, capacity=1000)
+    st = int(sim.status.item())
+    assert st & P._abi.STATUS_NLIST_OVERFLOW
+    need = int(sim.nlist.offset[s.n].item())
+    off_ref, idx_ref = oracle.neighbors(sim.host_state()[0], s.box, s.r_c)
+    assert need == len(idx_ref)
+    sim.grow_nlist()
+    sim.rebuild()
+    torch.cuda.synchronize()
+    assert sim.check_status() == 0
+    off, idx = sim.host_nlist()
+    np.testing.assert_array_equal(idx, idx_ref)
+
+
+# ---------------------------------------------------------------- forces --
+
+@pytest.mark.parametrize("name", list(_systems()))
+@pytest.mark.parametrize("step", [0, 7, (1 << 32) + 3])
+def test_forces_fp64(name, step):
+    s = _systems()[name]
+    sim = _sorted_system(s)
+    pe = torch.empty(s.n, dtype=torch.float64, device="cuda")
+    sim.compute_forces(step, pe_out=pe)
+    torch.cuda.synchronize()
+    x, v, f, tag, typ = sim.host_state()
+    f_ref, pe_ref, npair_ref, scale = oracle.forces(s, x, v, tag, typ, step, with_scale=True)
+    _check_fp64(f, f_ref, scale)
+    np.testing.assert_allclose(pe.cpu().numpy(), pe_ref, rtol=1e-12, atol=1e-12)
+    stats = sim.stats.cpu().numpy()
+    np.testing.assert_allclose(stats[0], pe_ref.sum(), rtol=1e-12)
+    assert stats[1] == npair_ref.sum() / 2
+
+
+@pytest.mark.parametrize("name", list(_systems()))
+def test_forces_mixed(name):
+    s = _systems()[name]
+    sim = _sorted_system(s, precision=P.MIXED)
+    x, v, f, tag, typ = sim.host_state()
+    f_ref, _, _ = oracle.forces(s, x, v, tag, typ, 0)
+    d = np.linalg.norm(f - f_ref, axis=0)
+    rel = np.linalg.norm(f - f_ref) / np.linalg.norm(f_ref)
+    assert rel <= MIXED_TOL, rel
+    rms = np.sqrt(np.mean(np.sum(f_ref**2, axis=0)))
+    assert np.percentile(d / rms, 99.99) <= MIXED_TOL
+
+
+def test_forces_antisymmetric_momentum():
+    """Newton's third law on the device: sum of all forces ~ round-off."""
+    s = di.amphiphile(n=6000, seed=8)
+    sim = _sorted_system(s)
+    _, _, f, _, _ = sim.host_state()
+    assert np.abs(f.sum(axis=1)).max() < 1e-12 * np.abs(f).sum()
+
+
+# ------------------------------------------------------------------ step --
+
+def test_step_teacher_forced_100():
+    """Each of 100 steps of the 3000-particle fluid against one oracle step
+    from the GPU's own previous state: positions bit-exact, forces 1e-12 S_i."""
+    s = di.small_fluid(1)
+    sim = _sorted_system(s)
+    red = torch.zeros((1, 8), dtype=torch.float64, device="cuda")
+    prev = sim.host_state()
+    for k in range(1, 101):
+        sim.step(1, reductions=red)
+        torch.cuda.synchronize()
+        cur = sim.host_state()
+        xo, vo, fo, red_ref = oracle.step(s, prev[0], prev[1], prev[2], prev[3], prev[4], k)
+        o_prev = np.argsort(prev[3])
+        o_cur = np.argsort(cur[3])
+        np.testing.assert_array_equal(cur[0][:, o_cur], xo[:, o_prev], err_msg=f"step {k} x")
+        # summation scale of this step's forces (velocity: the half-step one)
+        vh = prev[1] + 0.5 * s.dt * prev[2]
+        _, _, _, scale = oracle.forces(s, xo, vh, prev[3], prev[4], k, with_scale=True)
+        _check_fp64(cur[2][:, o_cur], fo[:, o_prev], scale[o_prev])
+        dv = np.abs(cur[1][:, o_cur] - vo[:, o_prev])
+        assert np.all(dv <= 0.5 * s.dt * FP64_TOL * scale[o_prev] + 1e-15), f"step {k} v"
+        r = red.cpu().numpy()[0]
+        np.testing.assert_allclose(r[:3], red_ref[:3], atol=1e-9)
+        np.testing.assert_allclose(r[3:7], red_ref[3:7], rtol=1e-12)
+        prev = cur
+    assert sim.step_count == 100
+    assert sim.check_status() == 0
+
+
+def test_step_deterministic_and_resumable():
+    s = di.amphiphile(n=6000, seed=2)
+    a = _sorted_system(s)
+    a.step(20)
+    b = _sorted_system(s)
+    b.step(20)
+    torch.cuda.synchronize()
+    for u, w in zip(a.host_state(), b.host_state()):
+        np.testing.assert_array_equal(u, w)
+    # resume: 10 + 10 steps through a host snapshot equals 20 straight steps
+    c = _sorted_system(s)
+    c.step(10)
+    x, v, f, tag, typ = c.host_state()
+    d = P.System(c.params, s.n, P.FP64)
+    d.restore(x, v, f, tag, typ, step=10)
+    d.step(10)
+    torch.cuda.synchronize()
+    for u, w in zip(a.host_state(), d.host_state()):
+        np.testing.assert_array_equal(u, w)
+
+
+def test_step_mixed_tracks_fp64():
+    s = di.small_fluid(4)
+    a = _sorted_system(s, precision=P.MIXED)
+    red = torch.zeros((1, 8), dtype=torch.float64, device="cuda")
+    prev = a.host_state()
+    for k in range(1, 11):
+        a.step(1, reductions=red)
+        torch.cuda.synchronize()
+        cur = a.host_state()
+        # the mixed step's forces against the FP64 oracle at the same state;
+        # they were evaluated with the half-step velocity v_h = v - dt/2 F
+        vh = cur[1] - 0.5 * s.dt * cur[2]
+        f_ref, _, _ = oracle.forces(s, cur[0], vh, cur[3], cur[4], k)
+        rel = np.linalg.norm(cur[2] - f_ref) / np.linalg.norm(f_ref)
+        assert rel <= MIXED_TOL, (k, rel)
+        prev = cur
+
+
+# --------------------------------------------------------------- adjoint --
+
+@pytest.mark.parametrize("name", ["fluid3000", "amphiphile"])
+def test_forces_backward_matches_oracle(name):
+    s = _systems()[name]
+    sim = _sorted_system(s)
+    x, v, f, tag, typ = sim.host_state()
+    rng = np.random.default_rng(0)
+    g = rng.standard_normal(x.shape)
+    nt = s.n_types
+    gx = torch.empty((3, s.n), dtype=torch.float64, device="cuda")
+    gv = torch.empty_like(gx)
+    ga = torch.empty(nt * nt, dtype=torch.float64, device="cuda")
+    gg = torch.empty_like(ga)
+    P.dpd_forces_backward(sim.params, sim.state, sim.cells, sim.nlist, 5,
+                          torch.as_tensor(g, device="cuda"), gx, gv, ga, gg, sim.ws)
+    torch.cuda.synchronize()
+    xb, vb, ab, gb = oracle.forces_vjp(s, x, v, tag, typ, 5, g)
+    np.testing.assert_allclose(gx.cpu().numpy(), xb, rtol=1e-9, atol=1e-9 * np.abs(xb).max())
+    np.testing.assert_allclose(gv.cpu().numpy(), vb, rtol=1e-9, atol=1e-9 * np.abs(vb).max())
+    np.testing.assert_allclose(ga.cpu().numpy().reshape(nt, nt), ab, rtol=1e-10)
+    np.testing.assert_allclose(gg.cpu().numpy().reshape(nt, nt), gb, rtol=1e-10)
