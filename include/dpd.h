@@ -167,16 +167,19 @@ int dpd_bin_reorder(const dpd_params* p, const dpd_state* in, dpd_state* out,
                     void* ws, size_t ws_bytes, void* stream);
 
 /* Ordered neighbour list (Sec. 3.3.2).
- * For a state produced by dpd_bin_reorder: row i lists every j != i with
- * |r_ij|^2 < (r_c + skin)^2 in strictly ascending j.  One 64-lane wavefront
- * per cell scans the 27 surrounding cells in ascending rank; insertion
- * points come from a wavefront ballot and a lane prefix count (no atomics,
- * deterministic).  If the rows need more than nl->capacity entries,
+ * For a state produced by dpd_bin_reorder (x32 = its FP32 in-cell offsets):
+ * row i lists every j != i with |r_ij|^2 < (r_c + skin)^2 (the FP64 rule of
+ * the header comment, bit for bit) in strictly ascending j.  One 64-lane
+ * wavefront per 2x2x2 block of cells scans the surrounding cells in
+ * ascending rank; an FP32 pre-test on the offsets decides all pairs outside
+ * a narrow band around the cutoff and the FP64 rule decides inside it;
+ * insertion points come from a wavefront ballot and a lane prefix count (no
+ * atomics, deterministic).  If the rows need more than nl->capacity entries,
  * DPD_STATUS_NLIST_OVERFLOW is set in *d_status, offset[] still holds the
  * required row sizes (offset[n] = the total needed) and index[] is not
  * written. */
 int dpd_build_neighbors(const dpd_params* p, const dpd_state* sorted, const dpd_cells* cells,
-                        dpd_nlist* nl, int32_t* d_status,
+                        const float* x32, dpd_nlist* nl, int32_t* d_status,
                         void* ws, size_t ws_bytes, void* stream);
 
 /* Pairwise DPD forces (Sec. 2, Eqs (2)-(8)) plus bonds (Sec. 4.5) and the
@@ -209,7 +212,8 @@ int dpd_forces(const dpd_params* p, int32_t precision, const dpd_state* sorted,
  *   reorder, rebuild the list, F <- F(x, v~, step + 1);
  *   v   = v_h + dt/2 F;  step <- step + 1.
  * On entry st->f must hold the forces of the current state (e.g. from
- * dpd_forces at the current step).  *d_step (device uint64) is the step
+ * dpd_forces at the current step).  x32 (FP32 in-cell offsets, [3][n]) is
+ * always required; v32 only for DPD_MIXED.  *d_step (device uint64) is the step
  * counter: read at every step and incremented on the device, so a captured
  * graph can be replayed.  On exit st holds the reordered state and
  * cells / nl describe it.  d_reductions (nullable, device double[n_steps][8])

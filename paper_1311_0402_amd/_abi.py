@@ -90,7 +90,7 @@ SIGNATURES = {
     "dpd_cell_grid": (C.c_int, [PP, P]),
     "dpd_workspace_bytes": (C.c_size_t, [PP, C.c_int32, C.c_int32]),
     "dpd_bin_reorder": (C.c_int, [PP, PS, PS, PC, P, P, P, C.c_size_t, P]),
-    "dpd_build_neighbors": (C.c_int, [PP, PS, PC, PN, P, P, C.c_size_t, P]),
+    "dpd_build_neighbors": (C.c_int, [PP, PS, PC, P, PN, P, P, C.c_size_t, P]),
     "dpd_forces": (C.c_int, [PP, C.c_int32, PS, PC, P, P, PN, C.c_uint64, P, P, P, P, P, C.c_size_t, P]),
     "dpd_step": (C.c_int, [PP, C.c_int32, PS, C.c_int32, P, P, PC, PN, P, P, P, P, P, C.c_size_t, P]),
     "dpd_forces_backward": (C.c_int, [PP, PS, PC, PN, C.c_uint64, P, P, P, P, P, P, C.c_size_t, P]),

@@ -86,7 +86,21 @@ int make_kparams(const dpd_params* p, KParams* k)
     int32_t nmax = k->nc[0] > k->nc[1] ? k->nc[0] : k->nc[1];
     nmax = nmax > k->nc[2] ? nmax : k->nc[2];
     k->nbits = bits_for(nmax);
+    int32_t bmax = 1;
+    int64_t nblk = 1;
+    for (int d = 0; d < 3; ++d) {
+        k->nb[d] = (k->nc[d] + 1) / 2;
+        k->small_dim[d] = k->nc[d] < 4 ? 1 : 0;
+        bmax = k->nb[d] > bmax ? k->nb[d] : bmax;
+        nblk *= k->nb[d];
+    }
+    k->nbits_b = bits_for(bmax);
+    k->n_blocks = (int32_t)nblk;
     k->rl2 = r_list * r_list;
+    // FP32 separations from cell offsets are within ~3e-6 r_list^2 of the
+    // FP64 value (offsets below 4 cells); the band is ten times wider
+    k->list_lo32 = (float)(k->rl2 * (1.0 - std::ldexp(1.0, -15)));
+    k->list_hi32 = (float)(k->rl2 * (1.0 + std::ldexp(1.0, -15)));
     k->rc2 = p->r_c * p->r_c;
     k->r_c = p->r_c;
     k->inv_rc = 1.0 / p->r_c;
@@ -175,6 +189,7 @@ WsLayout ws_layout(int32_t n, int32_t n_cells, bool need_vt, int32_t n_types)
     w.tmp_src = take(N * sizeof(int32_t));
     const int64_t scan_items = (int64_t)(n > n_cells ? n : n_cells) + 1;
     w.scan_part = take((size_t)ceil_div(scan_items, kScanTile) * sizeof(int32_t) + 64);
+    w.rank_tab = take((size_t)(n_cells > 0 ? n_cells : 1) * sizeof(int32_t));
     w.red_part = take((size_t)3 * kRedBlocks * 2 * sizeof(double));
     w.fred_part = take((size_t)force_blocks(n) * 2 * sizeof(double));
     w.bwd_part = take((size_t)backward_part_doubles(n, n_types) * sizeof(double));
@@ -196,8 +211,9 @@ int enqueue_reorder(const KParams& kp, const WsLayout& L, void* ws, const dpd_st
     uint32_t* tmp_tag = carve<uint32_t>(ws, L.tmp_tag);
     int32_t* tmp_src = carve<int32_t>(ws, L.tmp_src);
     int32_t* part = carve<int32_t>(ws, L.scan_part);
+    const int32_t* rank_tab = carve<int32_t>(ws, L.rank_tab);
     DPD_TRY(launch_fill_i32(cells->cell_start, (int64_t)kp.n_cells + 1, 0, s), "fill cell counts");
-    DPD_TRY(launch_bin(kp, n, in->x, key, slot, cxyz, cells->cell_start, s), "bin");
+    DPD_TRY(launch_bin(kp, n, in->x, rank_tab, key, slot, cxyz, cells->cell_start, s), "bin");
     DPD_TRY(launch_scan(cells->cell_start, (int64_t)kp.n_cells + 1, part, s), "scan cells");
     DPD_TRY(launch_place(n, key, slot, cells->cell_start, in->tag, tmp_tag, tmp_src, s), "place");
     GatherArgs g;
@@ -210,16 +226,18 @@ int enqueue_reorder(const KParams& kp, const WsLayout& L, void* ws, const dpd_st
 }
 
 int enqueue_nlist(const KParams& kp, const WsLayout& L, void* ws, const dpd_state* st,
-                  const dpd_cells* cells, dpd_nlist* nl, int32_t* d_status, hipStream_t s)
+                  const dpd_cells* cells, const float* x32, dpd_nlist* nl, int32_t* d_status, hipStream_t s)
 {
     const int32_t n = st->n;
     int32_t* part = carve<int32_t>(ws, L.scan_part);
+    const int32_t* rank_tab = carve<int32_t>(ws, L.rank_tab);
     DPD_TRY(launch_fill_i32(nl->offset + n, 1, 0, s), "clear offset tail");
-    DPD_TRY(launch_nlist_count(kp, n, st->x, cells->cell_start, cells->cell_xyz, nl->offset, s), "nlist count");
+    DPD_TRY(launch_nlist_count(kp, n, st->x, x32, cells->cell_xyz, cells->cell_start, rank_tab, nl->offset, s),
+            "nlist count");
     DPD_TRY(launch_scan(nl->offset, (int64_t)n + 1, part, s), "scan rows");
     DPD_TRY(launch_nlist_check(n, nl->offset, nl->capacity, d_status, s), "nlist check");
-    DPD_TRY(launch_nlist_fill(kp, n, st->x, cells->cell_start, cells->cell_xyz, nl->offset, nl->index,
-                              nl->capacity, s), "nlist fill");
+    DPD_TRY(launch_nlist_fill(kp, n, st->x, x32, cells->cell_xyz, cells->cell_start, rank_tab, nl->offset,
+                              nl->index, nl->capacity, s), "nlist fill");
     return DPD_OK;
 }
 
@@ -283,11 +301,13 @@ int dpd_bin_reorder(const dpd_params* p, const dpd_state* in, dpd_state* out, dp
     if ((rc = check_cells(cells, in->n, false))) return rc;
     const WsLayout L = ws_layout(in->n, kp.n_cells, !kp.lam_half, kp.n_types);
     if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+    DPD_TRY(launch_rank_table(kp, carve<int32_t>(ws, L.rank_tab), as_stream(stream)), "rank table");
     return enqueue_reorder(kp, L, ws, in, nullptr, out, nullptr, cells, x32, v32, as_stream(stream));
 }
 
 int dpd_build_neighbors(const dpd_params* p, const dpd_state* sorted, const dpd_cells* cells,
-                        dpd_nlist* nl, int32_t* d_status, void* ws, size_t ws_bytes, void* stream)
+                        const float* x32, dpd_nlist* nl, int32_t* d_status, void* ws, size_t ws_bytes,
+                        void* stream)
 {
     KParams kp;
     int rc = make_kparams(p, &kp);
@@ -296,9 +316,11 @@ int dpd_build_neighbors(const dpd_params* p, const dpd_state* sorted, const dpd_
     if (sorted->n < 0) return fail(DPD_EINVAL, "n must be >= 0");
     if (sorted->n > 0 && !sorted->x) return fail(DPD_EINVAL, "sorted->x is NULL");
     if ((rc = check_cells(cells, sorted->n, false)) || (rc = check_nlist(nl, sorted->n))) return rc;
+    if (sorted->n > 0 && !x32) return fail(DPD_EINVAL, "x32 (from dpd_bin_reorder) is NULL");
     const WsLayout L = ws_layout(sorted->n, kp.n_cells, !kp.lam_half, kp.n_types);
     if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
-    return enqueue_nlist(kp, L, ws, sorted, cells, nl, d_status, as_stream(stream));
+    DPD_TRY(launch_rank_table(kp, carve<int32_t>(ws, L.rank_tab), as_stream(stream)), "rank table");
+    return enqueue_nlist(kp, L, ws, sorted, cells, x32, nl, d_status, as_stream(stream));
 }
 
 int dpd_forces(const dpd_params* p, int32_t precision, const dpd_state* sorted, const dpd_cells* cells,
@@ -352,12 +374,13 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
     const int32_t n = st->n;
     const bool bonds = kp.partner != nullptr;
     if ((rc = check_cells(cells, n, bonds)) || (rc = check_nlist(nl, n))) return rc;
-    if (precision == DPD_MIXED && n > 0 && (!x32 || !v32))
-        return fail(DPD_EINVAL, "mixed precision needs x32 and v32");
+    if (n > 0 && !x32) return fail(DPD_EINVAL, "x32 is NULL (the list build needs it)");
+    if (precision == DPD_MIXED && n > 0 && !v32) return fail(DPD_EINVAL, "mixed precision needs v32");
     const WsLayout L = ws_layout(n, kp.n_cells, !kp.lam_half, kp.n_types);
     if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
     if (n == 0 || n_steps == 0) return DPD_OK;
     const hipStream_t s = as_stream(stream);
+    DPD_TRY(launch_rank_table(kp, carve<int32_t>(ws, L.rank_tab), s), "rank table");
 
     dpd_state b;                                    // drifted, not yet reordered
     b.n = n;
@@ -389,11 +412,10 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
         DPD_TRY(mark(k, 0), "event");
         DPD_TRY(launch_vv1(kp, n, st->x, st->v, st->f, st->tag, st->type, b.x, b.v, bvt, b.tag, b.type, s), "vv1");
         DPD_TRY(mark(k, 1), "event");
-        rc = enqueue_reorder(kp, L, ws, &b, bvt, st, vt_sorted, cells, mixed ? x32 : nullptr,
-                             mixed ? v32 : nullptr, s);
+        rc = enqueue_reorder(kp, L, ws, &b, bvt, st, vt_sorted, cells, x32, mixed ? v32 : nullptr, s);
         if (rc) return rc;
         DPD_TRY(mark(k, 2), "event");
-        rc = enqueue_nlist(kp, L, ws, st, cells, nl, d_status, s);
+        rc = enqueue_nlist(kp, L, ws, st, cells, x32, nl, d_status, s);
         if (rc) return rc;
         DPD_TRY(mark(k, 3), "event");
         DPD_TRY(launch_forces(kp, precision, a, s), "forces");

@@ -32,6 +32,12 @@ struct KParams {
     int32_t nc[3];
     int32_t nbits;        // bits of the largest cell coordinate
     int32_t n_cells;
+    int32_t nb[3];        // 2x2x2 cell blocks per side (neighbour-list work units)
+    int32_t nbits_b;
+    int32_t n_blocks;
+    int32_t small_dim[3]; // n_c < 4: a block's neighbourhood wraps onto itself
+    float list_lo32;      // FP32 pre-test: r^2 < lo is a neighbour for sure,
+    float list_hi32;      // r^2 >= hi is not; in between the FP64 test decides
     double rl2;           // (r_c + skin)^2, neighbour test  r^2 < rl2
     double rc2;           // r_c^2, force test              r^2 < rc2
     double r_c;
@@ -90,6 +96,32 @@ DPD_HD int32_t morton_rank(int32_t cx, int32_t cy, int32_t cz,
     return (int32_t)rank;
 }
 
+// Inverse of morton_rank: the cell whose rank is r (0 <= r < nx*ny*nz).
+// Same walk; at every code bit, a 0 is taken while r is below the number
+// of grid cells with that prefix, otherwise r drops by that number.
+DPD_HD void morton_unrank(int64_t r, int32_t nx, int32_t ny, int32_t nz, int32_t nbits,
+                          int32_t* cx, int32_t* cy, int32_t* cz)
+{
+    int64_t px = 0, py = 0, pz = 0;
+    for (int b = nbits - 1; b >= 0; --b) {
+        int64_t c0 = prefix_count(2 * pz, b, nz) * prefix_count(py, b + 1, ny) * prefix_count(px, b + 1, nx);
+        int bz = 0;
+        if (r >= c0) { r -= c0; bz = 1; }
+        pz = 2 * pz + bz;
+        c0 = prefix_count(pz, b, nz) * prefix_count(2 * py, b, ny) * prefix_count(px, b + 1, nx);
+        int by = 0;
+        if (r >= c0) { r -= c0; by = 1; }
+        py = 2 * py + by;
+        c0 = prefix_count(pz, b, nz) * prefix_count(py, b, ny) * prefix_count(2 * px, b, nx);
+        int bx = 0;
+        if (r >= c0) { r -= c0; bx = 1; }
+        px = 2 * px + bx;
+    }
+    *cx = (int32_t)px;
+    *cy = (int32_t)py;
+    *cz = (int32_t)pz;
+}
+
 DPD_HD int32_t bits_for(int32_t nmax)
 {
     int32_t b = 1;
@@ -106,6 +138,19 @@ DPD_HD uint32_t pack_cell(int32_t cx, int32_t cy, int32_t cz)
 
 // ---------------------------------------------------------------------------
 // Device helpers
+// ---------------------------------------------------------------------------
+
+// Workgroups are dealt to the 8 XCDs round-robin; renumber them so every
+// XCD (and its L2) works through one contiguous range of logical ids.
+__device__ __forceinline__ int32_t xcd_logical_id(int32_t p, int32_t groups)
+{
+    const int32_t q = groups / 8, r = groups % 8;
+    const int32_t xcd = p % 8, k = p / 8;
+    return xcd < r ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
+}
+
+// ---------------------------------------------------------------------------
+// (continued) device helpers
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }

@@ -25,6 +25,7 @@ struct WsLayout {
     size_t key, slot, cxyz;            // binning: cell rank, slot in cell, cell coords
     size_t tmp_tag, tmp_src;           // scatter before the in-cell tag order
     size_t scan_part;                  // partial sums of the device-wide scan
+    size_t rank_tab;                   // Morton rank of every cell (row-major cell index)
     size_t red_part;                   // velocity reduction partials
     size_t fred_part;                  // force-kernel partials (PE, pairs)
     size_t bwd_part;                   // adjoint partials (type-pair matrices)
@@ -35,8 +36,10 @@ WsLayout ws_layout(int32_t n, int32_t n_cells, bool need_vt, int32_t n_types);
 
 // ---- reorder (k_reorder.hip) ----
 hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t s);
-hipError_t launch_bin(const KParams& kp, int32_t n, const double* x, int32_t* key, int32_t* slot,
-                      uint32_t* cxyz, int32_t* counts, hipStream_t s);
+// rank_tab[cx + nc_x (cy + nc_y cz)] = Morton rank of the cell
+hipError_t launch_rank_table(const KParams& kp, int32_t* rank_tab, hipStream_t s);
+hipError_t launch_bin(const KParams& kp, int32_t n, const double* x, const int32_t* rank_tab, int32_t* key,
+                      int32_t* slot, uint32_t* cxyz, int32_t* counts, hipStream_t s);
 // in-place exclusive scan of data[0 .. count); partials needs ceil(count/kScanTile) ints
 hipError_t launch_scan(int32_t* data, int64_t count, int32_t* partials, hipStream_t s);
 hipError_t launch_place(int32_t n, const int32_t* key, const int32_t* slot, const int32_t* cell_start,
@@ -53,13 +56,14 @@ hipError_t launch_finalize(const KParams& kp, int32_t n, const int32_t* key, con
                            hipStream_t s);
 
 // ---- neighbour list (k_nlist.hip) ----
-hipError_t launch_nlist_count(const KParams& kp, int32_t n, const double* x, const int32_t* cell_start,
-                              const uint32_t* cell_xyz, int32_t* offset, hipStream_t s);
+hipError_t launch_nlist_count(const KParams& kp, int32_t n, const double* x, const float* x32,
+                              const uint32_t* cell_xyz, const int32_t* cell_start, const int32_t* rank_tab,
+                              int32_t* offset, hipStream_t s);
 hipError_t launch_nlist_check(int32_t n, const int32_t* offset, int64_t capacity, int32_t* status,
                               hipStream_t s);
-hipError_t launch_nlist_fill(const KParams& kp, int32_t n, const double* x, const int32_t* cell_start,
-                             const uint32_t* cell_xyz, const int32_t* offset, int32_t* index,
-                             int64_t capacity, hipStream_t s);
+hipError_t launch_nlist_fill(const KParams& kp, int32_t n, const double* x, const float* x32,
+                             const uint32_t* cell_xyz, const int32_t* cell_start, const int32_t* rank_tab,
+                             const int32_t* offset, int32_t* index, int64_t capacity, hipStream_t s);
 
 // ---- forces (k_force.hip) ----
 struct ForceArgs {

@@ -25,7 +25,24 @@ hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(kBlock) void k_rank_table(KParams kp, int32_t* __restrict__ rank_tab)
+{
+    const int32_t c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= kp.n_cells) return;
+    const int32_t cx = c % kp.nc[0];
+    const int32_t cy = (c / kp.nc[0]) % kp.nc[1];
+    const int32_t cz = c / (kp.nc[0] * kp.nc[1]);
+    rank_tab[c] = morton_rank(cx, cy, cz, kp.nc[0], kp.nc[1], kp.nc[2], kp.nbits);
+}
+
+hipError_t launch_rank_table(const KParams& kp, int32_t* rank_tab, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rank_table, dim3(ceil_div(kp.n_cells, kBlock)), dim3(kBlock), 0, s, kp, rank_tab);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(kBlock) void k_bin(KParams kp, int32_t n, const double* __restrict__ x,
+                                                const int32_t* __restrict__ rank_tab,
                                                 int32_t* __restrict__ key, int32_t* __restrict__ slot,
                                                 uint32_t* __restrict__ cxyz, int32_t* __restrict__ counts)
 {
@@ -34,17 +51,18 @@ __global__ __launch_bounds__(kBlock) void k_bin(KParams kp, int32_t n, const dou
     const int32_t cx = cell_coord(x[i], kp.inv_cell[0], kp.nc[0]);
     const int32_t cy = cell_coord(x[(int64_t)n + i], kp.inv_cell[1], kp.nc[1]);
     const int32_t cz = cell_coord(x[2 * (int64_t)n + i], kp.inv_cell[2], kp.nc[2]);
-    const int32_t r = morton_rank(cx, cy, cz, kp.nc[0], kp.nc[1], kp.nc[2], kp.nbits);
+    const int32_t r = rank_tab[cx + kp.nc[0] * (cy + kp.nc[1] * cz)];
     key[i] = r;
     cxyz[i] = pack_cell(cx, cy, cz);
     slot[i] = atomicAdd(&counts[r], 1);
 }
 
-hipError_t launch_bin(const KParams& kp, int32_t n, const double* x, int32_t* key, int32_t* slot,
-                      uint32_t* cxyz, int32_t* counts, hipStream_t s)
+hipError_t launch_bin(const KParams& kp, int32_t n, const double* x, const int32_t* rank_tab, int32_t* key,
+                      int32_t* slot, uint32_t* cxyz, int32_t* counts, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bin, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, kp, n, x, key, slot, cxyz, counts);
+    hipLaunchKernelGGL(k_bin, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, kp, n, x, rank_tab, key, slot,
+                       cxyz, counts);
     return hipGetLastError();
 }
 

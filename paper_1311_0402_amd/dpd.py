@@ -205,10 +205,10 @@ def dpd_bin_reorder(params: Params, src: State, dst: State, cells: Cells, ws: to
           "dpd_bin_reorder")
 
 
-def dpd_build_neighbors(params: Params, st: State, cells: Cells, nl: NList, status: torch.Tensor,
-                        ws: torch.Tensor, stream=None) -> None:
+def dpd_build_neighbors(params: Params, st: State, cells: Cells, x32: torch.Tensor, nl: NList,
+                        status: torch.Tensor, ws: torch.Tensor, stream=None) -> None:
     s, c, n = st.c(), cells.c(), nl.c()
-    check(lib().dpd_build_neighbors(C.byref(params.c()), C.byref(s), C.byref(c), C.byref(n),
+    check(lib().dpd_build_neighbors(C.byref(params.c()), C.byref(s), C.byref(c), _ptr(x32), C.byref(n),
                                     _ptr(status), _ptr(ws), ws.numel(), _stream(stream)),
           "dpd_build_neighbors")
 
@@ -313,10 +313,11 @@ class System:
     def reorder_from(self, src: State) -> None:
         mixed = self.precision == MIXED
         dpd_bin_reorder(self.params, src, self.state, self.cells, self.ws,
-                        self.x32 if mixed else None, self.v32 if mixed else None)
+                        self.x32, self.v32 if mixed else None)
 
     def rebuild(self) -> None:
-        dpd_build_neighbors(self.params, self.state, self.cells, self.nlist, self.status, self.ws)
+        dpd_build_neighbors(self.params, self.state, self.cells, self.x32, self.nlist, self.status,
+                            self.ws)
 
     def compute_forces(self, step: int, pe_out=None, precision=None) -> None:
         prec = self.precision if precision is None else precision
@@ -329,8 +330,7 @@ class System:
         mixed = self.precision == MIXED
         dpd_step(self.params, self.precision, self.state, n_steps, self.d_step, self.cells, self.nlist,
                  self.status, self.ws, reductions=reductions,
-                 x32=self.x32 if mixed else None, v32=self.v32 if mixed else None,
-                 phase_events=phase_events)
+                 x32=self.x32, v32=self.v32 if mixed else None, phase_events=phase_events)
 
     def check_status(self) -> int:
         st = int(self.status.item())

@@ -100,8 +100,12 @@ def test_null_and_size_errors_before_launch():
     d_step = np.zeros(1, dtype=np.uint64)
     ws = np.zeros(1024, dtype=np.uint8)
     wsp = (ws.ctypes.data + 255) // 256 * 256
+    x32 = np.zeros(3 * n, dtype=np.float32)
     code = lib.dpd_step(C.byref(p), 0, C.byref(st), 1, d_step.ctypes.data, None, C.byref(cells),
                         C.byref(nl), None, None, None, None, wsp, 256, None)
+    assert code == _abi.DPD_EINVAL and b"x32" in lib.dpd_last_error()
+    code = lib.dpd_step(C.byref(p), 0, C.byref(st), 1, d_step.ctypes.data, None, C.byref(cells),
+                        C.byref(nl), x32.ctypes.data, None, None, None, wsp, 256, None)
     assert code == _abi.DPD_ECAPACITY
     assert b"workspace" in lib.dpd_last_error()
 
@@ -114,8 +118,13 @@ int main() {
   while (std::scanf("%d %d %d", &nx, &ny, &nz) == 3) {
     int nmax = nx > ny ? nx : ny; nmax = nmax > nz ? nmax : nz;
     int nb = dpd::bits_for(nmax);
-    for (int z = 0; z < nz; ++z) for (int y = 0; y < ny; ++y) for (int x = 0; x < nx; ++x)
-      std::printf("%d\n", dpd::morton_rank(x, y, z, nx, ny, nz, nb));
+    for (int z = 0; z < nz; ++z) for (int y = 0; y < ny; ++y) for (int x = 0; x < nx; ++x) {
+      int r = dpd::morton_rank(x, y, z, nx, ny, nz, nb);
+      int ux, uy, uz;
+      dpd::morton_unrank(r, nx, ny, nz, nb, &ux, &uy, &uz);
+      if (ux != x || uy != y || uz != z) { std::printf("unrank mismatch\n"); return 1; }
+      std::printf("%d\n", r);
+    }
   }
 }
 """
@@ -123,7 +132,8 @@ int main() {
 
 def test_counting_morton_rank_equals_sorted_rank():
     """The kernels' counting rank (host build of the same header) equals the
-    oracle's rank by sorting Morton codes, on power-of-two and ragged grids."""
+    oracle's rank by sorting Morton codes, on power-of-two and ragged grids,
+    and the kernels' unrank inverts it."""
     grids = [(9, 9, 9), (8, 8, 8), (5, 3, 6), (17, 4, 33), (3, 3, 3), (20, 39, 19)]
     with tempfile.TemporaryDirectory() as td:
         src = os.path.join(td, "r.cpp")
