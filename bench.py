@@ -101,6 +101,64 @@ def run_precision(P, torch, sysd, precision, steps, warmup):
     return out
 
 
+def run_batched(P, torch, steps, warmup, seq_steps, n_sys=256):
+    """Replica ensemble: n_sys independent fluids of log-uniform size in
+    [1000, 64000] at density 3, mixed precision.  The batch advances as one
+    captured HIP graph per step (tiles from the autotuner); the comparison
+    runs the same systems one after another, each with its own dpd_step."""
+    import dpd_inputs as di
+    from paper_1311_0402_amd import autotune
+    spec = di.batched_spec(n_sys=n_sys, seed=4)
+    systems = di.batched_systems(spec, seed=5)
+    n_tot = int(sum(s.n for s in systems))
+    b = P.Batch([P.Params.like(s) for s in systems], [s.n for s in systems], precision=P.MIXED)
+    b.load(np.concatenate([s.x for s in systems], axis=1), np.concatenate([s.v for s in systems], axis=1),
+           np.concatenate([s.tag for s in systems]), np.concatenate([s.type for s in systems]))
+    torch.cuda.synchronize()
+    b.check_status()
+    t0 = time.perf_counter()
+    tiles, timings = autotune.tune(b, use_cache=False)
+    tune_s = time.perf_counter() - t0
+    b.step(warmup, use_graph=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.step(steps, use_graph=True)
+    e1.record()
+    torch.cuda.synchronize()
+    b.check_status()
+    ms = e0.elapsed_time(e1) / steps
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    # the same systems one after another
+    sims = []
+    for s in systems:
+        sim = P.System(P.Params.like(s), s.n, P.MIXED)
+        sim.load(s.x, s.v, s.tag, s.type)
+        sims.append(sim)
+    for sim in sims:
+        sim.step(2)
+    torch.cuda.synchronize()
+    e0.record()
+    for sim in sims:
+        sim.step(seq_steps)
+    e1.record()
+    torch.cuda.synchronize()
+    for sim in sims:
+        sim.check_status()
+    ms_seq = e0.elapsed_time(e1) / seq_steps
+    del sims
+    torch.cuda.empty_cache()
+    return {"n_sys": n_sys, "n_total": n_tot, "steps": steps, "ms_per_step": ms,
+            "particle_steps_per_s": n_tot / (ms * 1e-3),
+            "tiles": {"force_grid": tiles.force_grid, "nlist_waves": tiles.nlist_waves},
+            "autotune_s": tune_s, "autotune_ms_per_step": timings,
+            "sequential": {"steps": seq_steps, "ms_per_step": ms_seq,
+                           "particle_steps_per_s": n_tot / (ms_seq * 1e-3)},
+            "speedup_vs_sequential": ms_seq / ms}
+
+
 def cpu_baseline(sysd):
     """The CPU oracle on a bounded sample: whole oracle time steps (cell-list
     neighbour search, all host threads) on a slab of the same workload."""
@@ -135,6 +193,8 @@ def main():
     ap.add_argument("--n", type=int, default=16_000_000)
     ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -153,6 +213,12 @@ def main():
     for prec in (["fp64", "mixed"] if args.precision == "both" else [args.precision]):
         results[prec] = run_precision(P, torch, sysd, prec, args.steps, args.warmup)
         log(f"{prec}: {results[prec]['ms_per_step']:.3f} ms/step, phases {results[prec]['phase_ms']}")
+
+    if not args.no_batched:
+        results["batched"] = run_batched(P, torch, args.batched_steps, 10, max(5, args.batched_steps // 10))
+        bt = results["batched"]
+        log(f"batched: {bt['ms_per_step']:.3f} ms/step for {bt['n_total']} particles in {bt['n_sys']} systems "
+            f"(tiles {bt['tiles']}); sequential {bt['sequential']['ms_per_step']:.3f} ms/step")
 
     head = results.get("mixed") or results["fp64"]
     head_name = "mixed" if "mixed" in results else "fp64"

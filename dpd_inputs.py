@@ -258,3 +258,18 @@ def edge_case_fluid(seed: int = 7, box=(5.0, 4.5, 3.5), n: int = 180) -> System:
     v = _velocities(rng, n)
     return System(box=box, x=x, v=v, tag=np.arange(n, dtype=np.uint32),
                   type=np.zeros(n, dtype=np.uint8), seed=seed, name="edge")
+
+
+def clustered_fluid(seed: int = 8, box=(6.0, 6.0, 6.0), n_cluster: int = 150, n_rest: int = 100,
+                    size: float = 1.2) -> System:
+    """Most particles packed in a small corner region (rows far longer than
+    the box-average density suggests), the rest uniform."""
+    box = np.asarray(box, dtype=np.float64)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    xc = rng.uniform(0.2, 0.2 + size, size=(3, n_cluster))
+    xr = _uniform_positions(rng, n_rest, box)
+    x = np.ascontiguousarray(np.concatenate([xc, xr], axis=1))
+    n = n_cluster + n_rest
+    v = _velocities(rng, n)
+    return System(box=box, x=x, v=v, tag=np.arange(n, dtype=np.uint32),
+                  type=np.zeros(n, dtype=np.uint8), seed=seed, name="clustered")

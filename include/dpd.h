@@ -159,9 +159,12 @@ size_t dpd_workspace_bytes(const dpd_params* p, int32_t n, int32_t precision);
  * with bit b of c_x at 3b, c_y at 3b+1, c_z at 3b+2; particles are written to
  * `out` in ascending (cell rank, tag) order.  in and out must not overlap.
  * out->f is not touched.  cells receives cell_start, cell_xyz, perm and
- * (if non-NULL) idx_of_tag.  When x32 / v32 are non-NULL they receive FP32
- * copies for the mixed-precision force: x32 = (float)(x - c * L / n_c) (the
- * offset inside the particle's cell) and v32 = (float)v, both [3][n]. */
+ * (if non-NULL) idx_of_tag.  When x32 / v32 are non-NULL they receive
+ * packed FP32 copies, one float4 per sorted particle ([n][4], 16-byte
+ * aligned): x32[i] = ((float)(x_k - c_k L_k / n_c,k) for k = x, y, z -- the
+ * offset inside the particle's cell --, tag bits) and v32[i] = ((float)v,
+ * cell_xyz bits).  The neighbour list needs x32; the mixed-precision force
+ * needs both. */
 int dpd_bin_reorder(const dpd_params* p, const dpd_state* in, dpd_state* out,
                     dpd_cells* cells, float* x32, float* v32,
                     void* ws, size_t ws_bytes, void* stream);
@@ -191,7 +194,8 @@ int dpd_build_neighbors(const dpd_params* p, const dpd_state* sorted, const dpd_
  *   xi_ij = sqrt(-2 ln u1) cos(2 pi u2), (u1, u2) = ((w0 + 1/2) 2^-32,
  *   w1 2^-32), (w0..w3) = Philox4x32-10(counter = (min tag, max tag,
  *   step low word, step high word), key = (seed low word, seed high word)).
- * f_out[i] = sum over i's row in list order, then bonds, then body force.
+ * f_out[i] = the sum over i's row (a fixed reduction tree over the row's
+ * list entries: deterministic for a given list), plus bonds and body force.
  * DPD_MIXED evaluates the pair terms in FP32 from x32 / v32 / cells->cell_xyz
  * (as written by dpd_bin_reorder) and sums them with compensated FP32;
  * DPD_FP64 ignores x32 / v32.  pe_out (nullable, [n]) gets each particle's
@@ -212,8 +216,9 @@ int dpd_forces(const dpd_params* p, int32_t precision, const dpd_state* sorted,
  *   reorder, rebuild the list, F <- F(x, v~, step + 1);
  *   v   = v_h + dt/2 F;  step <- step + 1.
  * On entry st->f must hold the forces of the current state (e.g. from
- * dpd_forces at the current step).  x32 (FP32 in-cell offsets, [3][n]) is
- * always required; v32 only for DPD_MIXED.  *d_step (device uint64) is the step
+ * dpd_forces at the current step).  x32 (packed FP32 in-cell offsets,
+ * float4 [n], see dpd_bin_reorder) is always required; v32 (float4 [n])
+ * only for DPD_MIXED.  *d_step (device uint64) is the step
  * counter: read at every step and incremented on the device, so a captured
  * graph can be replayed.  On exit st holds the reordered state and
  * cells / nl describe it.  d_reductions (nullable, device double[n_steps][8])
@@ -236,11 +241,131 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
  *   a_bar[t][u] = dL/da_tu for the symmetric parameter (both entries equal),
  *   gamma_bar[t][u] likewise,
  * evaluated at the same (sorted state, list, step) as dpd_forces (FP64).
- * a_bar / gamma_bar are device double[n_types * n_types]. */
+ * a_bar / gamma_bar are device double[n_types * n_types].  With accumulate
+ * != 0 all four outputs are added to instead of overwritten. */
 int dpd_forces_backward(const dpd_params* p, const dpd_state* sorted, const dpd_cells* cells,
                         const dpd_nlist* nl, uint64_t step, const double* grad_f,
                         double* grad_x, double* grad_v, double* grad_a, double* grad_gamma,
-                        void* ws, size_t ws_bytes, void* stream);
+                        int32_t accumulate, void* ws, size_t ws_bytes, void* stream);
+
+/* Reverse of one dpd_step time step (lambda = 1/2 only), for trajectory
+ * gradients with ξ and the pair sets held fixed.  st / cells / nl are the
+ * state AFTER the step (as dpd_step leaves them: reordered x', v', F', and
+ * cells->perm mapping its order to the order before the step), `step` its
+ * counter value.  The forward step is
+ *   v_h = v + dt/2 F;  x' = x + dt v_h;  F' = F(x', v_h, step);
+ *   v' = v_h + dt/2 F';  then reordering by perm.
+ * Given the adjoints (gx_in, gv_in, gf_in) of (x', v', F') in the new order,
+ * writes the adjoints (gx_out, gv_out, gf_out) of (x, v, F) in the order
+ * before the step, and ADDS the step's contribution to grad_a / grad_gamma
+ * (symmetric-parameter gradients, device double[n_types^2]).  v_h is taken
+ * as v' - dt/2 F' (equal to the forward value up to rounding).  Outputs must
+ * not alias inputs; all arrays [3][n] device FP64.
+ * Returns DPD_EUNSUPPORTED for lambda != 1/2. */
+int dpd_step_backward(const dpd_params* p, const dpd_state* st, const dpd_cells* cells,
+                      const dpd_nlist* nl, uint64_t step, const double* gx_in, const double* gv_in,
+                      const double* gf_in, double* gx_out, double* gv_out, double* gf_out,
+                      double* grad_a, double* grad_gamma, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched replicas
+ *
+ * Many independent periodic systems advanced together.  The paper hides
+ * kernel-launch latency behind CUDA streams (Sec. 3.2.1); here every phase of
+ * a step covers all systems in one launch (the particles, cells and 2x2x2
+ * list blocks of all systems are numbered one after another), and a step
+ * can be replayed as one HIP graph.
+ *
+ * A batch is described once by dpd_batch_create: per-system parameters and
+ * particle ranges.  Systems may differ in box, particle count, a / gamma /
+ * sigma tables, seed and body force; they share r_c, skin, dt, lambda, s and
+ * n_types (the integrator and the weight form), and carry no bonds.  Within
+ * system s, particles occupy [sys_offset[s], sys_offset[s+1]) of the
+ * concatenated state and keep that range under reordering; tags are local
+ * (a permutation of 0 .. n_s - 1 within each system), so the pair Gaussian of
+ * a system equals that of the same system run alone.  Every system's
+ * trajectory is bitwise equal to its single-system dpd_step run; per-system
+ * statistics are summed in a different (fixed) order than dpd_step's.
+ *
+ * The handle is HOST memory allocated by dpd_batch_create and released by
+ * dpd_batch_destroy; its device tables live in caller memory (d_table),
+ * which must outlive the handle.  A handle may be used from one host thread
+ * at a time.
+ * ------------------------------------------------------------------------- */
+
+typedef struct dpd_batch dpd_batch;
+
+/* Launch shapes of the batched phases; any valid choice gives bitwise the
+ * same results (only the speed differs). */
+typedef struct dpd_tiles {
+    int32_t force_grid;     /* workgroups of the persistent force pass,
+                               64 .. 8192 (0 = one per 4 chunks of 64 rows,
+                               at most 2048)                                   */
+    int32_t nlist_waves;    /* waves per workgroup of the list build: 1, 2 or 4
+                               (0 = 4); each wave owns one 2x2x2 cell block  */
+    int32_t reserved[2];    /* 0                                              */
+} dpd_tiles;
+
+/* Device bytes of the batch table for n_sys systems and n_total particles
+ * (0 on invalid sizes). */
+size_t dpd_batch_table_bytes(int32_t n_sys, int64_t n_total);
+
+/* Describes a batch.  per_sys: host dpd_params[n_sys] (bond_partner must be
+ * NULL); sys_offset: host int64[n_sys + 1], sys_offset[0] = 0, strictly
+ * increasing, total below 2^31; n_sys in [1, 65535].  d_table: device memory
+ * of dpd_batch_table_bytes(n_sys, total) bytes, 256-byte aligned; it is
+ * filled by copies and one kernel enqueued on `stream`.  *out receives the
+ * handle.  DPD_EINVAL for invalid parameters (the message names the
+ * system), DPD_EUNSUPPORTED for bonds or for systems that differ in a
+ * shared field, DPD_ECAPACITY for a short table. */
+int dpd_batch_create(const dpd_params* per_sys, int32_t n_sys, const int64_t* sys_offset, void* d_table,
+                     size_t table_bytes, void* stream, dpd_batch** out);
+
+/* Releases the handle and its cached HIP graph (NULL is a no-op).  The
+ * caller synchronises first if graph replays may still run. */
+void dpd_batch_destroy(dpd_batch* b);
+
+/* Totals of the concatenated arrays: particles and cells (cell_start of a
+ * batch has n_cells_total + 1 entries).  Either pointer may be NULL. */
+int dpd_batch_sizes(const dpd_batch* b, int64_t* n_total, int64_t* n_cells_total);
+
+/* Workspace bytes for the batched calls in `precision` (0 on error). */
+size_t dpd_batch_workspace_bytes(const dpd_batch* b, int32_t precision);
+
+/* Launch shapes used by later calls (validated; DPD_EINVAL if out of range).
+ * Changing them drops a cached graph. */
+int dpd_batch_set_tiles(dpd_batch* b, const dpd_tiles* t);
+int dpd_batch_get_tiles(const dpd_batch* b, dpd_tiles* t);
+
+/* dpd_bin_reorder over all systems: each system's particles are binned in
+ * its own box and reordered within its own range; cells are numbered
+ * system by system, each system's in ascending Morton rank.  perm and
+ * idx_of_tag hold batch-wide indices (idx_of_tag[sys_offset[s] + tag]). */
+int dpd_batch_bin_reorder(const dpd_batch* b, const dpd_state* in, dpd_state* out, dpd_cells* cells,
+                          float* x32, float* v32, void* ws, size_t ws_bytes, void* stream);
+
+/* dpd_build_neighbors over all systems; list entries are batch-wide
+ * indices and never cross a system. */
+int dpd_batch_build_neighbors(const dpd_batch* b, const dpd_state* sorted, const dpd_cells* cells,
+                              const float* x32, dpd_nlist* nl, int32_t* d_status, void* ws,
+                              size_t ws_bytes, void* stream);
+
+/* dpd_forces over all systems at `step`; pe_out (nullable, device
+ * double[n_total]) gets each particle's share of the pair potential. */
+int dpd_batch_forces(const dpd_batch* b, int32_t precision, const dpd_state* sorted, const dpd_cells* cells,
+                     const float* x32, const float* v32, const dpd_nlist* nl, uint64_t step,
+                     double* f_out, double* pe_out, int32_t* d_status, void* ws, size_t ws_bytes,
+                     void* stream);
+
+/* dpd_step over all systems (same preconditions per system, shared step
+ * counter *d_step).  d_reductions (nullable): device double[n_steps][n_sys][8]
+ * with dpd_step's eight per-step totals for every system.  use_graph != 0:
+ * one step is captured into a HIP graph held by the handle (captured again
+ * when an argument or the tiles change) and the graph is launched n_steps
+ * times on `stream`; the results equal those of use_graph = 0. */
+int dpd_batch_step(dpd_batch* b, int32_t precision, dpd_state* st, int32_t n_steps, uint64_t* d_step,
+                   double* d_reductions, dpd_cells* cells, dpd_nlist* nl, float* x32, float* v32,
+                   int32_t* d_status, int32_t use_graph, void* ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -315,3 +315,69 @@ def run(sys_, x, v, f, tag, typ, step0: int, n_steps: int, *, use_cells: bool = 
         raise RuntimeError("orc_run failed")
     prof_mean = None if prof is None else prof / np.maximum(cnt, 1.0)
     return x, v, f, red, prof_mean
+
+
+# ------------------------------------------------- trajectory adjoint ----
+
+def trajectory(sys_, x0, v0, steps: int, *, a=None, gamma=None, use_cells: bool = True):
+    """States (x_k, v_k, F_k) for k = 0..steps, in the caller's (tag) order.
+
+    F_0 = F(x0, v0, 0); each later state is one velocity-Verlet step
+    (Eq (1), Algorithm 1's integration phases) with forces at step k.
+    """
+    s = _with_tables(sys_, a, gamma)
+    tag, typ = sys_.tag, sys_.type
+    f0, _, _ = forces(s, x0, v0, tag, typ, 0, mode="cells" if use_cells else "brute")
+    out = [(np.array(x0, dtype=np.float64), np.array(v0, dtype=np.float64), f0)]
+    x, v, f = out[0]
+    for k in range(1, steps + 1):
+        x, v, f, _ = step(s, x, v, f, tag, typ, k, use_cells=use_cells)
+        out.append((x, v, f))
+    return out
+
+
+def _with_tables(sys_, a, gamma):
+    import copy
+    s = copy.copy(sys_)
+    if a is not None:
+        s.a = np.asarray(a, dtype=np.float64)
+    if gamma is not None:
+        s.gamma = np.asarray(gamma, dtype=np.float64)
+    return s
+
+
+def force_matching_grad(sys_, x0, v0, steps: int, targets, *, a=None, gamma=None, use_cells: bool = True):
+    """Loss L = sum_{k=1..steps} |F_k - T_k|^2 and its gradient with respect
+    to (a, gamma, x0, v0), pair Gaussian and pair sets held fixed.
+
+    Reverse of each step (c = dt/2, lambda = 1/2, v~ = v_h):
+      Fb_k += 2 (F_k - T_k);  Fb_k += c vb_k;
+      (xPhi, vPhi, aPhi, gPhi) = VJP of F at (x_k, v_h,k, step k) with Fb_k;
+      xt = xb_k + xPhi;  vh = vb_k + vPhi + dt xt;
+      xb_{k-1} = xt;  vb_{k-1} = vh;  Fb_{k-1} = c vh.
+    Finally the VJP of F_0 = F(x0, v0, 0) with Fb_0.  Returns
+    (L, abar, gammabar, xbar0, vbar0).
+    """
+    s = _with_tables(sys_, a, gamma)
+    tag, typ = sys_.tag, sys_.type
+    traj = trajectory(sys_, x0, v0, steps, a=a, gamma=gamma, use_cells=use_cells)
+    T = np.asarray(targets, dtype=np.float64)
+    loss = sum(float(np.sum((traj[k][2] - T[k - 1]) ** 2)) for k in range(1, steps + 1))
+    c = 0.5 * s.dt
+    nt = int(s.n_types)
+    gx = np.zeros_like(traj[0][0]); gv = np.zeros_like(gx); gf = np.zeros_like(gx)
+    ga = np.zeros((nt, nt)); gg = np.zeros((nt, nt))
+    mode = "cells" if use_cells else "brute"
+    for k in range(steps, 0, -1):
+        xk, vk, fk = traj[k]
+        _, vprev, fprev = traj[k - 1]
+        gf = gf + 2.0 * (fk - T[k - 1])
+        gf_eff = gf + c * gv
+        vh = vprev + c * fprev                      # the velocity F_k was evaluated with
+        xb, vb, ab, gb = forces_vjp(s, xk, vh, tag, typ, k, gf_eff, mode=mode)
+        xt = gx + xb
+        vh_bar = gv + vb + s.dt * xt
+        gx, gv, gf = xt, vh_bar, c * vh_bar
+        ga += ab; gg += gb
+    xb, vb, ab, gb = forces_vjp(s, traj[0][0], traj[0][1], tag, typ, 0, gf, mode=mode)
+    return loss, ga + ab, gg + gb, gx + xb, gv + vb

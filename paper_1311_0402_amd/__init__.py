@@ -5,11 +5,11 @@ the ctypes declarations (``_abi``) and the torch binding (``dpd``).  Every
 numerical step runs in libdpd.so; importing the binding raises if the
 library was not built.
 """
-from .dpd import (FP64, MIXED, Cells, NList, Params, State, System, alloc_workspace, cell_grid,
+from .dpd import (FP64, MIXED, Batch, Cells, NList, Params, State, System, Tiles, alloc_workspace, cell_grid,
                   default_capacity, dpd_bin_reorder, dpd_build_neighbors, dpd_forces,
-                  dpd_forces_backward, dpd_step, workspace_bytes)
+                  dpd_forces_backward, dpd_step, dpd_step_backward, workspace_bytes)
 from ._abi import DPDError
 
-__all__ = ["FP64", "MIXED", "Cells", "NList", "Params", "State", "System", "alloc_workspace",
+__all__ = ["FP64", "MIXED", "Batch", "Cells", "NList", "Params", "State", "System", "Tiles", "alloc_workspace",
            "cell_grid", "default_capacity", "dpd_bin_reorder", "dpd_build_neighbors", "dpd_forces",
-           "dpd_forces_backward", "dpd_step", "workspace_bytes", "DPDError"]
+           "dpd_forces_backward", "dpd_step", "dpd_step_backward", "workspace_bytes", "DPDError"]

@@ -77,7 +77,16 @@ class dpd_nlist(C.Structure):
     ]
 
 
+class dpd_tiles(C.Structure):
+    _fields_ = [
+        ("force_grid", C.c_int32),
+        ("nlist_waves", C.c_int32),
+        ("reserved", C.c_int32 * 2),
+    ]
+
+
 P = C.c_void_p
+PT = C.POINTER(dpd_tiles)
 PP = C.POINTER(dpd_params)
 PS = C.POINTER(dpd_state)
 PC = C.POINTER(dpd_cells)
@@ -93,7 +102,20 @@ SIGNATURES = {
     "dpd_build_neighbors": (C.c_int, [PP, PS, PC, P, PN, P, P, C.c_size_t, P]),
     "dpd_forces": (C.c_int, [PP, C.c_int32, PS, PC, P, P, PN, C.c_uint64, P, P, P, P, P, C.c_size_t, P]),
     "dpd_step": (C.c_int, [PP, C.c_int32, PS, C.c_int32, P, P, PC, PN, P, P, P, P, P, C.c_size_t, P]),
-    "dpd_forces_backward": (C.c_int, [PP, PS, PC, PN, C.c_uint64, P, P, P, P, P, P, C.c_size_t, P]),
+    "dpd_forces_backward": (C.c_int, [PP, PS, PC, PN, C.c_uint64, P, P, P, P, P, C.c_int32, P, C.c_size_t, P]),
+    "dpd_step_backward": (C.c_int, [PP, PS, PC, PN, C.c_uint64, P, P, P, P, P, P, P, P, P, C.c_size_t, P]),
+    "dpd_batch_table_bytes": (C.c_size_t, [C.c_int32, C.c_int64]),
+    "dpd_batch_create": (C.c_int, [PP, C.c_int32, P, P, C.c_size_t, P, C.POINTER(C.c_void_p)]),
+    "dpd_batch_destroy": (None, [P]),
+    "dpd_batch_sizes": (C.c_int, [P, P, P]),
+    "dpd_batch_workspace_bytes": (C.c_size_t, [P, C.c_int32]),
+    "dpd_batch_set_tiles": (C.c_int, [P, PT]),
+    "dpd_batch_get_tiles": (C.c_int, [P, PT]),
+    "dpd_batch_bin_reorder": (C.c_int, [P, PS, PS, PC, P, P, P, C.c_size_t, P]),
+    "dpd_batch_build_neighbors": (C.c_int, [P, PS, PC, P, PN, P, P, C.c_size_t, P]),
+    "dpd_batch_forces": (C.c_int, [P, C.c_int32, PS, PC, P, P, PN, C.c_uint64, P, P, P, P, C.c_size_t, P]),
+    "dpd_batch_step": (C.c_int, [P, C.c_int32, PS, C.c_int32, P, P, PC, PN, P, P, P, C.c_int32, P, C.c_size_t,
+                                 P]),
 }
 
 _lib = None

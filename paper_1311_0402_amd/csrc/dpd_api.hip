@@ -7,7 +7,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <string>
+#include <vector>
 
 #include "../../include/dpd.h"
 #include "dpd_launch.h"
@@ -170,11 +172,38 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 }  // namespace
 
-WsLayout ws_layout(int32_t n, int32_t n_cells, bool need_vt, int32_t n_types)
+// What one enqueue covers: a single system (bv.kps == nullptr) or a batch.
+struct Job {
+    KParams kp;          // the system (single) or the shared fields of a batch
+    BatchView bv;
+    int32_t n_cells;     // cells of all systems
+    int32_t n_blocks;    // 2x2x2 list blocks of all systems
+    int32_t slab_k;      // neighbour slab width
+    int32_t force_grid;  // persistent force workgroups (0 = default)
+    int32_t nlist_waves; // waves per list-build workgroup
+};
+
+Job single_job(const KParams& kp, int32_t n)
+{
+    Job j;
+    j.kp = kp;
+    std::memset(&j.bv, 0, sizeof(j.bv));
+    j.n_cells = kp.n_cells;
+    j.n_blocks = kp.n_blocks;
+    const double vol = kp.L[0] * kp.L[1] * kp.L[2];
+    j.slab_k = nlist_slab_width(n / vol, kp.rl2);
+    j.force_grid = 0;
+    j.nlist_waves = 4;
+    return j;
+}
+
+WsLayout ws_layout(const Job& job, int32_t n)
 {
     WsLayout w;
     size_t o = 0;
     const size_t N = (size_t)(n > 0 ? n : 1);
+    const bool need_vt = !job.kp.lam_half;
+    const int32_t n_cells = job.n_cells;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
     w.bx = take(3 * N * sizeof(double));
     w.bv = take(3 * N * sizeof(double));
@@ -190,17 +219,26 @@ WsLayout ws_layout(int32_t n, int32_t n_cells, bool need_vt, int32_t n_types)
     const int64_t scan_items = (int64_t)(n > n_cells ? n : n_cells) + 1;
     w.scan_part = take((size_t)ceil_div(scan_items, kScanTile) * sizeof(int32_t) + 64);
     w.rank_tab = take((size_t)(n_cells > 0 ? n_cells : 1) * sizeof(int32_t));
+    w.slab_k = job.slab_k;
+    w.slab = take(N * (size_t)w.slab_k * sizeof(int32_t));
+    w.slab_flag = take(sizeof(int32_t));
     w.red_part = take((size_t)3 * kRedBlocks * 2 * sizeof(double));
-    w.fred_part = take((size_t)force_blocks(n) * 2 * sizeof(double));
-    w.bwd_part = take((size_t)backward_part_doubles(n, n_types) * sizeof(double));
+    w.fred_part = take((size_t)kMaxForceGrid * 2 * sizeof(double));
+    w.fsum_part = take((size_t)kRedBlocks * 2 * sizeof(double));
+    w.bwd_part = take((size_t)backward_part_doubles(n, job.kp.n_types) * sizeof(double));
+    // per-particle potential energy and pair counts (per-system statistics of a batch)
+    w.pe_part = take(N * sizeof(double));
+    w.np_part = take(N * sizeof(int32_t));
     w.total = o;
     return w;
 }
 
+WsLayout ws_layout(const KParams& kp, int32_t n) { return ws_layout(single_job(kp, n), n); }
+
 namespace {
 
 // binning + reordering from `in` into `out` (shared by dpd_bin_reorder and dpd_step)
-int enqueue_reorder(const KParams& kp, const WsLayout& L, void* ws, const dpd_state* in,
+int enqueue_reorder(const Job& job, const WsLayout& L, void* ws, const dpd_state* in,
                     const double* vt_in, dpd_state* out, double* vt_out, dpd_cells* cells,
                     float* x32, float* v32, hipStream_t s)
 {
@@ -212,32 +250,33 @@ int enqueue_reorder(const KParams& kp, const WsLayout& L, void* ws, const dpd_st
     int32_t* tmp_src = carve<int32_t>(ws, L.tmp_src);
     int32_t* part = carve<int32_t>(ws, L.scan_part);
     const int32_t* rank_tab = carve<int32_t>(ws, L.rank_tab);
-    DPD_TRY(launch_fill_i32(cells->cell_start, (int64_t)kp.n_cells + 1, 0, s), "fill cell counts");
-    DPD_TRY(launch_bin(kp, n, in->x, rank_tab, key, slot, cxyz, cells->cell_start, s), "bin");
-    DPD_TRY(launch_scan(cells->cell_start, (int64_t)kp.n_cells + 1, part, s), "scan cells");
+    DPD_TRY(launch_fill_i32(cells->cell_start, (int64_t)job.n_cells + 1, 0, s), "fill cell counts");
+    DPD_TRY(launch_bin(job.kp, job.bv, n, in->x, rank_tab, key, slot, cxyz, cells->cell_start, s), "bin");
+    DPD_TRY(launch_scan(cells->cell_start, (int64_t)job.n_cells + 1, part, s), "scan cells");
     DPD_TRY(launch_place(n, key, slot, cells->cell_start, in->tag, tmp_tag, tmp_src, s), "place");
     GatherArgs g;
     g.x_in = in->x; g.v_in = in->v; g.vt_in = vt_in; g.type_in = in->type; g.cxyz_in = cxyz;
     g.x_out = out->x; g.v_out = out->v; g.vt_out = vt_out; g.tag_out = out->tag; g.type_out = out->type;
     g.cell_xyz = cells->cell_xyz; g.perm = cells->perm; g.idx_of_tag = cells->idx_of_tag;
     g.x32 = x32; g.v32 = v32;
-    DPD_TRY(launch_finalize(kp, n, key, cells->cell_start, tmp_tag, tmp_src, g, s), "finalize");
+    DPD_TRY(launch_finalize(job.kp, job.bv, n, key, cells->cell_start, tmp_tag, tmp_src, g, s), "finalize");
     return DPD_OK;
 }
 
-int enqueue_nlist(const KParams& kp, const WsLayout& L, void* ws, const dpd_state* st,
+int enqueue_nlist(const Job& job, const WsLayout& L, void* ws, const dpd_state* st,
                   const dpd_cells* cells, const float* x32, dpd_nlist* nl, int32_t* d_status, hipStream_t s)
 {
-    const int32_t n = st->n;
-    int32_t* part = carve<int32_t>(ws, L.scan_part);
-    const int32_t* rank_tab = carve<int32_t>(ws, L.rank_tab);
-    DPD_TRY(launch_fill_i32(nl->offset + n, 1, 0, s), "clear offset tail");
-    DPD_TRY(launch_nlist_count(kp, n, st->x, x32, cells->cell_xyz, cells->cell_start, rank_tab, nl->offset, s),
-            "nlist count");
-    DPD_TRY(launch_scan(nl->offset, (int64_t)n + 1, part, s), "scan rows");
-    DPD_TRY(launch_nlist_check(n, nl->offset, nl->capacity, d_status, s), "nlist check");
-    DPD_TRY(launch_nlist_fill(kp, n, st->x, x32, cells->cell_xyz, cells->cell_start, rank_tab, nl->offset,
-                              nl->index, nl->capacity, s), "nlist fill");
+    DPD_TRY(launch_nlist(job.kp, job.bv, job.n_blocks, st->n, st->x, x32, cells->cell_start,
+                         carve<int32_t>(ws, L.rank_tab), nl->offset, nl->index, nl->capacity,
+                         carve<int32_t>(ws, L.slab), L.slab_k, carve<int32_t>(ws, L.slab_flag), d_status,
+                         carve<int32_t>(ws, L.scan_part), job.nlist_waves, s),
+            "neighbour list");
+    return DPD_OK;
+}
+
+int enqueue_rank_table(const Job& job, const WsLayout& L, void* ws, hipStream_t s)
+{
+    DPD_TRY(launch_rank_table(job.kp, job.bv, job.n_cells, carve<int32_t>(ws, L.rank_tab), s), "rank table");
     return DPD_OK;
 }
 
@@ -257,6 +296,124 @@ int check_nlist(const dpd_nlist* nl, int32_t n)
     if (nl->capacity < 0 || nl->capacity >= ((int64_t)1 << 31))
         return fail(DPD_EINVAL, "nlist capacity must be in [0, 2^31)");
     if (n > 0 && nl->capacity > 0 && !nl->index) return fail(DPD_EINVAL, "nlist->index is NULL");
+    return DPD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched replicas
+// ---------------------------------------------------------------------------
+
+// Device table of a batch (caller memory): per-system KParams, the particle /
+// cell / block offsets, the particle -> system map and a step-counter
+// snapshot that numbers the rows of the per-step statistics.
+struct BatchTable {
+    size_t kps, p_off, c_off, b_off, sys_of, step_base, total;
+};
+
+BatchTable batch_table(int32_t n_sys, int64_t n_total)
+{
+    BatchTable t;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+    const size_t ns = (size_t)n_sys;
+    t.kps = take(ns * sizeof(KParams));
+    t.p_off = take((ns + 1) * sizeof(int32_t));
+    t.c_off = take((ns + 1) * sizeof(int32_t));
+    t.b_off = take((ns + 1) * sizeof(int32_t));
+    t.sys_of = take((size_t)(n_total > 0 ? n_total : 1) * sizeof(uint16_t));
+    t.step_base = take(sizeof(uint64_t));
+    t.total = o;
+    return t;
+}
+
+// Arguments a captured step depends on; a change means capturing again.
+struct GraphKey {
+    int32_t precision;
+    int32_t force_grid, nlist_waves;
+    dpd_state st;
+    dpd_cells cells;
+    dpd_nlist nl;
+    const void *d_step, *red, *x32, *v32, *d_status, *ws;
+    size_t ws_bytes;
+};
+
+}  // namespace
+}  // namespace dpd
+
+struct dpd_batch {
+    int32_t n_sys = 0;
+    int64_t n_total = 0;
+    dpd::Job job;                      // shared KParams (system 0) + BatchView + totals + tiles
+    std::vector<dpd::KParams> kps;     // host copies (the device table is filled from these)
+    std::vector<int32_t> p_off, c_off, b_off;
+    uint64_t* step_base = nullptr;     // device
+    hipGraphExec_t exec = nullptr;     // cached one-step graph
+    hipStream_t capture = nullptr;     // stream the graph is captured on
+    dpd::GraphKey key;
+    bool have_key = false;
+};
+
+namespace dpd {
+namespace {
+
+void drop_graph(dpd_batch* b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+    b->have_key = false;
+}
+
+int check_batch_state(const dpd_batch* b, const dpd_state* st, const char* name, bool need_f)
+{
+    const int rc = check_state(st, name, need_f);
+    if (rc) return rc;
+    if ((int64_t)st->n != b->n_total)
+        return fail(DPD_EINVAL, "%s->n = %d but the batch holds %lld particles", name, st->n,
+                    (long long)b->n_total);
+    return DPD_OK;
+}
+
+// one batched step: integrate, reorder, list, forces, integrate, statistics
+int enqueue_batch_step(const dpd_batch* bt, const WsLayout& L, void* ws, int32_t precision, dpd_state* st,
+                       uint64_t* d_step, double* red, dpd_cells* cells, dpd_nlist* nl, float* x32, float* v32,
+                       int32_t* d_status, hipStream_t s)
+{
+    const Job& job = bt->job;
+    const KParams& kp = job.kp;
+    const int32_t n = st->n;
+    dpd_state b;                                    // drifted, not yet reordered
+    b.n = n;
+    b.x = carve<double>(ws, L.bx);
+    b.v = carve<double>(ws, L.bv);
+    b.f = nullptr;
+    b.tag = carve<uint32_t>(ws, L.btag);
+    b.type = carve<uint8_t>(ws, L.btype);
+    double* bvt = kp.lam_half ? nullptr : carve<double>(ws, L.bvt);
+    double* vt_sorted = kp.lam_half ? nullptr : carve<double>(ws, L.vt_sorted);
+    const bool mixed = precision == DPD_MIXED;
+    ForceArgs a;
+    a.n = n; a.x = st->x; a.v = kp.lam_half ? st->v : vt_sorted; a.tag = st->tag; a.type = st->type;
+    a.cell_xyz = cells->cell_xyz; a.x32 = x32; a.v32 = v32;
+    a.offset = nl->offset; a.index = nl->index; a.capacity = nl->capacity;
+    a.idx_of_tag = cells->idx_of_tag;
+    a.d_step = d_step; a.step_add = 1;
+    a.f = st->f;
+    a.pe = carve<double>(ws, L.pe_part);
+    a.npair = carve<int32_t>(ws, L.np_part);
+    a.fred_part = nullptr;
+    a.status = d_status;
+    a.grid = job.force_grid;
+    int rc;
+    DPD_TRY(launch_vv1(kp, job.bv, n, st->x, st->v, st->f, st->tag, st->type, b.x, b.v, bvt, b.tag, b.type, s),
+            "vv1");
+    if ((rc = enqueue_reorder(job, L, ws, &b, bvt, st, vt_sorted, cells, x32, mixed ? v32 : nullptr, s))) return rc;
+    if ((rc = enqueue_nlist(job, L, ws, st, cells, x32, nl, d_status, s))) return rc;
+    DPD_TRY(launch_forces(kp, job.bv, precision, a, s), "forces");
+    DPD_TRY(launch_vv2(kp, n, st->v, st->f, carve<double>(ws, L.red_part), nullptr, 0,
+                       carve<double>(ws, L.fsum_part), s), "vv2");
+    DPD_TRY(launch_sys_reduce(job.bv, n, st->v, a.pe, a.npair, red, d_step, bt->step_base, d_status, s),
+            "system statistics");
+    DPD_TRY(launch_counter(d_step, nullptr, s), "step counter");
     return DPD_OK;
 }
 
@@ -285,7 +442,7 @@ size_t dpd_workspace_bytes(const dpd_params* p, int32_t n, int32_t precision)
 {
     KParams k;
     if (n < 0 || (precision != DPD_FP64 && precision != DPD_MIXED) || make_kparams(p, &k) != DPD_OK) return 0;
-    return ws_layout(n, k.n_cells, !k.lam_half, k.n_types).total;
+    return ws_layout(k, n).total;
 }
 
 int dpd_bin_reorder(const dpd_params* p, const dpd_state* in, dpd_state* out, dpd_cells* cells,
@@ -299,10 +456,11 @@ int dpd_bin_reorder(const dpd_params* p, const dpd_state* in, dpd_state* out, dp
     if (in->n > 0 && (in->x == out->x || in->v == out->v || in->tag == out->tag || in->type == out->type))
         return fail(DPD_EINVAL, "in and out must not overlap");
     if ((rc = check_cells(cells, in->n, false))) return rc;
-    const WsLayout L = ws_layout(in->n, kp.n_cells, !kp.lam_half, kp.n_types);
+    const Job job = single_job(kp, in->n);
+    const WsLayout L = ws_layout(job, in->n);
     if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
-    DPD_TRY(launch_rank_table(kp, carve<int32_t>(ws, L.rank_tab), as_stream(stream)), "rank table");
-    return enqueue_reorder(kp, L, ws, in, nullptr, out, nullptr, cells, x32, v32, as_stream(stream));
+    if ((rc = enqueue_rank_table(job, L, ws, as_stream(stream)))) return rc;
+    return enqueue_reorder(job, L, ws, in, nullptr, out, nullptr, cells, x32, v32, as_stream(stream));
 }
 
 int dpd_build_neighbors(const dpd_params* p, const dpd_state* sorted, const dpd_cells* cells,
@@ -317,10 +475,11 @@ int dpd_build_neighbors(const dpd_params* p, const dpd_state* sorted, const dpd_
     if (sorted->n > 0 && !sorted->x) return fail(DPD_EINVAL, "sorted->x is NULL");
     if ((rc = check_cells(cells, sorted->n, false)) || (rc = check_nlist(nl, sorted->n))) return rc;
     if (sorted->n > 0 && !x32) return fail(DPD_EINVAL, "x32 (from dpd_bin_reorder) is NULL");
-    const WsLayout L = ws_layout(sorted->n, kp.n_cells, !kp.lam_half, kp.n_types);
+    const Job job = single_job(kp, sorted->n);
+    const WsLayout L = ws_layout(job, sorted->n);
     if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
-    DPD_TRY(launch_rank_table(kp, carve<int32_t>(ws, L.rank_tab), as_stream(stream)), "rank table");
-    return enqueue_nlist(kp, L, ws, sorted, cells, x32, nl, d_status, as_stream(stream));
+    if ((rc = enqueue_rank_table(job, L, ws, as_stream(stream)))) return rc;
+    return enqueue_nlist(job, L, ws, sorted, cells, x32, nl, d_status, as_stream(stream));
 }
 
 int dpd_forces(const dpd_params* p, int32_t precision, const dpd_state* sorted, const dpd_cells* cells,
@@ -336,12 +495,12 @@ int dpd_forces(const dpd_params* p, int32_t precision, const dpd_state* sorted, 
     if ((rc = check_nlist(nl, n))) return rc;
     if (n > 0 && !f_out) return fail(DPD_EINVAL, "f_out is NULL");
     const bool bonds = kp.partner != nullptr;
-    if (bonds || precision == DPD_MIXED) {
-        if ((rc = check_cells(cells, n, bonds))) return rc;
-    }
+    if (bonds && (rc = check_cells(cells, n, true))) return rc;
     if (precision == DPD_MIXED && n > 0 && (!x32 || !v32))
         return fail(DPD_EINVAL, "mixed precision needs x32 and v32");
-    const WsLayout L = ws_layout(n, kp.n_cells, !kp.lam_half, kp.n_types);
+    if (precision == DPD_MIXED && n > 0 && (!aligned(x32, 16) || !aligned(v32, 16)))
+        return fail(DPD_EINVAL, "x32 / v32 must be 16-byte aligned");
+    const WsLayout L = ws_layout(kp, n);
     if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
     const hipStream_t s = as_stream(stream);
     ForceArgs a;
@@ -351,11 +510,14 @@ int dpd_forces(const dpd_params* p, int32_t precision, const dpd_state* sorted, 
     a.idx_of_tag = cells ? cells->idx_of_tag : nullptr;
     a.d_step = nullptr; a.step_add = step;
     a.f = f_out; a.pe = pe_out;
+    a.npair = nullptr;
     a.fred_part = stats ? carve<double>(ws, L.fred_part) : nullptr;
     a.status = d_status;
-    DPD_TRY(launch_forces(kp, precision, a, s), "forces");
+    a.grid = 0;
+    const BatchView none{};
+    DPD_TRY(launch_forces(kp, none, precision, a, s), "forces");
     if (stats)
-        DPD_TRY(launch_reduce_final(n, nullptr, 0, a.fred_part, force_blocks(n), nullptr, stats, nullptr,
+        DPD_TRY(launch_reduce_final(n, nullptr, 0, a.fred_part, force_grid(a), nullptr, stats, nullptr,
                                     d_status, s), "force stats");
     return DPD_OK;
 }
@@ -376,11 +538,12 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
     if ((rc = check_cells(cells, n, bonds)) || (rc = check_nlist(nl, n))) return rc;
     if (n > 0 && !x32) return fail(DPD_EINVAL, "x32 is NULL (the list build needs it)");
     if (precision == DPD_MIXED && n > 0 && !v32) return fail(DPD_EINVAL, "mixed precision needs v32");
-    const WsLayout L = ws_layout(n, kp.n_cells, !kp.lam_half, kp.n_types);
+    const Job job = single_job(kp, n);
+    const WsLayout L = ws_layout(job, n);
     if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
     if (n == 0 || n_steps == 0) return DPD_OK;
     const hipStream_t s = as_stream(stream);
-    DPD_TRY(launch_rank_table(kp, carve<int32_t>(ws, L.rank_tab), s), "rank table");
+    if ((rc = enqueue_rank_table(job, L, ws, s))) return rc;
 
     dpd_state b;                                    // drifted, not yet reordered
     b.n = n;
@@ -398,10 +561,12 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
     a.offset = nl->offset; a.index = nl->index; a.capacity = nl->capacity;
     a.idx_of_tag = cells->idx_of_tag;
     a.d_step = d_step; a.step_add = 1;
-    a.f = st->f; a.pe = nullptr;
+    a.f = st->f; a.pe = nullptr; a.npair = nullptr;
     a.fred_part = carve<double>(ws, L.fred_part);
     a.status = d_status;
+    a.grid = 0;
     double* red_part = carve<double>(ws, L.red_part);
+    double* fsum_part = carve<double>(ws, L.fsum_part);
     const bool mixed = precision == DPD_MIXED;
 
     auto mark = [&](int32_t k, int phase) -> hipError_t {
@@ -410,18 +575,18 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
     };
     for (int32_t k = 0; k < n_steps; ++k) {
         DPD_TRY(mark(k, 0), "event");
-        DPD_TRY(launch_vv1(kp, n, st->x, st->v, st->f, st->tag, st->type, b.x, b.v, bvt, b.tag, b.type, s), "vv1");
+        DPD_TRY(launch_vv1(kp, job.bv, n, st->x, st->v, st->f, st->tag, st->type, b.x, b.v, bvt, b.tag, b.type, s), "vv1");
         DPD_TRY(mark(k, 1), "event");
-        rc = enqueue_reorder(kp, L, ws, &b, bvt, st, vt_sorted, cells, x32, mixed ? v32 : nullptr, s);
+        rc = enqueue_reorder(job, L, ws, &b, bvt, st, vt_sorted, cells, x32, mixed ? v32 : nullptr, s);
         if (rc) return rc;
         DPD_TRY(mark(k, 2), "event");
-        rc = enqueue_nlist(kp, L, ws, st, cells, x32, nl, d_status, s);
+        rc = enqueue_nlist(job, L, ws, st, cells, x32, nl, d_status, s);
         if (rc) return rc;
         DPD_TRY(mark(k, 3), "event");
-        DPD_TRY(launch_forces(kp, precision, a, s), "forces");
+        DPD_TRY(launch_forces(kp, job.bv, precision, a, s), "forces");
         DPD_TRY(mark(k, 4), "event");
-        DPD_TRY(launch_vv2(kp, n, st->v, st->f, red_part, s), "vv2");
-        DPD_TRY(launch_reduce_final(n, red_part, kRedBlocks, a.fred_part, force_blocks(n),
+        DPD_TRY(launch_vv2(kp, n, st->v, st->f, red_part, a.fred_part, force_grid(a), fsum_part, s), "vv2");
+        DPD_TRY(launch_reduce_final(n, red_part, kRedBlocks, fsum_part, kRedBlocks,
                                     d_reductions ? d_reductions + 8 * (int64_t)k : nullptr, nullptr, d_step,
                                     d_status, s), "reduce");
         DPD_TRY(mark(k, 5), "event");
@@ -431,8 +596,8 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
 
 int dpd_forces_backward(const dpd_params* p, const dpd_state* sorted, const dpd_cells* cells,
                         const dpd_nlist* nl, uint64_t step, const double* grad_f, double* grad_x,
-                        double* grad_v, double* grad_a, double* grad_gamma, void* ws, size_t ws_bytes,
-                        void* stream)
+                        double* grad_v, double* grad_a, double* grad_gamma, int32_t accumulate, void* ws,
+                        size_t ws_bytes, void* stream)
 {
     KParams kp;
     int rc = make_kparams(p, &kp);
@@ -444,7 +609,7 @@ int dpd_forces_backward(const dpd_params* p, const dpd_state* sorted, const dpd_
     if (bonds && (rc = check_cells(cells, n, true))) return rc;
     if (!grad_a || !grad_gamma) return fail(DPD_EINVAL, "grad_a / grad_gamma are NULL");
     if (n > 0 && (!grad_f || !grad_x || !grad_v)) return fail(DPD_EINVAL, "gradient arrays are NULL");
-    const WsLayout L = ws_layout(n, kp.n_cells, !kp.lam_half, kp.n_types);
+    const WsLayout L = ws_layout(kp, n);
     if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
     BackwardArgs a;
     a.n = n; a.x = sorted->x; a.v = sorted->v; a.tag = sorted->tag; a.type = sorted->type;
@@ -453,7 +618,317 @@ int dpd_forces_backward(const dpd_params* p, const dpd_state* sorted, const dpd_
     a.step = step; a.g = grad_f; a.xbar = grad_x; a.vbar = grad_v;
     a.part = carve<double>(ws, L.bwd_part);
     a.abar = grad_a; a.gbar = grad_gamma;
+    a.acc_xv = accumulate ? 1 : 0;
+    a.acc_params = accumulate ? 1 : 0;
     DPD_TRY(launch_forces_backward(kp, a, as_stream(stream)), "forces backward");
+    return DPD_OK;
+}
+
+int dpd_step_backward(const dpd_params* p, const dpd_state* st, const dpd_cells* cells, const dpd_nlist* nl,
+                      uint64_t step, const double* gx_in, const double* gv_in, const double* gf_in,
+                      double* gx_out, double* gv_out, double* gf_out, double* grad_a, double* grad_gamma,
+                      void* ws, size_t ws_bytes, void* stream)
+{
+    KParams kp;
+    int rc = make_kparams(p, &kp);
+    if (rc) return rc;
+    if (!kp.lam_half) return fail(DPD_EUNSUPPORTED, "the step adjoint is implemented for lambda = 1/2");
+    if ((rc = check_state(st, "state", true))) return rc;
+    const int32_t n = st->n;
+    if ((rc = check_nlist(nl, n)) || (rc = check_cells(cells, n, kp.partner != nullptr))) return rc;
+    if (!grad_a || !grad_gamma) return fail(DPD_EINVAL, "grad_a / grad_gamma are NULL");
+    if (n > 0 && (!gx_in || !gv_in || !gf_in || !gx_out || !gv_out || !gf_out))
+        return fail(DPD_EINVAL, "adjoint arrays are NULL");
+    if (n > 0 && (gx_out == gx_in || gv_out == gv_in || gf_out == gf_in))
+        return fail(DPD_EINVAL, "adjoint outputs must not alias the inputs");
+    const WsLayout L = ws_layout(kp, n);
+    if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+    StepBackwardArgs b;
+    BackwardArgs& a = b.fwd;
+    a.n = n; a.x = st->x; a.v = nullptr; a.tag = st->tag; a.type = st->type;
+    a.offset = nl->offset; a.index = nl->index; a.capacity = nl->capacity;
+    a.idx_of_tag = cells->idx_of_tag;
+    a.step = step; a.g = nullptr; a.xbar = nullptr; a.vbar = nullptr;
+    a.part = carve<double>(ws, L.bwd_part);
+    a.abar = grad_a; a.gbar = grad_gamma;
+    a.acc_xv = 0; a.acc_params = 1;
+    b.v_new = st->v; b.f_new = st->f; b.perm = cells->perm;
+    b.gx_in = gx_in; b.gv_in = gv_in; b.gf_in = gf_in;
+    b.gx_out = gx_out; b.gv_out = gv_out; b.gf_out = gf_out;
+    // scratch: the pre-reorder buffers and the list slab are free here
+    double* slab = carve<double>(ws, L.slab);
+    b.vt = carve<double>(ws, L.bx);
+    b.gf_eff = carve<double>(ws, L.bv);
+    b.xphi = slab;
+    b.vphi = slab + 3 * (size_t)(n > 0 ? n : 1);
+    DPD_TRY(launch_step_backward(kp, b, as_stream(stream)), "step backward");
+    return DPD_OK;
+}
+
+size_t dpd_batch_table_bytes(int32_t n_sys, int64_t n_total)
+{
+    if (n_sys < 1 || n_sys > 65535 || n_total < n_sys || n_total >= ((int64_t)1 << 31)) return 0;
+    return batch_table(n_sys, n_total).total;
+}
+
+int dpd_batch_create(const dpd_params* per_sys, int32_t n_sys, const int64_t* sys_offset, void* d_table,
+                     size_t table_bytes, void* stream, dpd_batch** out)
+{
+    if (!out) return fail(DPD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!per_sys || !sys_offset) return fail(DPD_EINVAL, "per_sys / sys_offset is NULL");
+    if (n_sys < 1 || n_sys > 65535) return fail(DPD_EINVAL, "n_sys must be in [1, 65535]");
+    if (sys_offset[0] != 0) return fail(DPD_EINVAL, "sys_offset[0] must be 0");
+    for (int32_t q = 0; q < n_sys; ++q)
+        if (!(sys_offset[q + 1] > sys_offset[q]))
+            return fail(DPD_EINVAL, "system %d is empty (sys_offset must increase strictly)", q);
+    const int64_t n_total = sys_offset[n_sys];
+    if (n_total >= ((int64_t)1 << 31)) return fail(DPD_EINVAL, "more than 2^31 - 1 particles");
+    const BatchTable T = batch_table(n_sys, n_total);
+    if (!d_table) return fail(DPD_EINVAL, "d_table is NULL");
+    if (!aligned(d_table, 256)) return fail(DPD_EINVAL, "d_table must be 256-byte aligned");
+    if (table_bytes < T.total) return fail(DPD_ECAPACITY, "d_table has %zu bytes, needs %zu", table_bytes, T.total);
+
+    std::unique_ptr<dpd_batch> b(new dpd_batch());
+    b->n_sys = n_sys;
+    b->n_total = n_total;
+    b->kps.resize(n_sys);
+    b->p_off.resize(n_sys + 1);
+    b->c_off.resize(n_sys + 1);
+    b->b_off.resize(n_sys + 1);
+    const dpd_params& p0 = per_sys[0];
+    int64_t c_tot = 0, b_tot = 0;
+    int32_t slab_k = 0;
+    for (int32_t q = 0; q < n_sys; ++q) {
+        const dpd_params& p = per_sys[q];
+        if (p.bond_partner) return fail(DPD_EUNSUPPORTED, "system %d: bonds are not supported in a batch", q);
+        if (p.r_c != p0.r_c || p.skin != p0.skin || p.dt != p0.dt || p.lambda != p0.lambda || p.s != p0.s ||
+            p.n_types != p0.n_types)
+            return fail(DPD_EUNSUPPORTED, "system %d differs from system 0 in r_c, skin, dt, lambda, s or n_types", q);
+        KParams& k = b->kps[q];
+        const int rc = make_kparams(&p, &k);
+        if (rc) {
+            const std::string why = g_error;
+            return fail(rc, "system %d: %s", q, why.c_str());
+        }
+        const int32_t ns = (int32_t)(sys_offset[q + 1] - sys_offset[q]);
+        k.p_off = (int32_t)sys_offset[q];
+        k.c_off = (int32_t)c_tot;
+        k.b_off = (int32_t)b_tot;
+        k.n_local = ns;
+        b->p_off[q] = k.p_off;
+        b->c_off[q] = k.c_off;
+        b->b_off[q] = k.b_off;
+        c_tot += k.n_cells;
+        b_tot += k.n_blocks;
+        if (c_tot >= ((int64_t)1 << 31) - 1 || b_tot >= ((int64_t)1 << 31)) return fail(DPD_EINVAL, "too many cells");
+        const double vol = k.L[0] * k.L[1] * k.L[2];
+        const int32_t w = nlist_slab_width(ns / vol, k.rl2);
+        slab_k = w > slab_k ? w : slab_k;
+    }
+    b->p_off[n_sys] = (int32_t)n_total;
+    b->c_off[n_sys] = (int32_t)c_tot;
+    b->b_off[n_sys] = (int32_t)b_tot;
+
+    Job& job = b->job;
+    job.kp = b->kps[0];
+    job.kp.p_off = job.kp.c_off = job.kp.b_off = 0;
+    job.kp.n_local = 0;
+    job.bv.kps = carve<KParams>(d_table, T.kps);
+    job.bv.p_off = carve<int32_t>(d_table, T.p_off);
+    job.bv.c_off = carve<int32_t>(d_table, T.c_off);
+    job.bv.b_off = carve<int32_t>(d_table, T.b_off);
+    job.bv.sys_of = carve<uint16_t>(d_table, T.sys_of);
+    job.bv.n_sys = n_sys;
+    job.n_cells = (int32_t)c_tot;
+    job.n_blocks = (int32_t)b_tot;
+    job.slab_k = slab_k;
+    job.force_grid = 0;
+    job.nlist_waves = 4;
+    b->step_base = carve<uint64_t>(d_table, T.step_base);
+
+    const hipStream_t s = as_stream(stream);
+    DPD_TRY(hipMemcpyAsync(carve<void>(d_table, T.kps), b->kps.data(), n_sys * sizeof(KParams),
+                           hipMemcpyHostToDevice, s), "copy batch table");
+    DPD_TRY(hipMemcpyAsync(carve<void>(d_table, T.p_off), b->p_off.data(), (n_sys + 1) * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s), "copy batch table");
+    DPD_TRY(hipMemcpyAsync(carve<void>(d_table, T.c_off), b->c_off.data(), (n_sys + 1) * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s), "copy batch table");
+    DPD_TRY(hipMemcpyAsync(carve<void>(d_table, T.b_off), b->b_off.data(), (n_sys + 1) * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s), "copy batch table");
+    DPD_TRY(launch_sys_map(job.bv, (int32_t)n_total, carve<uint16_t>(d_table, T.sys_of), s), "system map");
+    // the host vectors feed asynchronous copies: they must not move before
+    // the copies have run, so the caller's stream is drained here
+    DPD_TRY(hipStreamSynchronize(s), "batch setup");
+    *out = b.release();
+    return DPD_OK;
+}
+
+void dpd_batch_destroy(dpd_batch* b)
+{
+    if (!b) return;
+    drop_graph(b);
+    if (b->capture) (void)hipStreamDestroy(b->capture);
+    delete b;
+}
+
+int dpd_batch_sizes(const dpd_batch* b, int64_t* n_total, int64_t* n_cells_total)
+{
+    if (!b) return fail(DPD_EINVAL, "batch is NULL");
+    if (n_total) *n_total = b->n_total;
+    if (n_cells_total) *n_cells_total = b->job.n_cells;
+    return DPD_OK;
+}
+
+size_t dpd_batch_workspace_bytes(const dpd_batch* b, int32_t precision)
+{
+    if (!b || (precision != DPD_FP64 && precision != DPD_MIXED)) return 0;
+    return ws_layout(b->job, (int32_t)b->n_total).total;
+}
+
+int dpd_batch_set_tiles(dpd_batch* b, const dpd_tiles* t)
+{
+    if (!b || !t) return fail(DPD_EINVAL, "NULL argument");
+    if (t->force_grid != 0 && (t->force_grid < 64 || t->force_grid > kMaxForceGrid))
+        return fail(DPD_EINVAL, "force_grid must be 0 or in [64, %d]", kMaxForceGrid);
+    if (t->nlist_waves != 0 && t->nlist_waves != 1 && t->nlist_waves != 2 && t->nlist_waves != 4)
+        return fail(DPD_EINVAL, "nlist_waves must be 0, 1, 2 or 4");
+    if (t->reserved[0] || t->reserved[1]) return fail(DPD_EINVAL, "reserved fields must be 0");
+    const int32_t waves = t->nlist_waves ? t->nlist_waves : 4;
+    if (t->force_grid != b->job.force_grid || waves != b->job.nlist_waves) drop_graph(b);
+    b->job.force_grid = t->force_grid;
+    b->job.nlist_waves = waves;
+    return DPD_OK;
+}
+
+int dpd_batch_get_tiles(const dpd_batch* b, dpd_tiles* t)
+{
+    if (!b || !t) return fail(DPD_EINVAL, "NULL argument");
+    std::memset(t, 0, sizeof(*t));
+    t->force_grid = b->job.force_grid;
+    t->nlist_waves = b->job.nlist_waves;
+    return DPD_OK;
+}
+
+int dpd_batch_bin_reorder(const dpd_batch* b, const dpd_state* in, dpd_state* out, dpd_cells* cells,
+                          float* x32, float* v32, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!b) return fail(DPD_EINVAL, "batch is NULL");
+    int rc;
+    if ((rc = check_batch_state(b, in, "in", false)) || (rc = check_batch_state(b, out, "out", false))) return rc;
+    if (in->x == out->x || in->v == out->v || in->tag == out->tag || in->type == out->type)
+        return fail(DPD_EINVAL, "in and out must not overlap");
+    if ((rc = check_cells(cells, in->n, false))) return rc;
+    const WsLayout L = ws_layout(b->job, in->n);
+    if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+    if ((rc = enqueue_rank_table(b->job, L, ws, as_stream(stream)))) return rc;
+    return enqueue_reorder(b->job, L, ws, in, nullptr, out, nullptr, cells, x32, v32, as_stream(stream));
+}
+
+int dpd_batch_build_neighbors(const dpd_batch* b, const dpd_state* sorted, const dpd_cells* cells,
+                              const float* x32, dpd_nlist* nl, int32_t* d_status, void* ws,
+                              size_t ws_bytes, void* stream)
+{
+    if (!b) return fail(DPD_EINVAL, "batch is NULL");
+    int rc;
+    if (!sorted) return fail(DPD_EINVAL, "sorted is NULL");
+    if ((int64_t)sorted->n != b->n_total) return fail(DPD_EINVAL, "sorted->n does not match the batch");
+    if (!sorted->x) return fail(DPD_EINVAL, "sorted->x is NULL");
+    if ((rc = check_cells(cells, sorted->n, false)) || (rc = check_nlist(nl, sorted->n))) return rc;
+    if (!x32) return fail(DPD_EINVAL, "x32 (from dpd_batch_bin_reorder) is NULL");
+    const WsLayout L = ws_layout(b->job, sorted->n);
+    if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+    if ((rc = enqueue_rank_table(b->job, L, ws, as_stream(stream)))) return rc;
+    return enqueue_nlist(b->job, L, ws, sorted, cells, x32, nl, d_status, as_stream(stream));
+}
+
+int dpd_batch_forces(const dpd_batch* b, int32_t precision, const dpd_state* sorted, const dpd_cells* cells,
+                     const float* x32, const float* v32, const dpd_nlist* nl, uint64_t step,
+                     double* f_out, double* pe_out, int32_t* d_status, void* ws, size_t ws_bytes,
+                     void* stream)
+{
+    if (!b) return fail(DPD_EINVAL, "batch is NULL");
+    if (precision != DPD_FP64 && precision != DPD_MIXED) return fail(DPD_EINVAL, "unknown precision %d", precision);
+    int rc;
+    if ((rc = check_batch_state(b, sorted, "sorted", false))) return rc;
+    const int32_t n = sorted->n;
+    if ((rc = check_nlist(nl, n))) return rc;
+    if (!f_out) return fail(DPD_EINVAL, "f_out is NULL");
+    if (precision == DPD_MIXED && (!x32 || !v32)) return fail(DPD_EINVAL, "mixed precision needs x32 and v32");
+    if (precision == DPD_MIXED && (!aligned(x32, 16) || !aligned(v32, 16)))
+        return fail(DPD_EINVAL, "x32 / v32 must be 16-byte aligned");
+    const WsLayout L = ws_layout(b->job, n);
+    if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+    ForceArgs a;
+    a.n = n; a.x = sorted->x; a.v = sorted->v; a.tag = sorted->tag; a.type = sorted->type;
+    a.cell_xyz = cells ? cells->cell_xyz : nullptr; a.x32 = x32; a.v32 = v32;
+    a.offset = nl->offset; a.index = nl->index; a.capacity = nl->capacity;
+    a.idx_of_tag = cells ? cells->idx_of_tag : nullptr;
+    a.d_step = nullptr; a.step_add = step;
+    a.f = f_out; a.pe = pe_out; a.npair = nullptr; a.fred_part = nullptr;
+    a.status = d_status;
+    a.grid = b->job.force_grid;
+    DPD_TRY(launch_forces(b->job.kp, b->job.bv, precision, a, as_stream(stream)), "forces");
+    return DPD_OK;
+}
+
+int dpd_batch_step(dpd_batch* b, int32_t precision, dpd_state* st, int32_t n_steps, uint64_t* d_step,
+                   double* d_reductions, dpd_cells* cells, dpd_nlist* nl, float* x32, float* v32,
+                   int32_t* d_status, int32_t use_graph, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!b) return fail(DPD_EINVAL, "batch is NULL");
+    if (precision != DPD_FP64 && precision != DPD_MIXED) return fail(DPD_EINVAL, "unknown precision %d", precision);
+    int rc;
+    if ((rc = check_batch_state(b, st, "state", true))) return rc;
+    if (n_steps < 0) return fail(DPD_EINVAL, "n_steps must be >= 0");
+    if (!d_step) return fail(DPD_EINVAL, "d_step is NULL");
+    const int32_t n = st->n;
+    if ((rc = check_cells(cells, n, false)) || (rc = check_nlist(nl, n))) return rc;
+    if (!x32) return fail(DPD_EINVAL, "x32 is NULL (the list build needs it)");
+    if (precision == DPD_MIXED && !v32) return fail(DPD_EINVAL, "mixed precision needs v32");
+    const WsLayout L = ws_layout(b->job, n);
+    if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+    if (n_steps == 0) return DPD_OK;
+    const hipStream_t s = as_stream(stream);
+    if ((rc = enqueue_rank_table(b->job, L, ws, s))) return rc;
+    DPD_TRY(launch_counter(b->step_base, d_step, s), "step base");
+    if (!use_graph) {
+        for (int32_t k = 0; k < n_steps; ++k)
+            if ((rc = enqueue_batch_step(b, L, ws, precision, st, d_step, d_reductions, cells, nl, x32, v32,
+                                         d_status, s)))
+                return rc;
+        return DPD_OK;
+    }
+    GraphKey key;
+    std::memset(&key, 0, sizeof(key));
+    key.precision = precision;
+    key.force_grid = b->job.force_grid;
+    key.nlist_waves = b->job.nlist_waves;
+    key.st = *st; key.cells = *cells; key.nl = *nl;
+    key.d_step = d_step; key.red = d_reductions; key.x32 = x32; key.v32 = v32; key.d_status = d_status;
+    key.ws = ws; key.ws_bytes = ws_bytes;
+    if (!b->exec || !b->have_key || std::memcmp(&key, &b->key, sizeof(key)) != 0) {
+        drop_graph(b);
+        if (!b->capture) DPD_TRY(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking), "capture stream");
+        DPD_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal), "begin capture");
+        rc = enqueue_batch_step(b, L, ws, precision, st, d_step, d_reductions, cells, nl, x32, v32, d_status,
+                                b->capture);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(b->capture, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "end capture");
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) return hip_fail(ei, "instantiate graph");
+        b->exec = exec;
+        b->key = key;
+        b->have_key = true;
+    }
+    for (int32_t k = 0; k < n_steps; ++k) DPD_TRY(hipGraphLaunch(b->exec, s), "graph launch");
     return DPD_OK;
 }
 

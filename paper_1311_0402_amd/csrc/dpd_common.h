@@ -53,6 +53,8 @@ struct KParams {
     double body_g, body_split;
     double bond_k, bond_r0;
     const int32_t* partner;     // device, by tag; nullptr = no bonds
+    // position of this system inside a batch (all 0 for a single system)
+    int32_t p_off, c_off, b_off, n_local;
     // per type pair: a, gamma, sigma / sqrt(dt)
     double a[kMaxTypes * kMaxTypes];
     double g[kMaxTypes * kMaxTypes];
@@ -134,11 +136,34 @@ DPD_HD uint32_t pack_cell(int32_t cx, int32_t cy, int32_t cz)
     return (uint32_t)cx | ((uint32_t)cy << 10) | ((uint32_t)cz << 20);
 }
 
+// A batch of independent systems: one KParams per system in device memory,
+// particle / cell / list-block offsets (n_sys + 1 entries each) and the
+// static particle -> system map.  kps == nullptr means a single system.
+struct BatchView {
+    const KParams* kps;
+    const int32_t* p_off;
+    const int32_t* c_off;
+    const int32_t* b_off;
+    const uint16_t* sys_of;
+    int32_t n_sys;
+};
+
 #if defined(__HIPCC__)
 
 // ---------------------------------------------------------------------------
 // Device helpers
 // ---------------------------------------------------------------------------
+
+// largest s in [0, n_seg) with off[s] <= x (off ascending)
+__device__ __forceinline__ int32_t find_segment(const int32_t* __restrict__ off, int32_t n_seg, int32_t x)
+{
+    int32_t lo = 0, hi = n_seg;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
 
 // Workgroups are dealt to the 8 XCDs round-robin; renumber them so every
 // XCD (and its L2) works through one contiguous range of logical ids.
@@ -183,18 +208,18 @@ __device__ __forceinline__ double dist2(double dx, double dy, double dz)
 }
 
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
-// 32x32->64 multiplies and xors, key bumped by the Weyl constants.
+// 32x32->64 multiplies and xors, key bumped by the Weyl constants.  Each
+// multiply is written as one 64-bit product so it maps to a single
+// v_mad_u64_u32 (high and low word together).
 struct U4 { uint32_t x, y, z, w; };
 
 __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c.x;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
-        c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = U4{(uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0};
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -217,22 +242,22 @@ __device__ __forceinline__ double gauss64(U4 w)
     return sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
 }
 
-// Same variate in FP32.  For w0 >= 2^31, u1 is close to 1 and FP32 rounding
-// of u1 itself would dominate ln(u1); there ln(u1) = log1p(-t) with the
-// complement t = (2^32 - 1 - w0 + 1/2) 2^-32 formed in integers first, so t
-// keeps its full relative precision.
+// Same variate in FP32 with the hardware transcendentals: v_log_f32 (log2),
+// v_cos_f32 (argument in revolutions, so cos(2 pi u2) is one instruction) and
+// v_sqrt_f32.  For w0 >= 2^31, u1 is close to 1 and rounding u1 itself
+// would dominate ln(u1); there ln(u1) = ln(1 - t) with the complement
+// t = (2^32 - 1 - w0 + 1/2) 2^-32 formed in integers first: a four-term
+// series for t < 2^-7, log2(1 - t) above.
 __device__ __forceinline__ float gauss32(U4 w)
 {
-    float lnu;
-    if (w.x >= 0x80000000u) {
-        const float t = ((float)(0xFFFFFFFFu - w.x) + 0.5f) * 0x1p-32f;
-        lnu = log1pf(-t);
-    } else {
-        const float u1 = ((float)w.x + 0.5f) * 0x1p-32f;
-        lnu = __logf(u1);
-    }
+    constexpr float kLn2 = 0.693147180559945309f;
+    const float u1 = ((float)w.x + 0.5f) * 0x1p-32f;
+    const float t = ((float)(0xFFFFFFFFu - w.x) + 0.5f) * 0x1p-32f;
+    const float series = -t * (1.0f + t * (0.5f + t * (0.333333333f + t * 0.25f)));
+    const float lg = __builtin_amdgcn_logf(w.x >= 0x80000000u ? 1.0f - t : u1) * kLn2;
+    const float lnu = (w.x >= 0x80000000u && t < 0x1p-7f) ? series : lg;
     const float u2 = (float)w.y * 0x1p-32f;
-    return sqrtf(-2.0f * lnu) * cospif(2.0f * u2);
+    return __builtin_amdgcn_sqrtf(-2.0f * lnu) * __builtin_amdgcn_cosf(u2);
 }
 
 #endif  // __HIPCC__

@@ -26,20 +26,28 @@ struct WsLayout {
     size_t tmp_tag, tmp_src;           // scatter before the in-cell tag order
     size_t scan_part;                  // partial sums of the device-wide scan
     size_t rank_tab;                   // Morton rank of every cell (row-major cell index)
+    size_t slab;                       // neighbour rows before compaction, K slots per particle
+    size_t slab_flag;                  // set when some row did not fit its K slots
+    int32_t slab_k;
     size_t red_part;                   // velocity reduction partials
     size_t fred_part;                  // force-kernel partials (PE, pairs)
+    size_t fsum_part;                  // force partials folded to kRedBlocks columns
     size_t bwd_part;                   // adjoint partials (type-pair matrices)
+    size_t pe_part;                    // per-particle potential energy (batch statistics)
+    size_t np_part;                    // per-particle pair count (batch statistics)
     size_t total;
 };
 
-WsLayout ws_layout(int32_t n, int32_t n_cells, bool need_vt, int32_t n_types);
+WsLayout ws_layout(const KParams& kp, int32_t n);
 
 // ---- reorder (k_reorder.hip) ----
 hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t s);
-// rank_tab[cx + nc_x (cy + nc_y cz)] = Morton rank of the cell
-hipError_t launch_rank_table(const KParams& kp, int32_t* rank_tab, hipStream_t s);
-hipError_t launch_bin(const KParams& kp, int32_t n, const double* x, const int32_t* rank_tab, int32_t* key,
-                      int32_t* slot, uint32_t* cxyz, int32_t* counts, hipStream_t s);
+// rank_tab[c_off + cx + nc_x (cy + nc_y cz)] = c_off + Morton rank of the cell
+// (bv.kps == nullptr: one system, c_off = 0, c_tot = its cell count)
+hipError_t launch_rank_table(const KParams& kp, const BatchView& bv, int32_t c_tot, int32_t* rank_tab,
+                             hipStream_t s);
+hipError_t launch_bin(const KParams& kp, const BatchView& bv, int32_t n, const double* x, const int32_t* rank_tab,
+                      int32_t* key, int32_t* slot, uint32_t* cxyz, int32_t* counts, hipStream_t s);
 // in-place exclusive scan of data[0 .. count); partials needs ceil(count/kScanTile) ints
 hipError_t launch_scan(int32_t* data, int64_t count, int32_t* partials, hipStream_t s);
 hipError_t launch_place(int32_t n, const int32_t* key, const int32_t* slot, const int32_t* cell_start,
@@ -51,19 +59,21 @@ struct GatherArgs {
     uint32_t* cell_xyz; int32_t* perm; int32_t* idx_of_tag;
     float* x32; float* v32;
 };
-hipError_t launch_finalize(const KParams& kp, int32_t n, const int32_t* key, const int32_t* cell_start,
-                           const uint32_t* tmp_tag, const int32_t* tmp_src, const GatherArgs& g,
-                           hipStream_t s);
+hipError_t launch_finalize(const KParams& kp, const BatchView& bv, int32_t n, const int32_t* key,
+                           const int32_t* cell_start, const uint32_t* tmp_tag, const int32_t* tmp_src,
+                           const GatherArgs& g, hipStream_t s);
 
 // ---- neighbour list (k_nlist.hip) ----
-hipError_t launch_nlist_count(const KParams& kp, int32_t n, const double* x, const float* x32,
-                              const uint32_t* cell_xyz, const int32_t* cell_start, const int32_t* rank_tab,
-                              int32_t* offset, hipStream_t s);
+int32_t nlist_slab_width(double density, double rl2);
+// whole list build: row sizes + slab rows, scan, capacity check, compaction
+// (or the direct pass when a row overflowed its slab row); n_blocks counts
+// the 2x2x2 cell blocks of all systems
+hipError_t launch_nlist(const KParams& kp, const BatchView& bv, int32_t n_blocks, int32_t n, const double* x,
+                        const float* x32, const int32_t* cell_start, const int32_t* rank_tab, int32_t* offset,
+                        int32_t* index, int64_t capacity, int32_t* slab, int32_t slab_k, int32_t* flag,
+                        int32_t* status, int32_t* scan_part, int waves, hipStream_t s);
 hipError_t launch_nlist_check(int32_t n, const int32_t* offset, int64_t capacity, int32_t* status,
                               hipStream_t s);
-hipError_t launch_nlist_fill(const KParams& kp, int32_t n, const double* x, const float* x32,
-                             const uint32_t* cell_xyz, const int32_t* cell_start, const int32_t* rank_tab,
-                             const int32_t* offset, int32_t* index, int64_t capacity, hipStream_t s);
 
 // ---- forces (k_force.hip) ----
 struct ForceArgs {
@@ -74,18 +84,35 @@ struct ForceArgs {
     const int32_t* idx_of_tag;
     const uint64_t* d_step; uint64_t step_add;   // step = (d_step ? *d_step : 0) + step_add
     double* f; double* pe;                        // pe nullable
-    double* fred_part;                            // [blocks][2]: PE, pair count
+    int32_t* npair;                               // nullable: pairs inside r_c per particle
+    double* fred_part;                            // [grid][2]: PE, pair count
     int32_t* status;                              // nullable
+    int32_t grid;                                 // persistent workgroups (0 = force_blocks(n))
 };
-hipError_t launch_forces(const KParams& kp, int precision, const ForceArgs& a, hipStream_t s);
+hipError_t launch_forces(const KParams& kp, const BatchView& bv, int precision, const ForceArgs& a,
+                         hipStream_t s);
 int force_blocks(int32_t n);
+constexpr int kMaxForceGrid = 8192;
+inline int force_grid(const ForceArgs& a) { return a.grid > 0 ? a.grid : force_blocks(a.n); }
 
 // ---- integration and reductions (k_integrate.hip) ----
-hipError_t launch_vv1(const KParams& kp, int32_t n, const double* x, const double* v, const double* f,
-                      const uint32_t* tag, const uint8_t* type, double* bx, double* bv, double* bvt,
-                      uint32_t* btag, uint8_t* btype, hipStream_t s);
+hipError_t launch_vv1(const KParams& kp, const BatchView& bat, int32_t n, const double* x, const double* v,
+                      const double* f, const uint32_t* tag, const uint8_t* type, double* bx, double* bv,
+                      double* bvt, uint32_t* btag, uint8_t* btype, hipStream_t s);
+// per-system statistics of a batch: one block per system sums v (momentum,
+// |v|^2), the per-particle PE and pair counts over its particle range and
+// writes them to row (*d_step - *base) of red[rows][n_sys][8] (red nullable)
+hipError_t launch_sys_reduce(const BatchView& bat, int32_t n, const double* v, const double* pe,
+                             const int32_t* npair, double* red, const uint64_t* d_step, const uint64_t* base,
+                             int32_t* status, hipStream_t s);
+// *dst = *src, or *dst += 1 when src is null (device step counters)
+hipError_t launch_counter(uint64_t* dst, const uint64_t* src, hipStream_t s);
+// particle -> system map of a batch
+hipError_t launch_sys_map(const BatchView& bat, int32_t n, uint16_t* sys_of, hipStream_t s);
+// phase 2 + momentum / |v|^2 partials; also folds the force partials
+// (fred_part, n_fred blocks) into fsum_part[kRedBlocks][2]
 hipError_t launch_vv2(const KParams& kp, int32_t n, double* v, const double* f, double* red_part,
-                      hipStream_t s);
+                      const double* fred_part, int32_t n_fred, double* fsum_part, hipStream_t s);
 // sums the partials in a fixed order; red (nullable) gets the 8 step totals;
 // stats (nullable) gets (PE, pairs); increments *d_step when non-null
 hipError_t launch_reduce_final(int32_t n, const double* red_part, int n_red, const double* fred_part,
@@ -103,8 +130,20 @@ struct BackwardArgs {
     double* xbar; double* vbar;
     double* part;          // [blocks][2 * n_types^2]
     double* abar; double* gbar;
+    int acc_xv;            // add into xbar / vbar instead of overwriting
+    int acc_params;        // add into abar / gbar instead of overwriting
 };
 hipError_t launch_forces_backward(const KParams& kp, const BackwardArgs& a, hipStream_t s);
+
+struct StepBackwardArgs {
+    BackwardArgs fwd;      // state of the later step (x', tags, types, list); abar / gbar accumulate
+    const double* v_new; const double* f_new;
+    const int32_t* perm;
+    const double* gx_in; const double* gv_in; const double* gf_in;
+    double* gx_out; double* gv_out; double* gf_out;
+    double* vt; double* gf_eff; double* xphi; double* vphi;   // workspace, [3][n] each
+};
+hipError_t launch_step_backward(const KParams& kp, const StepBackwardArgs& b, hipStream_t s);
 int backward_part_doubles(int32_t n, int32_t n_types);
 
 }  // namespace dpd

@@ -119,8 +119,8 @@ __global__ __launch_bounds__(kBlock) void k_force_bwd(KParams kp, BackwardArgs a
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            a.xbar[k * N + i] = xb[k];
-            a.vbar[k * N + i] = vb[k];
+            a.xbar[k * N + i] = a.acc_xv ? a.xbar[k * N + i] + xb[k] : xb[k];
+            a.vbar[k * N + i] = a.acc_xv ? a.vbar[k * N + i] + vb[k] : vb[k];
         }
     }
     // per-block partials of the type-pair matrices, row = type of i
@@ -144,7 +144,8 @@ __global__ __launch_bounds__(kBlock) void k_force_bwd(KParams kp, BackwardArgs a
 }
 
 __global__ __launch_bounds__(kBlock) void k_bwd_final(int nblocks, int nt, const double* __restrict__ part,
-                                                      double* __restrict__ abar, double* __restrict__ gbar)
+                                                      double* __restrict__ abar, double* __restrict__ gbar,
+                                                      int accumulate)
 {
     __shared__ double s[kBlock];
     __shared__ double m[2 * kMaxTypes * kMaxTypes];
@@ -166,8 +167,8 @@ __global__ __launch_bounds__(kBlock) void k_bwd_final(int nblocks, int nt, const
             for (int u = 0; u < nt; ++u) {
                 const double va = (t == u) ? m[t * nt + t] : m[t * nt + u] + m[u * nt + t];
                 const double vg = (t == u) ? m[nt * nt + t * nt + t] : m[nt * nt + t * nt + u] + m[nt * nt + u * nt + t];
-                abar[t * nt + u] = va;
-                gbar[t * nt + u] = vg;
+                abar[t * nt + u] = accumulate ? abar[t * nt + u] + va : va;
+                gbar[t * nt + u] = accumulate ? gbar[t * nt + u] + vg : vg;
             }
     }
 }
@@ -189,7 +190,75 @@ hipError_t launch_forces_backward(const KParams& kp, const BackwardArgs& a, hipS
     case 2: hipLaunchKernelGGL(k_force_bwd<2>, grid, block, 0, s, kp, a); break;
     default: hipLaunchKernelGGL(k_force_bwd<3>, grid, block, 0, s, kp, a); break;
     }
-    hipLaunchKernelGGL(k_bwd_final, dim3(1), block, 0, s, blocks, kp.n_types, a.part, a.abar, a.gbar);
+    hipLaunchKernelGGL(k_bwd_final, dim3(1), block, 0, s, blocks, kp.n_types, a.part, a.abar, a.gbar,
+                       a.acc_params);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Reverse of one velocity-Verlet step (lambda = 1/2).  Forward:
+//   v_h = v + c F,  x' = x + dt v_h (wrapped),  F' = Phi(x', v_h),
+//   v' = v_h + c F',  c = dt/2,  then the reorder x'_new[q] = x'_old[perm[q]].
+// Reverse, with incoming adjoints (xb', vb', Fb') of the new state:
+//   Fb'  += c vb'                           (k_bwd_prep)
+//   (xPhi, vPhi) = VJP of Phi at (x', v_h)  (k_force_bwd)
+//   xt = xb' + xPhi,  vh = vb' + vPhi + dt xt
+//   xb[perm[q]] = xt,  vb[perm[q]] = vh,  Fb[perm[q]] = c vh   (k_bwd_scatter)
+// v_h is recovered as v' - c F' (within rounding of the forward value).
+// ---------------------------------------------------------------------------
+
+namespace {
+
+__global__ __launch_bounds__(kBlock) void k_bwd_prep(KParams kp, int32_t n, const double* __restrict__ v,
+                                                     const double* __restrict__ f,
+                                                     const double* __restrict__ gv_in,
+                                                     const double* __restrict__ gf_in, double* __restrict__ vt,
+                                                     double* __restrict__ gf_eff)
+{
+    const int64_t a = (int64_t)blockIdx.y * n + blockIdx.x * kBlock + threadIdx.x;
+    if (blockIdx.x * kBlock + threadIdx.x >= n) return;
+    vt[a] = __fma_rn(-kp.half_dt, f[a], v[a]);
+    gf_eff[a] = __fma_rn(kp.half_dt, gv_in[a], gf_in[a]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_bwd_scatter(KParams kp, int32_t n, const int32_t* __restrict__ perm,
+                                                        const double* __restrict__ gx_in,
+                                                        const double* __restrict__ gv_in,
+                                                        const double* __restrict__ xphi,
+                                                        const double* __restrict__ vphi,
+                                                        double* __restrict__ gx_out, double* __restrict__ gv_out,
+                                                        double* __restrict__ gf_out)
+{
+    const int32_t q = blockIdx.x * kBlock + threadIdx.x;
+    if (q >= n) return;
+    const int64_t base = (int64_t)blockIdx.y * n;
+    const int64_t src = base + q, dst = base + perm[q];
+    const double xt = gx_in[src] + xphi[src];
+    const double vh = __fma_rn(kp.dt, xt, gv_in[src] + vphi[src]);
+    gx_out[dst] = xt;
+    gv_out[dst] = vh;
+    gf_out[dst] = kp.half_dt * vh;
+}
+
+}  // namespace
+
+hipError_t launch_step_backward(const KParams& kp, const StepBackwardArgs& b, hipStream_t s)
+{
+    const int32_t n = b.fwd.n;
+    if (n <= 0) return hipSuccess;
+    const dim3 grid(ceil_div(n, kBlock), 3), block(kBlock);
+    hipLaunchKernelGGL(k_bwd_prep, grid, block, 0, s, kp, n, b.v_new, b.f_new, b.gv_in, b.gf_in, b.vt, b.gf_eff);
+    BackwardArgs a = b.fwd;
+    a.v = b.vt;
+    a.g = b.gf_eff;
+    a.xbar = b.xphi;
+    a.vbar = b.vphi;
+    a.acc_xv = 0;
+    a.acc_params = 1;
+    hipError_t e = launch_forces_backward(kp, a, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bwd_scatter, grid, block, 0, s, kp, n, b.perm, b.gx_in, b.gv_in, b.xphi, b.vphi, b.gx_out,
+                       b.gv_out, b.gf_out);
     return hipGetLastError();
 }
 

@@ -1,7 +1,7 @@
 // k_force.hip -- pairwise DPD force (Sec. 2, Eqs (2)-(8) of the paper),
 // harmonic bonds (Sec. 4.5) and the reverse-Poiseuille body force (Sec. 4.2).
 //
-// One lane per particle i walks i's ascending neighbour row.  Per pair:
+// Per pair (the lane layout is described at the kernels below):
 // minimum-image separation, w_C = 1 - r/r_c, w_R = w_C^s (specialised for
 // s = 1/2, 1, 2), w_D = w_R^2, the symmetric pair Gaussian xi_ij from
 // Philox4x32-10 on (min tag, max tag, step, seed) and Box-Muller, and
@@ -97,56 +97,174 @@ __device__ __forceinline__ void add_bonds_body(const KParams& kp, const ForceArg
     if (kp.body_g != 0.0) fx += (yi < kp.body_split) ? kp.body_g : -kp.body_g;
 }
 
+// Work layout.  A wavefront owns 64 consecutive particles ("rows"); their
+// neighbour rows are one contiguous run of CSR entries, which the wave walks
+// 64 entries at a time, one pair per lane (coalesced index loads, no idle
+// lanes waiting for long rows).  Each lane finds its entry's row by a binary
+// search over the rows' end offsets held one per lane, evaluates the pair,
+// and a segmented scan (one segment per row) carries the sums to the lane
+// that ends the row's part of the batch; the row's own lane then adds it to
+// its accumulator.  The grid is persistent: each wave takes a contiguous
+// range of 64-particle chunks, numbered XCD by XCD.
+
+constexpr int kChunk = kWave;
+
+template <typename T>
+__device__ __forceinline__ T seg_scan(T v, int lane, int ss)
+{
+    // inclusive scan over lanes [ss, lane] of this lane's segment
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const bool need = lane - d >= ss;
+        if (!__ballot(need)) break;                 // every segment already complete
+        const T t = __shfl_up(v, d, kWave);
+        v = need ? v + t : v;
+    }
+    return v;
+}
+
+struct PairJob {
+    int32_t i0, ni;      // first particle of the chunk, particles in it
+    int32_t e0, e1;      // its CSR entries
+    int32_t rstart, rend;  // this lane's row (lane < ni)
+};
+
+__device__ __forceinline__ PairJob chunk_job(const ForceArgs& a, int32_t c, bool ok, int lane)
+{
+    PairJob j;
+    j.i0 = c * kChunk;
+    j.ni = a.n - j.i0 < kChunk ? a.n - j.i0 : kChunk;
+    const int32_t own = j.i0 + (lane < j.ni ? lane : j.ni - 1);
+    j.e0 = ok ? a.offset[j.i0] : 0;
+    j.e1 = ok ? a.offset[j.i0 + j.ni] : 0;
+    j.rend = ok ? a.offset[own + 1] : 0;
+    const int32_t prev = __shfl_up(j.rend, 1, kWave);
+    j.rstart = lane == 0 ? j.e0 : prev;
+    if (lane >= j.ni) { j.rstart = j.e1; j.rend = j.e1; }
+    return j;
+}
+
+// row (0..63) of entry e: number of rows whose end is <= e
+__device__ __forceinline__ int32_t row_of(int32_t rend, int32_t e)
+{
+    int32_t r = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+        const int32_t probe = __shfl(rend, r + step - 1, kWave);
+        r = (probe <= e) ? r + step : r;
+    }
+    return r < kWave ? r : kWave - 1;
+}
+
+// lane holding the last entry of this lane's row inside batch [eb, eb+64),
+// or -1 when the row has no entry there
+__device__ __forceinline__ int32_t row_end_lane(const PairJob& jb, int32_t eb)
+{
+    const int32_t lo = jb.rstart > eb ? jb.rstart : eb;
+    int32_t hi = jb.rend < eb + kWave ? jb.rend : eb + kWave;
+    return lo < hi ? hi - eb - 1 : -1;
+}
+
+// One pair (FP64): force contribution on i and its half of the pair
+// potential.  P supplies geometry and cutoff; A / G / S the type tables
+// (a, gamma, sigma / sqrt(dt)).
 template <int kWMode>
-__global__ __launch_bounds__(kBlock) void k_force_fp64(KParams kp, ForceArgs a)
+__device__ __forceinline__ bool pair64(const KParams& P, const double* A, const double* G, const double* S,
+                                       const ForceArgs& a, int64_t N, int32_t i, int32_t j, uint64_t step,
+                                       double& px, double& py, double& pz, double& pp)
+{
+    const double dx = min_image(a.x[i] - a.x[j], P.L[0], P.halfL[0]);
+    const double dy = min_image(a.x[N + i] - a.x[N + j], P.L[1], P.halfL[1]);
+    const double dz = min_image(a.x[2 * N + i] - a.x[2 * N + j], P.L[2], P.halfL[2]);
+    const double r2 = dist2(dx, dy, dz);
+    if (!(r2 < P.rc2)) return false;
+    const double rr = sqrt(r2);
+    const double ex = dx / rr, ey = dy / rr, ez = dz / rr;
+    const double wc = 1.0 - rr * P.inv_rc;
+    const double wr = weight_r(wc, kWMode, P.s);
+    const double wd = wr * wr;
+    const double ev = ex * (a.v[i] - a.v[j]) + ey * (a.v[N + i] - a.v[N + j]) + ez * (a.v[2 * N + i] - a.v[2 * N + j]);
+    const int tp = a.type[i] * P.n_types + a.type[j];
+    const double xi_ij = gauss64(pair_words(a.tag[i], a.tag[j], step, P.seed_lo, P.seed_hi));
+    const double phi = A[tp] * wc - G[tp] * wd * ev + S[tp] * wr * xi_ij;
+    px = phi * ex; py = phi * ey; pz = phi * ez;
+    pp = 0.25 * A[tp] * P.r_c * wc * wc;
+    return true;
+}
+
+template <int kWMode, bool kB>
+__global__ __launch_bounds__(kBlock) void k_force_fp64(KParams kp, BatchView bv, ForceArgs a, int32_t n_chunks)
 {
     __shared__ double s_a[kTab], s_g[kTab], s_s[kTab];
-    const int nt2 = kp.n_types * kp.n_types;
-    for (int t = threadIdx.x; t < nt2; t += kBlock) {
-        s_a[t] = kp.a[t]; s_g[t] = kp.g[t]; s_s[t] = kp.srdt[t];
-    }
-    __syncthreads();
-    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
-    double fx = 0.0, fy = 0.0, fz = 0.0, pe = 0.0, npair = 0.0;
-    if (i < a.n) {
-        const int64_t N = a.n;
-        const uint64_t step = (a.d_step ? *a.d_step : 0ull) + a.step_add;
-        const double xi = a.x[i], yi = a.x[N + i], zi = a.x[2 * N + i];
-        const double vxi = a.v[i], vyi = a.v[N + i], vzi = a.v[2 * N + i];
-        const uint32_t ti = a.tag[i];
-        const int tyi = a.type[i] * kp.n_types;
-        if ((int64_t)a.offset[a.n] <= a.capacity) {
-            const int32_t e1 = a.offset[i + 1];
-            for (int32_t e = a.offset[i]; e < e1; ++e) {
-                const int32_t j = a.index[e];
-                const double dx = min_image(xi - a.x[j], kp.L[0], kp.halfL[0]);
-                const double dy = min_image(yi - a.x[N + j], kp.L[1], kp.halfL[1]);
-                const double dz = min_image(zi - a.x[2 * N + j], kp.L[2], kp.halfL[2]);
-                const double r2 = dist2(dx, dy, dz);
-                if (!(r2 < kp.rc2)) continue;
-                const double r = sqrt(r2);
-                const double ex = dx / r, ey = dy / r, ez = dz / r;
-                const double wc = 1.0 - r * kp.inv_rc;
-                const double wr = weight_r(wc, kWMode, kp.s);
-                const double wd = wr * wr;
-                const double ev = ex * (vxi - a.v[j]) + ey * (vyi - a.v[N + j]) + ez * (vzi - a.v[2 * N + j]);
-                const int tp = tyi + a.type[j];
-                const double xi_ij = gauss64(pair_words(ti, a.tag[j], step, kp.seed_lo, kp.seed_hi));
-                const double phi = s_a[tp] * wc - s_g[tp] * wd * ev + s_s[tp] * wr * xi_ij;
-                fx += phi * ex;
-                fy += phi * ey;
-                fz += phi * ez;
-                pe += 0.25 * s_a[tp] * kp.r_c * wc * wc;
-                npair += 1.0;
-            }
+    if (!kB) {
+        const int nt2 = kp.n_types * kp.n_types;
+        for (int t = threadIdx.x; t < nt2; t += kBlock) {
+            s_a[t] = kp.a[t]; s_g[t] = kp.g[t]; s_s[t] = kp.srdt[t];
         }
-        add_bonds_body(kp, a, i, xi, yi, zi, fx, fy, fz, pe);
-        a.f[i] = fx;
-        a.f[N + i] = fy;
-        a.f[2 * N + i] = fz;
-        if (a.pe) a.pe[i] = pe;
+        __syncthreads();
     }
-    if (a.fred_part) block_partials2(pe, 0.5 * npair, a.fred_part);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
+    const int64_t w = (int64_t)xcd_logical_id(blockIdx.x, gridDim.x) * (kBlock / kWave) + threadIdx.x / kWave;
+    const int32_t c_begin = (int32_t)(n_chunks * w / waves), c_end = (int32_t)(n_chunks * (w + 1) / waves);
+    const int64_t N = a.n;
+    const uint64_t step = (a.d_step ? *a.d_step : 0ull) + a.step_add;
+    const bool ok = (int64_t)a.offset[a.n] <= a.capacity;
+    const bool want_pe = a.pe != nullptr;
+    const bool want_np = a.npair != nullptr;
+    double pe_tot = 0.0, np_tot = 0.0;
+    for (int32_t c = c_begin; c < c_end; ++c) {
+        const PairJob jb = chunk_job(a, c, ok, lane);
+        double fx = 0.0, fy = 0.0, fz = 0.0, pe_row = 0.0, np_row = 0.0;
+        for (int32_t eb = jb.e0; eb < jb.e1; eb += kWave) {
+            const int32_t e = eb + lane;
+            const bool valid = e < jb.e1;
+            const int32_t r = row_of(jb.rend, e);
+            const int32_t i = jb.i0 + r;
+            const int32_t j = valid ? a.index[e] : i;
+            double px = 0.0, py = 0.0, pz = 0.0, pp = 0.0, pn = 0.0;
+            if (valid) {
+                bool hit;
+                if constexpr (kB) {
+                    const KParams& P = bv.kps[bv.sys_of[i]];
+                    hit = pair64<kWMode>(P, P.a, P.g, P.srdt, a, N, i, j, step, px, py, pz, pp);
+                } else {
+                    hit = pair64<kWMode>(kp, s_a, s_g, s_s, a, N, i, j, step, px, py, pz, pp);
+                }
+                pn = hit ? 1.0 : 0.0;
+                np_tot += pn;
+            }
+            pe_tot += pp;
+            const int32_t ss0 = __shfl(jb.rstart, r, kWave) - eb;
+            const int ss = ss0 > 0 ? ss0 : 0;
+            px = seg_scan(px, lane, ss);
+            py = seg_scan(py, lane, ss);
+            pz = seg_scan(pz, lane, ss);
+            if (want_pe) pp = seg_scan(pp, lane, ss);
+            if (want_np) pn = seg_scan(pn, lane, ss);
+            const int32_t src = row_end_lane(jb, eb);
+            const int32_t sl = src < 0 ? 0 : src;
+            const double tx = __shfl(px, sl, kWave);
+            const double ty = __shfl(py, sl, kWave);
+            const double tz = __shfl(pz, sl, kWave);
+            const double tp2 = want_pe ? __shfl(pp, sl, kWave) : 0.0;
+            const double tn = want_np ? __shfl(pn, sl, kWave) : 0.0;
+            if (src >= 0) { fx += tx; fy += ty; fz += tz; pe_row += tp2; np_row += tn; }
+        }
+        if (lane < jb.ni) {
+            const int32_t i = jb.i0 + lane;
+            double pe_b = 0.0;
+            if constexpr (kB) add_bonds_body(bv.kps[bv.sys_of[i]], a, i, a.x[i], a.x[N + i], a.x[2 * N + i], fx, fy, fz, pe_b);
+            else add_bonds_body(kp, a, i, a.x[i], a.x[N + i], a.x[2 * N + i], fx, fy, fz, pe_b);
+            pe_tot += pe_b;
+            a.f[i] = fx;
+            a.f[N + i] = fy;
+            a.f[2 * N + i] = fz;
+            if (want_pe) a.pe[i] = pe_row + pe_b;
+            if (want_np) a.npair[i] = (int32_t)np_row;
+        }
+    }
+    if (a.fred_part) block_partials2(pe_tot, 0.5 * np_tot, a.fred_part);
 }
 
 __device__ __forceinline__ void two_sum_add(float& s, float& c, float v)
@@ -164,109 +282,192 @@ __device__ __forceinline__ int cell_delta(int32_t ci, int32_t cj, int32_t n)
     return d < -1 ? d + n : d;
 }
 
-template <int kWMode>
-__global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, ForceArgs a)
+// One pair in the mixed form.  xw[i] = (x, y, z offsets inside the cell,
+// tag bits), vw[i] = (predicted velocity, cell bits), both float4.
+template <int kWMode, typename Tab>
+__device__ __forceinline__ bool pair32(const KParams& P, const Tab* A, const Tab* G, const Tab* S,
+                                       const ForceArgs& a, const float4* __restrict__ xw,
+                                       const float4* __restrict__ vw, int64_t N, int32_t i, int32_t j,
+                                       uint64_t step, float& px, float& py, float& pz, float& pp)
+{
+    const float4 pi = xw[i], qi = vw[i];
+    const float4 pj = xw[j], qj = vw[j];
+    const uint32_t ci = __float_as_uint(qi.w), cj = __float_as_uint(qj.w);
+    const float ox = (float)cell_delta((int32_t)(ci & 1023u), (int32_t)(cj & 1023u), P.nc[0]) * P.cell_len32[0];
+    const float oy = (float)cell_delta((int32_t)((ci >> 10) & 1023u), (int32_t)((cj >> 10) & 1023u), P.nc[1]) * P.cell_len32[1];
+    const float oz = (float)cell_delta((int32_t)(ci >> 20), (int32_t)(cj >> 20), P.nc[2]) * P.cell_len32[2];
+    const float dx = (pi.x - pj.x) + ox;
+    const float dy = (pi.y - pj.y) + oy;
+    const float dz = (pi.z - pj.z) + oz;
+    const float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
+    // with no skin the FP64 list already decided the pair set; a skin needs
+    // the FP32 test (documented reading)
+    if (!(P.rl2 == P.rc2 || r2 < (float)P.rc2)) return false;
+    float rr, ex, ey, ez;
+    if (r2 >= kCloseR2) {
+        const float inv_r = __builtin_amdgcn_rsqf(r2);
+        rr = r2 * inv_r;
+        ex = dx * inv_r; ey = dy * inv_r; ez = dz * inv_r;
+    } else {
+        // FP32 offsets cannot resolve the direction of a nearly coincident
+        // pair: take its geometry from FP64 positions
+        const double ddx = min_image(a.x[i] - a.x[j], P.L[0], P.halfL[0]);
+        const double ddy = min_image(a.x[N + i] - a.x[N + j], P.L[1], P.halfL[1]);
+        const double ddz = min_image(a.x[2 * N + i] - a.x[2 * N + j], P.L[2], P.halfL[2]);
+        const double r64 = sqrt(dist2(ddx, ddy, ddz));
+        if (!(r64 > 0.0)) return false;              // coincident: no direction, no force
+        rr = (float)r64;
+        ex = (float)(ddx / r64); ey = (float)(ddy / r64); ez = (float)(ddz / r64);
+    }
+    float wc = 1.0f - rr * (float)P.inv_rc;
+    wc = wc > 0.f ? wc : 0.f;
+    const float wr = weight_r32(wc, kWMode, (float)P.s);
+    const float wd = wr * wr;
+    const float ev = ex * (qi.x - qj.x) + ey * (qi.y - qj.y) + ez * (qi.z - qj.z);
+    const int tp = a.type[i] * P.n_types + a.type[j];
+    const float xi_ij = gauss32(pair_words(__float_as_uint(pi.w), __float_as_uint(pj.w), step, P.seed_lo, P.seed_hi));
+    const float at = (float)A[tp], gt = (float)G[tp], st = (float)S[tp];
+    const float phi = at * wc - gt * wd * ev + st * wr * xi_ij;
+    px = phi * ex; py = phi * ey; pz = phi * ez;
+    pp = 0.25f * (float)P.r_c * at * wc * wc;
+    return true;
+}
+
+// Mixed form.  Pair terms in FP32, the segmented scan in FP32, each row's
+// batches added with a two-sum, the result stored in FP64.
+template <int kWMode, bool kB>
+__global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv, ForceArgs a, int32_t n_chunks)
 {
     __shared__ float s_a[kTab], s_g[kTab], s_s[kTab];
-    const int nt2 = kp.n_types * kp.n_types;
-    for (int t = threadIdx.x; t < nt2; t += kBlock) {
-        s_a[t] = (float)kp.a[t]; s_g[t] = (float)kp.g[t]; s_s[t] = (float)kp.srdt[t];
+    if (!kB) {
+        const int nt2 = kp.n_types * kp.n_types;
+        for (int t = threadIdx.x; t < nt2; t += kBlock) {
+            s_a[t] = (float)kp.a[t]; s_g[t] = (float)kp.g[t]; s_s[t] = (float)kp.srdt[t];
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
-    double pe64 = 0.0, npair = 0.0;
-    if (i < a.n) {
-        const int64_t N = a.n;
-        const uint64_t step = (a.d_step ? *a.d_step : 0ull) + a.step_add;
-        const float xi = a.x32[i], yi = a.x32[N + i], zi = a.x32[2 * N + i];
-        const float vxi = a.v32[i], vyi = a.v32[N + i], vzi = a.v32[2 * N + i];
-        const uint32_t ci = a.cell_xyz[i];
-        const int32_t cix = ci & 1023u, ciy = (ci >> 10) & 1023u, ciz = ci >> 20;
-        const uint32_t ti = a.tag[i];
-        const int tyi = a.type[i] * kp.n_types;
-        const float rc32 = (float)kp.r_c, inv_rc32 = (float)kp.inv_rc, rc2_32 = (float)kp.rc2;
-        float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, pe = 0.f;
-        if ((int64_t)a.offset[a.n] <= a.capacity) {
-            const int32_t e1 = a.offset[i + 1];
-            for (int32_t e = a.offset[i]; e < e1; ++e) {
-                const int32_t j = a.index[e];
-                const uint32_t cj = a.cell_xyz[j];
-                const float ox = (float)cell_delta(cix, (int32_t)(cj & 1023u), kp.nc[0]) * kp.cell_len32[0];
-                const float oy = (float)cell_delta(ciy, (int32_t)((cj >> 10) & 1023u), kp.nc[1]) * kp.cell_len32[1];
-                const float oz = (float)cell_delta(ciz, (int32_t)(cj >> 20), kp.nc[2]) * kp.cell_len32[2];
-                const float dx = (xi - a.x32[j]) + ox;
-                const float dy = (yi - a.x32[N + j]) + oy;
-                const float dz = (zi - a.x32[2 * N + j]) + oz;
-                const float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
-                // with no skin the FP64 list already decided the pair set; a
-                // skin needs the FP32 test (documented reading)
-                if (kp.rl2 != kp.rc2 && !(r2 < rc2_32)) continue;
-                float r, ex, ey, ez;
-                if (r2 >= kCloseR2) {
-                    const float inv_r = rsqrtf(r2);
-                    r = r2 * inv_r;
-                    ex = dx * inv_r; ey = dy * inv_r; ez = dz * inv_r;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
+    const int64_t w = (int64_t)xcd_logical_id(blockIdx.x, gridDim.x) * (kBlock / kWave) + threadIdx.x / kWave;
+    const int32_t c_begin = (int32_t)(n_chunks * w / waves), c_end = (int32_t)(n_chunks * (w + 1) / waves);
+    const int64_t N = a.n;
+    const uint64_t step = (a.d_step ? *a.d_step : 0ull) + a.step_add;
+    const bool ok = (int64_t)a.offset[a.n] <= a.capacity;
+    const bool want_pe = a.pe != nullptr;
+    const bool want_np = a.npair != nullptr;
+    const float4* __restrict__ xw = reinterpret_cast<const float4*>(a.x32);
+    const float4* __restrict__ vw = reinterpret_cast<const float4*>(a.v32);
+    double pe_tot = 0.0, np_tot = 0.0;
+    for (int32_t c = c_begin; c < c_end; ++c) {
+        const PairJob jb = chunk_job(a, c, ok, lane);
+        float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, pe_row = 0.f, np_row = 0.f;
+        for (int32_t eb = jb.e0; eb < jb.e1; eb += kWave) {
+            const int32_t e = eb + lane;
+            const bool valid = e < jb.e1;
+            const int32_t r = row_of(jb.rend, e);
+            const int32_t i = jb.i0 + r;
+            const int32_t j = valid ? a.index[e] : i;
+            float px = 0.f, py = 0.f, pz = 0.f, pp = 0.f, pn = 0.f;
+            if (valid) {
+                bool hit;
+                if constexpr (kB) {
+                    const KParams& P = bv.kps[bv.sys_of[i]];
+                    hit = pair32<kWMode>(P, P.a, P.g, P.srdt, a, xw, vw, N, i, j, step, px, py, pz, pp);
                 } else {
-                    // FP32 offsets cannot resolve the direction of a nearly
-                    // coincident pair: take its geometry from FP64 positions
-                    const double ddx = min_image(a.x[i] - a.x[j], kp.L[0], kp.halfL[0]);
-                    const double ddy = min_image(a.x[N + i] - a.x[N + j], kp.L[1], kp.halfL[1]);
-                    const double ddz = min_image(a.x[2 * N + i] - a.x[2 * N + j], kp.L[2], kp.halfL[2]);
-                    const double rr = sqrt(dist2(ddx, ddy, ddz));
-                    if (!(rr > 0.0)) continue;      // coincident: no direction, no force
-                    r = (float)rr;
-                    ex = (float)(ddx / rr); ey = (float)(ddy / rr); ez = (float)(ddz / rr);
+                    hit = pair32<kWMode>(kp, s_a, s_g, s_s, a, xw, vw, N, i, j, step, px, py, pz, pp);
                 }
-                float wc = 1.0f - r * inv_rc32;
-                wc = wc > 0.f ? wc : 0.f;
-                const float wr = weight_r32(wc, kWMode, (float)kp.s);
-                const float wd = wr * wr;
-                const float ev = ex * (vxi - a.v32[j]) + ey * (vyi - a.v32[N + j]) + ez * (vzi - a.v32[2 * N + j]);
-                const int tp = tyi + a.type[j];
-                const float xi_ij = gauss32(pair_words(ti, a.tag[j], step, kp.seed_lo, kp.seed_hi));
-                const float phi = s_a[tp] * wc - s_g[tp] * wd * ev + s_s[tp] * wr * xi_ij;
-                two_sum_add(sx, cx, phi * ex);
-                two_sum_add(sy, cy, phi * ey);
-                two_sum_add(sz, cz, phi * ez);
-                pe += 0.25f * s_a[tp] * rc32 * wc * wc;
-                npair += 1.0;
+                pn = hit ? 1.f : 0.f;
+                np_tot += pn;
+            }
+            pe_tot += pp;
+            const int32_t ss0 = __shfl(jb.rstart, r, kWave) - eb;
+            const int ss = ss0 > 0 ? ss0 : 0;
+            px = seg_scan(px, lane, ss);
+            py = seg_scan(py, lane, ss);
+            pz = seg_scan(pz, lane, ss);
+            if (want_pe) pp = seg_scan(pp, lane, ss);
+            if (want_np) pn = seg_scan(pn, lane, ss);
+            const int32_t src = row_end_lane(jb, eb);
+            const int32_t sl = src < 0 ? 0 : src;
+            const float tx = __shfl(px, sl, kWave), ty = __shfl(py, sl, kWave), tz = __shfl(pz, sl, kWave);
+            const float tp2 = want_pe ? __shfl(pp, sl, kWave) : 0.f;
+            const float tn = want_np ? __shfl(pn, sl, kWave) : 0.f;
+            if (src >= 0) {
+                two_sum_add(sx, cx, tx);
+                two_sum_add(sy, cy, ty);
+                two_sum_add(sz, cz, tz);
+                pe_row += tp2;
+                np_row += tn;
             }
         }
-        double fx = (double)sx + (double)cx, fy = (double)sy + (double)cy, fz = (double)sz + (double)cz;
-        pe64 = pe;
-        if (kp.partner || kp.body_g != 0.0)
-            add_bonds_body(kp, a, i, a.x[i], a.x[N + i], a.x[2 * N + i], fx, fy, fz, pe64);
-        a.f[i] = fx;
-        a.f[N + i] = fy;
-        a.f[2 * N + i] = fz;
-        if (a.pe) a.pe[i] = pe64;
+        if (lane < jb.ni) {
+            const int32_t i = jb.i0 + lane;
+            double fx = (double)sx + (double)cx, fy = (double)sy + (double)cy, fz = (double)sz + (double)cz;
+            double pe_b = 0.0;
+            if constexpr (kB) {
+                const KParams& P = bv.kps[bv.sys_of[i]];
+                if (P.partner || P.body_g != 0.0)
+                    add_bonds_body(P, a, i, a.x[i], a.x[N + i], a.x[2 * N + i], fx, fy, fz, pe_b);
+            } else {
+                if (kp.partner || kp.body_g != 0.0)
+                    add_bonds_body(kp, a, i, a.x[i], a.x[N + i], a.x[2 * N + i], fx, fy, fz, pe_b);
+            }
+            pe_tot += pe_b;
+            a.f[i] = fx;
+            a.f[N + i] = fy;
+            a.f[2 * N + i] = fz;
+            if (want_pe) a.pe[i] = (double)pe_row + pe_b;
+            if (want_np) a.npair[i] = (int32_t)np_row;
+        }
     }
-    if (a.fred_part) block_partials2(pe64, 0.5 * npair, a.fred_part);
+    if (a.fred_part) block_partials2(pe_tot, 0.5 * np_tot, a.fred_part);
 }
 
 }  // namespace
 
-int force_blocks(int32_t n) { return ceil_div(n > 0 ? n : 1, kBlock); }
-
-hipError_t launch_forces(const KParams& kp, int precision, const ForceArgs& a, hipStream_t s)
+// Persistent grid: enough workgroups to fill the chip several times over,
+// never more than there are 64-particle chunks to hand out.
+int force_blocks(int32_t n)
 {
-    if (a.n <= 0) return hipSuccess;
-    const dim3 grid(force_blocks(a.n)), block(kBlock);
+    const int chunks = ceil_div(n > 0 ? n : 1, kChunk);
+    const int waves_per_block = kBlock / kWave;
+    const int max_blocks = 256 * 8;
+    const int blocks = ceil_div(chunks, waves_per_block);
+    return blocks < max_blocks ? blocks : max_blocks;
+}
+
+namespace {
+
+template <bool kB>
+void launch_forces_t(const KParams& kp, const BatchView& bv, int precision, const ForceArgs& a, hipStream_t s)
+{
+    const dim3 grid(force_grid(a)), block(kBlock);
+    const int32_t chunks = ceil_div(a.n, kChunk);
     if (precision == 0) {
         switch (kp.wmode) {
-        case 0: hipLaunchKernelGGL(k_force_fp64<0>, grid, block, 0, s, kp, a); break;
-        case 1: hipLaunchKernelGGL(k_force_fp64<1>, grid, block, 0, s, kp, a); break;
-        case 2: hipLaunchKernelGGL(k_force_fp64<2>, grid, block, 0, s, kp, a); break;
-        default: hipLaunchKernelGGL(k_force_fp64<3>, grid, block, 0, s, kp, a); break;
+        case 0: hipLaunchKernelGGL((k_force_fp64<0, kB>), grid, block, 0, s, kp, bv, a, chunks); break;
+        case 1: hipLaunchKernelGGL((k_force_fp64<1, kB>), grid, block, 0, s, kp, bv, a, chunks); break;
+        case 2: hipLaunchKernelGGL((k_force_fp64<2, kB>), grid, block, 0, s, kp, bv, a, chunks); break;
+        default: hipLaunchKernelGGL((k_force_fp64<3, kB>), grid, block, 0, s, kp, bv, a, chunks); break;
         }
     } else {
         switch (kp.wmode) {
-        case 0: hipLaunchKernelGGL(k_force_mixed<0>, grid, block, 0, s, kp, a); break;
-        case 1: hipLaunchKernelGGL(k_force_mixed<1>, grid, block, 0, s, kp, a); break;
-        case 2: hipLaunchKernelGGL(k_force_mixed<2>, grid, block, 0, s, kp, a); break;
-        default: hipLaunchKernelGGL(k_force_mixed<3>, grid, block, 0, s, kp, a); break;
+        case 0: hipLaunchKernelGGL((k_force_mixed<0, kB>), grid, block, 0, s, kp, bv, a, chunks); break;
+        case 1: hipLaunchKernelGGL((k_force_mixed<1, kB>), grid, block, 0, s, kp, bv, a, chunks); break;
+        case 2: hipLaunchKernelGGL((k_force_mixed<2, kB>), grid, block, 0, s, kp, bv, a, chunks); break;
+        default: hipLaunchKernelGGL((k_force_mixed<3, kB>), grid, block, 0, s, kp, bv, a, chunks); break;
         }
     }
+}
+
+}  // namespace
+
+// In a batch the weight exponent (and so kp.wmode) is shared by all systems.
+hipError_t launch_forces(const KParams& kp, const BatchView& bv, int precision, const ForceArgs& a, hipStream_t s)
+{
+    if (a.n <= 0) return hipSuccess;
+    if (bv.kps) launch_forces_t<true>(kp, bv, precision, a, s);
+    else launch_forces_t<false>(kp, bv, precision, a, s);
     return hipGetLastError();
 }
 

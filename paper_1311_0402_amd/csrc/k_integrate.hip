@@ -15,16 +15,13 @@ namespace dpd {
 
 namespace {
 
-__global__ __launch_bounds__(kBlock) void k_vv1(KParams kp, int32_t n, const double* __restrict__ x,
-                                                const double* __restrict__ v, const double* __restrict__ f,
-                                                const uint32_t* __restrict__ tag,
-                                                const uint8_t* __restrict__ type, double* __restrict__ bx,
-                                                double* __restrict__ bv, double* __restrict__ bvt,
-                                                uint32_t* __restrict__ btag, uint8_t* __restrict__ btype)
+__device__ __forceinline__ void vv1_one(const KParams& kp, int32_t n, int32_t i, int k,
+                                        const double* __restrict__ x, const double* __restrict__ v,
+                                        const double* __restrict__ f, const uint32_t* __restrict__ tag,
+                                        const uint8_t* __restrict__ type, double* __restrict__ bx,
+                                        double* __restrict__ bv, double* __restrict__ bvt,
+                                        uint32_t* __restrict__ btag, uint8_t* __restrict__ btype)
 {
-    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
-    const int k = blockIdx.y;                       // component
-    if (i >= n) return;
     const int64_t a = (int64_t)k * n + i;
     const double L = kp.L[k];
     const double vh = __fma_rn(kp.half_dt, f[a], v[a]);
@@ -40,8 +37,79 @@ __global__ __launch_bounds__(kBlock) void k_vv1(KParams kp, int32_t n, const dou
     }
 }
 
+template <bool kB>
+__global__ __launch_bounds__(kBlock) void k_vv1(KParams kp, BatchView bat, int32_t n, const double* __restrict__ x,
+                                                const double* __restrict__ v, const double* __restrict__ f,
+                                                const uint32_t* __restrict__ tag,
+                                                const uint8_t* __restrict__ type, double* __restrict__ bx,
+                                                double* __restrict__ bv, double* __restrict__ bvt,
+                                                uint32_t* __restrict__ btag, uint8_t* __restrict__ btype)
+{
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    const int k = blockIdx.y;                       // component
+    if (i >= n) return;
+    if constexpr (kB) vv1_one(bat.kps[bat.sys_of[i]], n, i, k, x, v, f, tag, type, bx, bv, bvt, btag, btype);
+    else vv1_one(kp, n, i, k, x, v, f, tag, type, bx, bv, bvt, btag, btype);
+}
+
+// one block per system: momentum, |v|^2, potential energy and pairs over the
+// system's particle range (fixed order), then k_B T.  The totals go to row
+// (*d_step - *base) of red (row 0 when base is null).
+__global__ __launch_bounds__(kBlock) void k_sys_reduce(BatchView bat, int32_t n, const double* __restrict__ v,
+                                                       const double* __restrict__ pe,
+                                                       const int32_t* __restrict__ npair, double* __restrict__ red,
+                                                       const uint64_t* d_step, const uint64_t* base,
+                                                       int32_t* status)
+{
+    __shared__ double s[6][kBlock];
+    const int32_t sy = blockIdx.x;
+    const int32_t lo = bat.p_off[sy], hi = bat.p_off[sy + 1];
+    const int64_t N = n;
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int32_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+        const double vx = v[i], vy = v[N + i], vz = v[2 * N + i];
+        acc[0] += vx; acc[1] += vy; acc[2] += vz;
+        acc[3] += vx * vx + vy * vy + vz * vz;
+        acc[4] += pe[i];
+        acc[5] += (double)npair[i];
+    }
+    for (int q = 0; q < 6; ++q) s[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int wdt = kBlock / 2; wdt > 0; wdt >>= 1) {
+        if (threadIdx.x < wdt)
+            for (int q = 0; q < 6; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + wdt];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double nn = (double)(hi - lo);
+        const double P0 = s[0][0], P1 = s[1][0], P2 = s[2][0], v2 = s[3][0];
+        const double kbt = nn > 1.0 ? (v2 - (P0 * P0 + P1 * P1 + P2 * P2) / nn) / (3.0 * (nn - 1.0)) : 0.0;
+        if (red) {
+            const int64_t row = base ? (int64_t)(*d_step - *base) : 0;
+            double* r = red + 8 * (row * bat.n_sys + sy);
+            r[0] = P0; r[1] = P1; r[2] = P2; r[3] = v2; r[4] = s[4][0]; r[5] = 0.5 * s[5][0]; r[6] = kbt; r[7] = 0.0;
+        }
+        const double chk = P0 + P1 + P2 + v2 + s[4][0];
+        if (status && !(chk - chk == 0.0)) atomicOr(status, 2 /* DPD_STATUS_NONFINITE */);
+    }
+}
+
+// one thread: *dst = *src (a step counter snapshot) or *dst += 1 (src null)
+__global__ void k_counter(uint64_t* dst, const uint64_t* src)
+{
+    if (threadIdx.x == 0) *dst = src ? *src : *dst + 1ull;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sys_map(BatchView bat, int32_t n, uint16_t* __restrict__ sys_of)
+{
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) sys_of[i] = (uint16_t)find_segment(bat.p_off, bat.n_sys, i);
+}
+
 __global__ __launch_bounds__(kBlock) void k_vv2(KParams kp, int32_t n, double* __restrict__ v,
-                                                const double* __restrict__ f, double* __restrict__ part)
+                                                const double* __restrict__ f, double* __restrict__ part,
+                                                const double* __restrict__ fred, int32_t n_fred,
+                                                double* __restrict__ fsum)
 {
     __shared__ double s_p[kBlock / kWave], s_q[kBlock / kWave];
     const int k = blockIdx.y;
@@ -52,6 +120,30 @@ __global__ __launch_bounds__(kBlock) void k_vv2(KParams kp, int32_t n, double* _
         v[base + i] = vn;
         p += vn;
         q += vn * vn;
+    }
+    if (k == 0 && fred) {
+        // fold the force kernel's per-block (PE, pairs) partials, strided by
+        // this block, so the final sum has only kRedBlocks terms per column
+        __shared__ double s_fa[kBlock], s_fb[kBlock];
+        double fa = 0.0, fb = 0.0;
+        for (int32_t m = blockIdx.x + kRedBlocks * threadIdx.x; m < n_fred; m += kRedBlocks * kBlock) {
+            fa += fred[2 * (int64_t)m];
+            fb += fred[2 * (int64_t)m + 1];
+        }
+        s_fa[threadIdx.x] = fa;
+        s_fb[threadIdx.x] = fb;
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) {
+                s_fa[threadIdx.x] += s_fa[threadIdx.x + w];
+                s_fb[threadIdx.x] += s_fb[threadIdx.x + w];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            fsum[2 * blockIdx.x] = s_fa[0];
+            fsum[2 * blockIdx.x + 1] = s_fb[0];
+        }
     }
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) {
@@ -120,20 +212,48 @@ __global__ __launch_bounds__(kBlock) void k_reduce_final(int32_t n, const double
 
 }  // namespace
 
-hipError_t launch_vv1(const KParams& kp, int32_t n, const double* x, const double* v, const double* f,
-                      const uint32_t* tag, const uint8_t* type, double* bx, double* bv, double* bvt,
-                      uint32_t* btag, uint8_t* btype, hipStream_t s)
+hipError_t launch_vv1(const KParams& kp, const BatchView& bat, int32_t n, const double* x, const double* v,
+                      const double* f, const uint32_t* tag, const uint8_t* type, double* bx, double* bv,
+                      double* bvt, uint32_t* btag, uint8_t* btype, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_vv1, dim3(ceil_div(n, kBlock), 3), dim3(kBlock), 0, s, kp, n, x, v, f, tag, type,
-                       bx, bv, bvt, btag, btype);
+    if (bat.kps)
+        hipLaunchKernelGGL(k_vv1<true>, dim3(ceil_div(n, kBlock), 3), dim3(kBlock), 0, s, kp, bat, n, x, v, f, tag,
+                           type, bx, bv, bvt, btag, btype);
+    else
+        hipLaunchKernelGGL(k_vv1<false>, dim3(ceil_div(n, kBlock), 3), dim3(kBlock), 0, s, kp, bat, n, x, v, f, tag,
+                           type, bx, bv, bvt, btag, btype);
+    return hipGetLastError();
+}
+
+hipError_t launch_sys_reduce(const BatchView& bat, int32_t n, const double* v, const double* pe,
+                             const int32_t* npair, double* red, const uint64_t* d_step, const uint64_t* base,
+                             int32_t* status, hipStream_t s)
+{
+    if (bat.n_sys <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sys_reduce, dim3(bat.n_sys), dim3(kBlock), 0, s, bat, n, v, pe, npair, red, d_step, base,
+                       status);
+    return hipGetLastError();
+}
+
+hipError_t launch_counter(uint64_t* dst, const uint64_t* src, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_counter, dim3(1), dim3(64), 0, s, dst, src);
+    return hipGetLastError();
+}
+
+hipError_t launch_sys_map(const BatchView& bat, int32_t n, uint16_t* sys_of, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sys_map, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, bat, n, sys_of);
     return hipGetLastError();
 }
 
 hipError_t launch_vv2(const KParams& kp, int32_t n, double* v, const double* f, double* red_part,
-                      hipStream_t s)
+                      const double* fred_part, int32_t n_fred, double* fsum_part, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_vv2, dim3(kRedBlocks, 3), dim3(kBlock), 0, s, kp, n, v, f, red_part);
+    hipLaunchKernelGGL(k_vv2, dim3(kRedBlocks, 3), dim3(kBlock), 0, s, kp, n, v, f, red_part, fred_part, n_fred,
+                       fsum_part);
     return hipGetLastError();
 }
 

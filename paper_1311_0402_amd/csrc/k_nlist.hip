@@ -19,8 +19,10 @@
 // bit for bit.  Candidates two cells away from i fail the test (cells are
 // wider than r_list).
 //
-// A count pass sizes the rows, a scan makes the CSR offsets, a fill pass
-// writes them.
+// One pass writes every row into a fixed-width scratch slab and the row
+// sizes; a scan makes the CSR offsets and a compaction copies the rows into
+// the CSR list.  Rows that do not fit the slab width send the build through
+// a second, direct pass instead (same walk, writing at the scanned offsets).
 #include <climits>
 
 #include "dpd_launch.h"
@@ -37,9 +39,10 @@ __device__ __forceinline__ int32_t wrap_cell(int32_t c, int32_t n)
     return c >= n ? c - n : c;
 }
 
+// index into the (batch-wide) rank table
 __device__ __forceinline__ int32_t lin_cell(const KParams& kp, int32_t cx, int32_t cy, int32_t cz)
 {
-    return cx + kp.nc[0] * (cy + kp.nc[1] * cz);
+    return kp.c_off + cx + kp.nc[0] * (cy + kp.nc[1] * cz);
 }
 
 __device__ __forceinline__ float min_image32(float d, float L)
@@ -59,28 +62,30 @@ __device__ __forceinline__ bool exact_hit(const KParams& kp, const double* __res
     return dist2(dx, dy, dz) < kp.rl2;
 }
 
-template <bool kFill>
-__global__ __launch_bounds__(kBlock) void k_nlist(KParams kp, int32_t n, const double* __restrict__ x,
-                                                  const float* __restrict__ x32,
-                                                  const uint32_t* __restrict__ cell_xyz,
-                                                  const int32_t* __restrict__ cell_start,
-                                                  const int32_t* __restrict__ rank_tab,
-                                                  int32_t* __restrict__ offset, int32_t* __restrict__ index,
-                                                  int64_t capacity)
+// kDirect = false: rows go to a fixed-width scratch slab (row i at
+// slab[i * K]) and row sizes to offset[]; a scan and k_nlist_compact then
+// produce the CSR list.  kDirect = true: the same walk writes straight into
+// the CSR list (needs the scanned offsets); it only runs when some row did
+// not fit its K slab slots.
+template <bool kDirect>
+__device__ __forceinline__ void nlist_block(const KParams& kp, int32_t blk, int32_t n,
+                                            const double* __restrict__ x, const float* __restrict__ x32,
+                                            const int32_t* __restrict__ cell_start,
+                                            const int32_t* __restrict__ rank_tab, int32_t* __restrict__ offset,
+                                            int32_t* __restrict__ index, int32_t* __restrict__ slab,
+                                            int32_t slab_k, int32_t* __restrict__ flag)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const int32_t blk = xcd_logical_id(blockIdx.x, gridDim.x) * kWavesPerBlock + threadIdx.x / kWave;
-    if (blk >= kp.n_blocks) return;
-    if (kFill && (int64_t)offset[n] > capacity) return;   // overflow flagged by the check kernel
     const int64_t N = n;
 
     // ---- the block and its particle range ----
     int32_t bx, by, bz;
     morton_unrank(blk, kp.nb[0], kp.nb[1], kp.nb[2], kp.nbits_b, &bx, &by, &bz);
     const int32_t o[3] = {2 * bx, 2 * by, 2 * bz};                 // block origin (cells)
-    int32_t nv = 1;
+    int32_t vd[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) nv *= (kp.nc[d] - o[d] >= 2) ? 2 : 1;
+    for (int d = 0; d < 3; ++d) vd[d] = (kp.nc[d] - o[d] >= 2) ? 2 : 1;
+    const int32_t nv = vd[0] * vd[1] * vd[2];
     const int32_t r0 = rank_tab[lin_cell(kp, o[0], o[1], o[2])];
     const int32_t i_lo = cell_start[r0], i_hi = cell_start[r0 + nv];
     if (i_lo == i_hi) return;
@@ -89,9 +94,8 @@ __global__ __launch_bounds__(kBlock) void k_nlist(KParams kp, int32_t n, const d
     int32_t ulo[3], ucnt[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const int32_t v = (kp.nc[d] - o[d] >= 2) ? 2 : 1;
         ulo[d] = o[d] - 1;
-        ucnt[d] = v + 2;
+        ucnt[d] = vd[d] + 2;
         if (kp.small_dim[d] && ucnt[d] > kp.nc[d]) { ulo[d] = 0; ucnt[d] = kp.nc[d]; }
     }
     const int32_t U = ucnt[0] * ucnt[1] * ucnt[2];
@@ -119,21 +123,19 @@ __global__ __launch_bounds__(kBlock) void k_nlist(KParams kp, int32_t n, const d
     }
     const int32_t total = __builtin_amdgcn_readlane(s_incl, kWave - 1);
 
+    const float4* __restrict__ xw = reinterpret_cast<const float4*>(x32);
     const float cl0 = kp.cell_len32[0], cl1 = kp.cell_len32[1], cl2 = kp.cell_len32[2];
     const bool wrap_any = kp.small_dim[0] | kp.small_dim[1] | kp.small_dim[2];
 
     for (int32_t ib = i_lo; ib < i_hi; ib += kWave) {            // i particles, 64 at a time
-        const int32_t ni = (i_hi - ib) < kWave ? (i_hi - ib) : kWave;
-        // lane li holds particle ib + li in the block frame
-        float pix = 0.f, piy = 0.f, piz = 0.f;
+        const int32_t ie = (i_hi - ib) < kWave ? i_hi : ib + kWave;
+        // lane li holds particle ib + li: in-cell offsets and its row count
+        float wix = 0.f, wiy = 0.f, wiz = 0.f;
         int32_t run = 0;
-        if (lane < ni) {
-            const int32_t i = ib + lane;
-            const uint32_t c = cell_xyz[i];
-            pix = x32[i] + (float)((int32_t)(c & 1023u) - o[0]) * cl0;
-            piy = x32[N + i] + (float)((int32_t)((c >> 10) & 1023u) - o[1]) * cl1;
-            piz = x32[2 * N + i] + (float)((int32_t)(c >> 20) - o[2]) * cl2;
-            if (kFill) run = offset[i];
+        if (lane < ie - ib) {
+            const float4 w = xw[ib + lane];
+            wix = w.x; wiy = w.y; wiz = w.z;
+            run = kDirect ? offset[ib + lane] : 0;
         }
         for (int32_t kb = 0; kb < total; kb += kWave) {           // candidates, 64 at a time
             const int32_t k = kb + lane;
@@ -150,17 +152,29 @@ __global__ __launch_bounds__(kBlock) void k_nlist(KParams kp, int32_t n, const d
             const int32_t cin = __shfl(s_incl, m, kWave);
             const int32_t cln = __shfl(s_len, m, kWave);
             const int32_t cof = __shfl(s_off, m, kWave);
-            const int32_t j = valid ? cs + (k - (cin - cln)) : 0;
-            const float ox = (float)(int8_t)(cof & 0xFF), oy = (float)(int8_t)((cof >> 8) & 0xFF),
-                        oz = (float)(int8_t)((cof >> 16) & 0xFF);
-            const float pjx = x32[j] + ox * cl0;
-            const float pjy = x32[N + j] + oy * cl1;
-            const float pjz = x32[2 * N + j] + oz * cl2;
-            for (int32_t li = 0; li < ni; ++li) {
-                const int32_t i = ib + li;
-                float dx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pix), li)) - pjx;
-                float dy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(piy), li)) - pjy;
-                float dz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(piz), li)) - pjz;
+            const int32_t j = valid ? cs + (k - (cin - cln)) : -1;
+            const float4 wj = xw[valid ? j : 0];
+            const float pjx = wj.x + (float)(int8_t)(cof & 0xFF) * cl0;
+            const float pjy = wj.y + (float)(int8_t)((cof >> 8) & 0xFF) * cl1;
+            const float pjz = wj.z + (float)(int8_t)((cof >> 16) & 0xFF) * cl2;
+            // walk the block's cells in rank order; inside cell g the i
+            // side sits at whole-cell offset delta_g from the block origin,
+            // which is folded into the candidate positions once per cell
+            int32_t g = -1, g_end = ib, code = -1;
+            float qx = 0.f, qy = 0.f, qz = 0.f;
+            for (int32_t i = ib; i < ie; ++i) {
+                while (i >= g_end) {                               // next non-empty block cell
+                    ++g;
+                    do { ++code; } while (!((code & 1) < vd[0] && ((code >> 1) & 1) < vd[1] && (code >> 2) < vd[2]));
+                    g_end = cell_start[r0 + g + 1];
+                    qx = pjx - (float)(code & 1) * cl0;
+                    qy = pjy - (float)((code >> 1) & 1) * cl1;
+                    qz = pjz - (float)(code >> 2) * cl2;
+                }
+                const int li = i - ib;
+                float dx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wix), li)) - qx;
+                float dy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wiy), li)) - qy;
+                float dz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wiz), li)) - qz;
                 if (wrap_any) {
                     dx = kp.small_dim[0] ? min_image32(dx, kp.L32[0]) : dx;
                     dy = kp.small_dim[1] ? min_image32(dy, kp.L32[1]) : dy;
@@ -174,14 +188,105 @@ __global__ __launch_bounds__(kBlock) void k_nlist(KParams kp, int32_t n, const d
                     if (amb) hit = exact_hit(kp, x, N, i, j);
                 }
                 const uint64_t mask = __ballot(hit);
-                if (kFill) {
-                    const int32_t base = __builtin_amdgcn_readlane(run, li);
-                    if (hit) index[base + lanes_below(mask)] = j;
+                const int32_t base = __builtin_amdgcn_readlane(run, li);
+                const int32_t at = base + lanes_below(mask);
+                const int32_t cnt = (int32_t)__popcll(mask);
+                if (kDirect) {
+                    if (hit) index[at] = j;
+                } else {
+                    if (hit && at < slab_k) slab[(int64_t)i * slab_k + at] = j;
+                    if (base + cnt > slab_k && lane == 0) atomicOr(flag, 1);
                 }
-                run = (lane == li) ? run + (int32_t)__popcll(mask) : run;
+                run = (lane == li) ? base + cnt : run;
             }
         }
-        if (!kFill && lane < ni) offset[ib + lane] = run;
+        if (!kDirect && lane < ie - ib) offset[ib + lane] = run;
+    }
+}
+
+// blk counts the 2x2x2 blocks of all systems of a batch in turn; kW waves
+// per workgroup, one block per wave
+template <bool kDirect, bool kB, int kW>
+__global__ __launch_bounds__(kW * kWave) void k_nlist(KParams kp, BatchView bv, int32_t n_blocks, int32_t n,
+                                                      const double* __restrict__ x, const float* __restrict__ x32,
+                                                      const int32_t* __restrict__ cell_start,
+                                                      const int32_t* __restrict__ rank_tab,
+                                                      int32_t* __restrict__ offset, int32_t* __restrict__ index,
+                                                      int64_t capacity, int32_t* __restrict__ slab, int32_t slab_k,
+                                                      int32_t* __restrict__ flag)
+{
+    const int32_t blk = xcd_logical_id(blockIdx.x, gridDim.x) * kW + threadIdx.x / kWave;
+    if (blk >= n_blocks) return;
+    if (kDirect && (*flag == 0 || (int64_t)offset[n] > capacity)) return;
+    if constexpr (kB) {
+        const int32_t sy = find_segment(bv.b_off, bv.n_sys, blk);
+        nlist_block<kDirect>(bv.kps[sy], blk - bv.b_off[sy], n, x, x32, cell_start, rank_tab, offset, index, slab,
+                             slab_k, flag);
+    } else {
+        nlist_block<kDirect>(kp, blk, n, x, x32, cell_start, rank_tab, offset, index, slab, slab_k, flag);
+    }
+}
+
+template <bool kDirect, int kW>
+void launch_nlist_pass(const KParams& kp, const BatchView& bv, int32_t n_blocks, int32_t n, const double* x,
+                       const float* x32, const int32_t* cell_start, const int32_t* rank_tab, int32_t* offset,
+                       int32_t* index, int64_t capacity, int32_t* slab, int32_t slab_k, int32_t* flag,
+                       hipStream_t s)
+{
+    const dim3 grid(ceil_div(n_blocks, kW)), block(kW * kWave);
+    if (bv.kps)
+        hipLaunchKernelGGL((k_nlist<kDirect, true, kW>), grid, block, 0, s, kp, bv, n_blocks, n, x, x32, cell_start,
+                           rank_tab, offset, index, capacity, slab, slab_k, flag);
+    else
+        hipLaunchKernelGGL((k_nlist<kDirect, false, kW>), grid, block, 0, s, kp, bv, n_blocks, n, x, x32,
+                           cell_start, rank_tab, offset, index, capacity, slab, slab_k, flag);
+}
+
+template <bool kDirect>
+void launch_nlist_pass(int waves, const KParams& kp, const BatchView& bv, int32_t n_blocks, int32_t n,
+                       const double* x, const float* x32, const int32_t* cell_start, const int32_t* rank_tab,
+                       int32_t* offset, int32_t* index, int64_t capacity, int32_t* slab, int32_t slab_k,
+                       int32_t* flag, hipStream_t s)
+{
+    if (waves == 1)
+        launch_nlist_pass<kDirect, 1>(kp, bv, n_blocks, n, x, x32, cell_start, rank_tab, offset, index, capacity,
+                                      slab, slab_k, flag, s);
+    else if (waves == 2)
+        launch_nlist_pass<kDirect, 2>(kp, bv, n_blocks, n, x, x32, cell_start, rank_tab, offset, index, capacity,
+                                      slab, slab_k, flag, s);
+    else
+        launch_nlist_pass<kDirect, 4>(kp, bv, n_blocks, n, x, x32, cell_start, rank_tab, offset, index, capacity,
+                                      slab, slab_k, flag, s);
+}
+
+// CSR list from the slab: one wave per 64 consecutive rows writes their
+// entries [offset[i0], offset[i0 + 64]) in order, one entry per lane.
+__global__ __launch_bounds__(kBlock) void k_nlist_compact(int32_t n, const int32_t* __restrict__ offset,
+                                                          int64_t capacity, const int32_t* __restrict__ slab,
+                                                          int32_t slab_k, const int32_t* __restrict__ flag,
+                                                          int32_t* __restrict__ index)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t i0 = ((int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave) * kWave;
+    if (i0 >= n || *flag != 0 || (int64_t)offset[n] > capacity) return;
+    const int32_t ni = n - i0 < kWave ? (int32_t)(n - i0) : kWave;
+    const int32_t own = (int32_t)i0 + (lane < ni ? lane : ni - 1);
+    const int32_t e0 = offset[i0], e1 = offset[i0 + ni];
+    int32_t rend = offset[own + 1];
+    const int32_t prev = __shfl_up(rend, 1, kWave);
+    int32_t rstart = lane == 0 ? e0 : prev;
+    if (lane >= ni) { rstart = e1; rend = e1; }
+    for (int32_t eb = e0; eb < e1; eb += kWave) {
+        const int32_t e = eb + lane;
+        int32_t r = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1) {
+            const int32_t probe = __shfl(rend, r + step - 1, kWave);
+            r = (probe <= e) ? r + step : r;
+        }
+        r = r < kWave ? r : kWave - 1;
+        const int32_t rs = __shfl(rstart, r, kWave);
+        if (e < e1) index[e] = slab[(i0 + r) * slab_k + (e - rs)];
     }
 }
 
@@ -192,17 +297,36 @@ __global__ void k_nlist_check(int32_t n, const int32_t* __restrict__ offset, int
         atomicOr(status, 1 /* DPD_STATUS_NLIST_OVERFLOW */);
 }
 
-int nlist_groups(const KParams& kp) { return ceil_div(kp.n_blocks, kWavesPerBlock); }
-
 }  // namespace
 
-hipError_t launch_nlist_count(const KParams& kp, int32_t n, const double* x, const float* x32,
-                              const uint32_t* cell_xyz, const int32_t* cell_start, const int32_t* rank_tab,
-                              int32_t* offset, hipStream_t s)
+// Slots per row of the scratch slab: about 2.5 times the mean neighbour
+// count plus a margin (rows that do not fit fall back to the direct pass).
+int32_t nlist_slab_width(double density, double rl2)
+{
+    const double mean = 4.18879020478639 * density * rl2 * sqrt(rl2);
+    int32_t k = (int32_t)(2.5 * mean + 24.0);
+    k = k < 48 ? 48 : k;
+    return (k + 15) / 16 * 16;
+}
+
+hipError_t launch_nlist(const KParams& kp, const BatchView& bv, int32_t n_blocks, int32_t n, const double* x,
+                        const float* x32, const int32_t* cell_start, const int32_t* rank_tab, int32_t* offset,
+                        int32_t* index, int64_t capacity, int32_t* slab, int32_t slab_k, int32_t* flag,
+                        int32_t* status, int32_t* scan_part, int waves, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_nlist<false>, dim3(nlist_groups(kp)), dim3(kBlock), 0, s, kp, n, x, x32, cell_xyz,
-                       cell_start, rank_tab, offset, (int32_t*)nullptr, (int64_t)0);
+    hipError_t e;
+    if ((e = launch_fill_i32(offset + n, 1, 0, s)) != hipSuccess) return e;
+    if ((e = launch_fill_i32(flag, 1, 0, s)) != hipSuccess) return e;
+    launch_nlist_pass<false>(waves, kp, bv, n_blocks, n, x, x32, cell_start, rank_tab, offset, index, capacity,
+                             slab, slab_k, flag, s);
+    if ((e = launch_scan(offset, (int64_t)n + 1, scan_part, s)) != hipSuccess) return e;
+    if ((e = launch_nlist_check(n, offset, capacity, status, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_nlist_compact, dim3(ceil_div(ceil_div(n, kWave), kWavesPerBlock)), dim3(kBlock), 0, s,
+                       n, (const int32_t*)offset, capacity, (const int32_t*)slab, slab_k, (const int32_t*)flag,
+                       index);
+    launch_nlist_pass<true>(waves, kp, bv, n_blocks, n, x, x32, cell_start, rank_tab, offset, index, capacity,
+                            slab, slab_k, flag, s);
     return hipGetLastError();
 }
 
@@ -211,16 +335,6 @@ hipError_t launch_nlist_check(int32_t n, const int32_t* offset, int64_t capacity
 {
     if (!status) return hipSuccess;
     hipLaunchKernelGGL(k_nlist_check, dim3(1), dim3(64), 0, s, n, offset, capacity, status);
-    return hipGetLastError();
-}
-
-hipError_t launch_nlist_fill(const KParams& kp, int32_t n, const double* x, const float* x32,
-                             const uint32_t* cell_xyz, const int32_t* cell_start, const int32_t* rank_tab,
-                             const int32_t* offset, int32_t* index, int64_t capacity, hipStream_t s)
-{
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_nlist<true>, dim3(nlist_groups(kp)), dim3(kBlock), 0, s, kp, n, x, x32, cell_xyz,
-                       cell_start, rank_tab, const_cast<int32_t*>(offset), index, capacity);
     return hipGetLastError();
 }
 

@@ -25,44 +25,76 @@ hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(kBlock) void k_rank_table(KParams kp, int32_t* __restrict__ rank_tab)
+// Morton rank of every cell; in a batch the table covers all systems' cells
+// (system s at c_off[s]) and holds global ranks c_off[s] + local rank.
+__device__ __forceinline__ void rank_one(const KParams& P, int32_t* __restrict__ rank_tab, int32_t c)
 {
-    const int32_t c = blockIdx.x * kBlock + threadIdx.x;
-    if (c >= kp.n_cells) return;
-    const int32_t cx = c % kp.nc[0];
-    const int32_t cy = (c / kp.nc[0]) % kp.nc[1];
-    const int32_t cz = c / (kp.nc[0] * kp.nc[1]);
-    rank_tab[c] = morton_rank(cx, cy, cz, kp.nc[0], kp.nc[1], kp.nc[2], kp.nbits);
+    const int32_t lc = c - P.c_off;
+    const int32_t cx = lc % P.nc[0];
+    const int32_t cy = (lc / P.nc[0]) % P.nc[1];
+    const int32_t cz = lc / (P.nc[0] * P.nc[1]);
+    rank_tab[c] = P.c_off + morton_rank(cx, cy, cz, P.nc[0], P.nc[1], P.nc[2], P.nbits);
 }
 
-hipError_t launch_rank_table(const KParams& kp, int32_t* rank_tab, hipStream_t s)
+template <bool kB>
+__global__ __launch_bounds__(kBlock) void k_rank_table(KParams kp, BatchView bv, int32_t c_tot,
+                                                       int32_t* __restrict__ rank_tab)
 {
-    hipLaunchKernelGGL(k_rank_table, dim3(ceil_div(kp.n_cells, kBlock)), dim3(kBlock), 0, s, kp, rank_tab);
+    const int32_t c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= c_tot) return;
+    if constexpr (kB) rank_one(bv.kps[find_segment(bv.c_off, bv.n_sys, c)], rank_tab, c);
+    else rank_one(kp, rank_tab, c);
+}
+
+hipError_t launch_rank_table(const KParams& kp, const BatchView& bv, int32_t c_tot, int32_t* rank_tab,
+                             hipStream_t s)
+{
+    if (c_tot <= 0) return hipSuccess;
+    if (bv.kps)
+        hipLaunchKernelGGL(k_rank_table<true>, dim3(ceil_div(c_tot, kBlock)), dim3(kBlock), 0, s, kp, bv, c_tot,
+                           rank_tab);
+    else
+        hipLaunchKernelGGL(k_rank_table<false>, dim3(ceil_div(c_tot, kBlock)), dim3(kBlock), 0, s, kp, bv, c_tot,
+                           rank_tab);
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(kBlock) void k_bin(KParams kp, int32_t n, const double* __restrict__ x,
+__device__ __forceinline__ void bin_one(const KParams& P, int32_t n, int32_t i, const double* __restrict__ x,
+                                        const int32_t* __restrict__ rank_tab, int32_t* __restrict__ key,
+                                        int32_t* __restrict__ slot, uint32_t* __restrict__ cxyz,
+                                        int32_t* __restrict__ counts)
+{
+    const int32_t cx = cell_coord(x[i], P.inv_cell[0], P.nc[0]);
+    const int32_t cy = cell_coord(x[(int64_t)n + i], P.inv_cell[1], P.nc[1]);
+    const int32_t cz = cell_coord(x[2 * (int64_t)n + i], P.inv_cell[2], P.nc[2]);
+    const int32_t r = rank_tab[P.c_off + cx + P.nc[0] * (cy + P.nc[1] * cz)];
+    key[i] = r;
+    cxyz[i] = pack_cell(cx, cy, cz);
+    slot[i] = atomicAdd(&counts[r], 1);
+}
+
+template <bool kB>
+__global__ __launch_bounds__(kBlock) void k_bin(KParams kp, BatchView bv, int32_t n, const double* __restrict__ x,
                                                 const int32_t* __restrict__ rank_tab,
                                                 int32_t* __restrict__ key, int32_t* __restrict__ slot,
                                                 uint32_t* __restrict__ cxyz, int32_t* __restrict__ counts)
 {
     const int32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    const int32_t cx = cell_coord(x[i], kp.inv_cell[0], kp.nc[0]);
-    const int32_t cy = cell_coord(x[(int64_t)n + i], kp.inv_cell[1], kp.nc[1]);
-    const int32_t cz = cell_coord(x[2 * (int64_t)n + i], kp.inv_cell[2], kp.nc[2]);
-    const int32_t r = rank_tab[cx + kp.nc[0] * (cy + kp.nc[1] * cz)];
-    key[i] = r;
-    cxyz[i] = pack_cell(cx, cy, cz);
-    slot[i] = atomicAdd(&counts[r], 1);
+    if constexpr (kB) bin_one(bv.kps[bv.sys_of[i]], n, i, x, rank_tab, key, slot, cxyz, counts);
+    else bin_one(kp, n, i, x, rank_tab, key, slot, cxyz, counts);
 }
 
-hipError_t launch_bin(const KParams& kp, int32_t n, const double* x, const int32_t* rank_tab, int32_t* key,
-                      int32_t* slot, uint32_t* cxyz, int32_t* counts, hipStream_t s)
+hipError_t launch_bin(const KParams& kp, const BatchView& bv, int32_t n, const double* x, const int32_t* rank_tab,
+                      int32_t* key, int32_t* slot, uint32_t* cxyz, int32_t* counts, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bin, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, kp, n, x, rank_tab, key, slot,
-                       cxyz, counts);
+    if (bv.kps)
+        hipLaunchKernelGGL(k_bin<true>, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, kp, bv, n, x, rank_tab, key,
+                           slot, cxyz, counts);
+    else
+        hipLaunchKernelGGL(k_bin<false>, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, kp, bv, n, x, rank_tab, key,
+                           slot, cxyz, counts);
     return hipGetLastError();
 }
 
@@ -201,13 +233,12 @@ hipError_t launch_place(int32_t n, const int32_t* key, const int32_t* slot, cons
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(kBlock) void k_finalize(KParams kp, int32_t n, const int32_t* __restrict__ key,
-                                                     const int32_t* __restrict__ cell_start,
-                                                     const uint32_t* __restrict__ tmp_tag,
-                                                     const int32_t* __restrict__ tmp_src, GatherArgs g)
+__device__ __forceinline__ void finalize_one(const KParams& P, int32_t n, int32_t p,
+                                             const int32_t* __restrict__ key,
+                                             const int32_t* __restrict__ cell_start,
+                                             const uint32_t* __restrict__ tmp_tag,
+                                             const int32_t* __restrict__ tmp_src, const GatherArgs& g)
 {
-    const int32_t p = blockIdx.x * kBlock + threadIdx.x;
-    if (p >= n) return;
     const int32_t src = tmp_src[p];
     const int32_t c = key[src];
     const int32_t lo = cell_start[c], hi = cell_start[c + 1];
@@ -221,7 +252,9 @@ __global__ __launch_bounds__(kBlock) void k_finalize(KParams kp, int32_t n, cons
     g.type_out[dst] = g.type_in[src];
     const uint32_t packed = g.cxyz_in[src];
     g.cell_xyz[dst] = packed;
-    if (g.idx_of_tag && t < (uint32_t)n) g.idx_of_tag[t] = dst;
+    // tags are numbered per system (0 .. n_local - 1)
+    const uint32_t n_tags = (uint32_t)(P.n_local > 0 ? P.n_local : n);
+    if (g.idx_of_tag && t < n_tags) g.idx_of_tag[P.p_off + t] = dst;
     double xs[3], vs[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -240,23 +273,48 @@ __global__ __launch_bounds__(kBlock) void k_finalize(KParams kp, int32_t n, cons
     if (g.x32) {
         const int32_t cc[3] = {(int32_t)(packed & 1023u), (int32_t)((packed >> 10) & 1023u),
                                (int32_t)(packed >> 20)};
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-            g.x32[k * N + dst] = (float)(xs[k] - (double)cc[k] * kp.cell_len[k]);
+        float4 w;
+        w.x = (float)(xs[0] - (double)cc[0] * P.cell_len[0]);
+        w.y = (float)(xs[1] - (double)cc[1] * P.cell_len[1]);
+        w.z = (float)(xs[2] - (double)cc[2] * P.cell_len[2]);
+        w.w = __uint_as_float(t);
+        reinterpret_cast<float4*>(g.x32)[dst] = w;
     }
     if (g.v32) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) g.v32[k * N + dst] = (float)vs[k];
+        float4 w;
+        w.x = (float)vs[0];
+        w.y = (float)vs[1];
+        w.z = (float)vs[2];
+        w.w = __uint_as_float(packed);
+        reinterpret_cast<float4*>(g.v32)[dst] = w;
     }
 }
 
-hipError_t launch_finalize(const KParams& kp, int32_t n, const int32_t* key, const int32_t* cell_start,
-                           const uint32_t* tmp_tag, const int32_t* tmp_src, const GatherArgs& g,
-                           hipStream_t s)
+template <bool kB>
+__global__ __launch_bounds__(kBlock) void k_finalize(KParams kp, BatchView bv, int32_t n,
+                                                     const int32_t* __restrict__ key,
+                                                     const int32_t* __restrict__ cell_start,
+                                                     const uint32_t* __restrict__ tmp_tag,
+                                                     const int32_t* __restrict__ tmp_src, GatherArgs g)
+{
+    const int32_t p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= n) return;
+    // a particle never leaves its system, so position p and its source share it
+    if constexpr (kB) finalize_one(bv.kps[bv.sys_of[p]], n, p, key, cell_start, tmp_tag, tmp_src, g);
+    else finalize_one(kp, n, p, key, cell_start, tmp_tag, tmp_src, g);
+}
+
+hipError_t launch_finalize(const KParams& kp, const BatchView& bv, int32_t n, const int32_t* key,
+                           const int32_t* cell_start, const uint32_t* tmp_tag, const int32_t* tmp_src,
+                           const GatherArgs& g, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_finalize, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, kp, n, key, cell_start,
-                       tmp_tag, tmp_src, g);
+    if (bv.kps)
+        hipLaunchKernelGGL(k_finalize<true>, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, kp, bv, n, key,
+                           cell_start, tmp_tag, tmp_src, g);
+    else
+        hipLaunchKernelGGL(k_finalize<false>, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, kp, bv, n, key,
+                           cell_start, tmp_tag, tmp_src, g);
     return hipGetLastError();
 }
 

@@ -247,13 +247,26 @@ def dpd_step(params: Params, precision: int, st: State, n_steps: int, d_step: to
 def dpd_forces_backward(params: Params, st: State, cells: Optional[Cells], nl: NList, step: int,
                         grad_f: torch.Tensor, grad_x: torch.Tensor, grad_v: torch.Tensor,
                         grad_a: torch.Tensor, grad_gamma: torch.Tensor, ws: torch.Tensor,
-                        stream=None) -> None:
+                        accumulate: bool = False, stream=None) -> None:
     s, n = st.c(), nl.c()
     c = cells.c() if cells is not None else None
     check(lib().dpd_forces_backward(C.byref(params.c()), C.byref(s), C.byref(c) if c is not None else None,
                                     C.byref(n), int(step), _ptr(grad_f), _ptr(grad_x), _ptr(grad_v),
-                                    _ptr(grad_a), _ptr(grad_gamma), _ptr(ws), ws.numel(), _stream(stream)),
+                                    _ptr(grad_a), _ptr(grad_gamma), 1 if accumulate else 0, _ptr(ws),
+                                    ws.numel(), _stream(stream)),
           "dpd_forces_backward")
+
+
+def dpd_step_backward(params: Params, st: State, cells: Cells, nl: NList, step: int,
+                      gx_in: torch.Tensor, gv_in: torch.Tensor, gf_in: torch.Tensor,
+                      gx_out: torch.Tensor, gv_out: torch.Tensor, gf_out: torch.Tensor,
+                      grad_a: torch.Tensor, grad_gamma: torch.Tensor, ws: torch.Tensor, stream=None) -> None:
+    s, c, n = st.c(), cells.c(), nl.c()
+    check(lib().dpd_step_backward(C.byref(params.c()), C.byref(s), C.byref(c), C.byref(n), int(step),
+                                  _ptr(gx_in), _ptr(gv_in), _ptr(gf_in), _ptr(gx_out), _ptr(gv_out),
+                                  _ptr(gf_out), _ptr(grad_a), _ptr(grad_gamma), _ptr(ws), ws.numel(),
+                                  _stream(stream)),
+          "dpd_step_backward")
 
 
 # ------------------------------------------------------------------ System --
@@ -277,8 +290,9 @@ class System:
         self.cells = Cells.empty(self.n, n_cells, device)
         self.nlist = NList.empty(self.n, capacity or default_capacity(params, self.n), device)
         self.ws = alloc_workspace(params, self.n, self.precision, device)
-        self.x32 = torch.empty((3, max(self.n, 1)), dtype=torch.float32, device=device)
-        self.v32 = torch.empty((3, max(self.n, 1)), dtype=torch.float32, device=device)
+        # packed FP32 copies, one float4 per sorted particle (see dpd_bin_reorder)
+        self.x32 = torch.empty((max(self.n, 1), 4), dtype=torch.float32, device=device)
+        self.v32 = torch.empty((max(self.n, 1), 4), dtype=torch.float32, device=device)
         self.d_step = torch.zeros(1, dtype=torch.int64, device=device)
         self.status = torch.zeros(1, dtype=torch.int32, device=device)
         self.stats = torch.zeros(2, dtype=torch.float64, device=device)
@@ -295,12 +309,29 @@ class System:
         self.status.zero_()
         self.reorder_from(src)
         self.rebuild()
+        self.fit_capacity()
         self.compute_forces(int(step))
+
+    def fit_capacity(self, slack: float = 1.25) -> bool:
+        """After a list build: if it overflowed, grow the list to the size the
+        build reported (times slack) and build again.  Synchronises."""
+        st = int(self.status.item())
+        if not st & _abi.STATUS_NLIST_OVERFLOW:
+            return False
+        self.grow_nlist(slack)
+        self.rebuild()
+        st = int(self.status.item())
+        if st & _abi.STATUS_NLIST_OVERFLOW:
+            raise DPDError(_abi.DPD_ECAPACITY, "neighbour list still overflows after growing")
+        return True
 
     def restore(self, x, v, f, tag, typ, step: int) -> None:
         """Resume from a snapshot of the sorted state (as ``host_state``
         returns it): no reordering and no force evaluation, so the next
-        ``step`` continues the interrupted run bit for bit."""
+        ``step`` continues the interrupted run bit for bit.  (The cell list,
+        FP32 copies and neighbour list are rebuilt by that step; call
+        ``reorder_from`` first to use ``rebuild`` / ``compute_forces`` on
+        the restored state directly.)"""
         st = self.state
         st.x.copy_(torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64)))
         st.v.copy_(torch.as_tensor(np.ascontiguousarray(v, dtype=np.float64)))
@@ -360,3 +391,162 @@ class System:
     def host_nlist(self):
         off = self.nlist.offset.cpu().numpy().astype(np.int64)
         return off, self.nlist.index[: int(off[-1])].cpu().numpy()
+
+
+# ------------------------------------------------------------------ Batch --
+
+@dataclass
+class Tiles:
+    """Launch shapes of the batched phases (mirrors dpd_tiles); 0 = default."""
+
+    force_grid: int = 0
+    nlist_waves: int = 0
+
+    def c(self) -> _abi.dpd_tiles:
+        t = _abi.dpd_tiles()
+        t.force_grid, t.nlist_waves = int(self.force_grid), int(self.nlist_waves)
+        return t
+
+
+class Batch:
+    """Device buffers of a batch of independent systems plus its driver.
+
+    ``params`` lists one Params per system (same r_c, skin, dt, lambda, s and
+    n_types; no bonds), ``sizes`` their particle counts.  Arrays are the
+    systems' arrays concatenated in order; tags are local to each system.
+    """
+
+    def __init__(self, params, sizes, precision: int = MIXED, capacity: Optional[int] = None, device="cuda",
+                 stream=None):
+        if len(params) != len(sizes) or not params:
+            raise ValueError("one Params per system, at least one system")
+        self.params = list(params)
+        self.sizes = np.asarray(sizes, dtype=np.int64)
+        self.n_sys = len(self.params)
+        self.offsets = np.zeros(self.n_sys + 1, dtype=np.int64)
+        self.offsets[1:] = np.cumsum(self.sizes)
+        self.n = int(self.offsets[-1])
+        self.precision = int(precision)
+        self.device = device
+        L = lib()
+        tb = int(L.dpd_batch_table_bytes(self.n_sys, self.n))
+        if tb == 0:
+            raise DPDError(_abi.DPD_EINVAL, "dpd_batch_table_bytes")
+        self.table = torch.empty(tb, dtype=torch.uint8, device=device)
+        arr = (_abi.dpd_params * self.n_sys)(*[p.c() for p in self.params])
+        h = C.c_void_p()
+        check(L.dpd_batch_create(arr, self.n_sys, self.offsets.ctypes.data, _ptr(self.table), tb,
+                                 _stream(stream), C.byref(h)), "dpd_batch_create")
+        self.handle = h
+        n_tot, n_cells = C.c_int64(), C.c_int64()
+        check(L.dpd_batch_sizes(self.handle, C.byref(n_tot), C.byref(n_cells)), "dpd_batch_sizes")
+        self.n_cells = int(n_cells.value)
+        nb = int(L.dpd_batch_workspace_bytes(self.handle, self.precision))
+        if nb == 0:
+            raise DPDError(_abi.DPD_EINVAL, "dpd_batch_workspace_bytes")
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=device)
+        if capacity is None:
+            capacity = sum(default_capacity(p, int(n)) for p, n in zip(self.params, self.sizes))
+        self.state = State.empty(self.n, device)
+        self.cells = Cells.empty(self.n, self.n_cells, device)
+        self.nlist = NList.empty(self.n, capacity, device)
+        self.x32 = torch.empty((self.n, 4), dtype=torch.float32, device=device)
+        self.v32 = torch.empty((self.n, 4), dtype=torch.float32, device=device)
+        self.d_step = torch.zeros(1, dtype=torch.int64, device=device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            torch.cuda.synchronize()
+            lib().dpd_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- tiles ----------------------------------------------------------
+    def set_tiles(self, tiles: Tiles) -> None:
+        t = tiles.c()
+        check(lib().dpd_batch_set_tiles(self.handle, C.byref(t)), "dpd_batch_set_tiles")
+
+    def get_tiles(self) -> Tiles:
+        t = _abi.dpd_tiles()
+        check(lib().dpd_batch_get_tiles(self.handle, C.byref(t)), "dpd_batch_get_tiles")
+        return Tiles(int(t.force_grid), int(t.nlist_waves))
+
+    # -- setup ----------------------------------------------------------
+    def load(self, x, v, tag, typ, step: int = 0) -> None:
+        """Copy concatenated host arrays in, reorder, build the list and
+        compute F(step)."""
+        src = State.empty(self.n, self.device)
+        src.x.copy_(torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64)))
+        src.v.copy_(torch.as_tensor(np.ascontiguousarray(v, dtype=np.float64)))
+        src.tag.copy_(torch.as_tensor(np.ascontiguousarray(tag).astype(np.uint32).view(np.int32)))
+        src.type.copy_(torch.as_tensor(np.ascontiguousarray(typ, dtype=np.uint8)))
+        self.d_step.fill_(int(step))
+        self.status.zero_()
+        self.reorder_from(src)
+        self.rebuild()
+        self.fit_capacity()
+        self.compute_forces(int(step))
+
+    def reorder_from(self, src: State, stream=None) -> None:
+        s_in, s_out, c = src.c(), self.state.c(), self.cells.c()
+        mixed = self.precision == MIXED
+        check(lib().dpd_batch_bin_reorder(self.handle, C.byref(s_in), C.byref(s_out), C.byref(c), _ptr(self.x32),
+                                          _ptr(self.v32) if mixed else None, _ptr(self.ws), self.ws.numel(),
+                                          _stream(stream)), "dpd_batch_bin_reorder")
+
+    def rebuild(self, stream=None) -> None:
+        s, c, n = self.state.c(), self.cells.c(), self.nlist.c()
+        check(lib().dpd_batch_build_neighbors(self.handle, C.byref(s), C.byref(c), _ptr(self.x32), C.byref(n),
+                                              _ptr(self.status), _ptr(self.ws), self.ws.numel(), _stream(stream)),
+              "dpd_batch_build_neighbors")
+
+    def fit_capacity(self, slack: float = 1.25) -> bool:
+        st = int(self.status.item())
+        if not st & _abi.STATUS_NLIST_OVERFLOW:
+            return False
+        need = int(self.nlist.offset[self.n].item())
+        self.nlist = NList.empty(self.n, int(max(need, self.nlist.capacity) * slack), self.device)
+        self.status.zero_()
+        self.rebuild()
+        if int(self.status.item()) & _abi.STATUS_NLIST_OVERFLOW:
+            raise DPDError(_abi.DPD_ECAPACITY, "neighbour list still overflows after growing")
+        return True
+
+    def compute_forces(self, step: int, pe_out=None, precision=None, stream=None) -> None:
+        prec = self.precision if precision is None else int(precision)
+        s, c, n = self.state.c(), self.cells.c(), self.nlist.c()
+        mixed = prec == MIXED
+        check(lib().dpd_batch_forces(self.handle, prec, C.byref(s), C.byref(c), _ptr(self.x32) if mixed else None,
+                                     _ptr(self.v32) if mixed else None, C.byref(n), int(step),
+                                     _ptr(self.state.f), _ptr(pe_out), _ptr(self.status), _ptr(self.ws),
+                                     self.ws.numel(), _stream(stream)), "dpd_batch_forces")
+
+    # -- time stepping --------------------------------------------------
+    def step(self, n_steps: int, reductions: Optional[torch.Tensor] = None, use_graph: bool = True,
+             stream=None) -> None:
+        """reductions: optional float64 [n_steps, n_sys, 8] device tensor."""
+        if reductions is not None and tuple(reductions.shape) != (n_steps, self.n_sys, 8):
+            raise ValueError("reductions must have shape (n_steps, n_sys, 8)")
+        mixed = self.precision == MIXED
+        s, c, n = self.state.c(), self.cells.c(), self.nlist.c()
+        check(lib().dpd_batch_step(self.handle, self.precision, C.byref(s), int(n_steps), _ptr(self.d_step),
+                                   _ptr(reductions), C.byref(c), C.byref(n), _ptr(self.x32),
+                                   _ptr(self.v32) if mixed else None, _ptr(self.status), 1 if use_graph else 0,
+                                   _ptr(self.ws), self.ws.numel(), _stream(stream)), "dpd_batch_step")
+
+    def check_status(self) -> int:
+        st = int(self.status.item())
+        if st & _abi.STATUS_NLIST_OVERFLOW:
+            raise DPDError(_abi.DPD_ECAPACITY, "neighbour list overflow (grow the capacity)")
+        if st & _abi.STATUS_NONFINITE:
+            raise DPDError(_abi.DPD_EINVAL, "non-finite totals")
+        return st
+
+    def system_slice(self, k: int) -> slice:
+        return slice(int(self.offsets[k]), int(self.offsets[k + 1]))

@@ -53,6 +53,7 @@ def _systems():
         "ragged": di.uniform_fluid(2717, (9.3, 7.6, 12.9), 8),
         "amphiphile": di.amphiphile(n=6000, seed=4),
         "poiseuille": di.poiseuille(seed=9, box=(6.0, 12.0, 5.0), rho=4.0),
+        "clustered": di.clustered_fluid(),
     }
 
 
@@ -68,7 +69,7 @@ def test_bin_reorder_bitexact(name):
     dst = P.State.empty(s.n)
     cells = P.Cells.empty(s.n, int(np.prod(nc)))
     ws = P.alloc_workspace(params, s.n)
-    x32 = torch.empty((3, s.n), dtype=torch.float32, device="cuda")
+    x32 = torch.empty((s.n, 4), dtype=torch.float32, device="cuda")
     v32 = torch.empty_like(x32)
     P.dpd_bin_reorder(params, src, dst, cells, ws, x32=x32, v32=v32)
     torch.cuda.synchronize()
@@ -82,13 +83,19 @@ def test_bin_reorder_bitexact(name):
     np.testing.assert_array_equal(dst.type.cpu().numpy(), s.type[perm_ref])
     iot = cells.idx_of_tag.cpu().numpy()
     np.testing.assert_array_equal(iot[s.tag[perm_ref]], np.arange(s.n))
-    # FP32 copies: offset inside the cell, velocities rounded
+    # packed FP32 copies: (offset inside the cell, tag bits), (velocity, cell bits)
     cxyz = cells.cell_xyz.cpu().numpy().view(np.uint32)
     cc = np.stack([cxyz & 1023, (cxyz >> 10) & 1023, cxyz >> 20]).astype(np.float64)
+    np.testing.assert_array_equal(cc, np.minimum(np.array(nc)[:, None] - 1,
+                                                 (s.x[:, perm_ref] * (np.array(nc) / s.box)[:, None]).astype(np.int64)))
     ell = s.box / np.array(nc)
     xs = s.x[:, perm_ref]
-    np.testing.assert_array_equal(x32.cpu().numpy(), (xs - cc * ell[:, None]).astype(np.float32))
-    np.testing.assert_array_equal(v32.cpu().numpy(), s.v[:, perm_ref].astype(np.float32))
+    xw = x32.cpu().numpy()
+    vw = v32.cpu().numpy()
+    np.testing.assert_array_equal(xw[:, :3].T, (xs - cc * ell[:, None]).astype(np.float32))
+    np.testing.assert_array_equal(xw[:, 3].view(np.uint32), s.tag[perm_ref])
+    np.testing.assert_array_equal(vw[:, :3].T, s.v[:, perm_ref].astype(np.float32))
+    np.testing.assert_array_equal(vw[:, 3].view(np.uint32), cxyz)
 
 
 def test_bin_reorder_is_deterministic_and_idempotent():
@@ -121,14 +128,18 @@ def test_neighbor_rows_bitexact(name):
 
 def test_neighbor_overflow_flags_and_recovers():
     s = di.small_fluid(3)
-    sim = _sorted_system(s, capacity=1000)
+    params = P.Params.like(s)
+    sim = P.System(params, s.n, P.FP64, capacity=1000)
+    src = _device_state(s)
+    sim.reorder_from(src)
+    sim.rebuild()
+    torch.cuda.synchronize()
     st = int(sim.status.item())
     assert st & P._abi.STATUS_NLIST_OVERFLOW
     need = int(sim.nlist.offset[s.n].item())
     off_ref, idx_ref = oracle.neighbors(sim.host_state()[0], s.box, s.r_c)
     assert need == len(idx_ref)
-    sim.grow_nlist()
-    sim.rebuild()
+    assert sim.fit_capacity()
     torch.cuda.synchronize()
     assert sim.check_status() == 0
     off, idx = sim.host_nlist()

@@ -517,3 +517,42 @@ def test_forces_vjp_finite_differences_s_half_with_bonds():
     s = di.amphiphile(n=400, seed=19, chain_fraction=0.2)
     # small h: for s = 1/2 the weight derivative (1 - r)^(-1/2) is steep near r_c
     _vjp_fd_check(s, 4, 1e-7, 1e-5, rng)
+
+
+# ------------------------------------------------- trajectory adjoint --
+
+@pytest.mark.parametrize("s_exp,h,rtol", [(1.0, 1e-6, 1e-7), (0.5, 1e-7, 2e-6)])
+def test_force_matching_gradient_finite_differences(s_exp, h, rtol):
+    """The oracle's reverse sweep of the velocity-Verlet trajectory equals
+    central finite differences of its own loss, for a_AB, gamma and random
+    directions in x0 and v0.  With s = 1/2 the weight's derivative diverges
+    at r_c, so pairs near the cutoff need a smaller h for the difference
+    quotient to converge (its error shrinks with h: ~1e-3 at h = 1e-5,
+    ~2e-7 at h = 1e-7)."""
+    s = di.binary_mixture(n=300, box=(5.0, 5.0, 4.0), seed=21, a_ab=40.0)
+    s.s = s_exp
+    K = 6
+    rng = np.random.default_rng(4)
+    ref = oracle.trajectory(s, s.x, s.v, K, a=np.array([[25.0, 31.0], [31.0, 25.0]]))
+    T = np.stack([ref[k][2] for k in range(1, K + 1)])
+    L, ga, gg, gx, gv = oracle.force_matching_grad(s, s.x, s.v, K, T)
+
+    def loss(a=None, gamma=None, x=None, v=None):
+        tr = oracle.trajectory(s, s.x if x is None else x, s.v if v is None else v, K, a=a, gamma=gamma)
+        return sum(float(np.sum((tr[k][2] - T[k - 1]) ** 2)) for k in range(1, K + 1))
+
+    np.testing.assert_allclose(loss(), L, rtol=1e-13)
+    da = np.array([[0.0, 1.0], [1.0, 0.0]])
+    fd = (loss(a=s.a + h * da) - loss(a=s.a - h * da)) / (2 * h)
+    np.testing.assert_allclose(ga[0, 1], fd, rtol=rtol)
+    assert ga[0, 1] == ga[1, 0]
+    for t, u in ((0, 0), (0, 1)):
+        dg = np.zeros((2, 2)); dg[t, u] = dg[u, t] = 1.0
+        fd = (loss(gamma=s.gamma + h * dg) - loss(gamma=s.gamma - h * dg)) / (2 * h)
+        np.testing.assert_allclose(gg[t, u], fd, rtol=rtol)
+    dx = rng.standard_normal(s.x.shape)
+    fd = (loss(x=s.x + h * dx) - loss(x=s.x - h * dx)) / (2 * h)
+    np.testing.assert_allclose(np.sum(gx * dx), fd, rtol=rtol)
+    dv = rng.standard_normal(s.v.shape)
+    fd = (loss(v=s.v + h * dv) - loss(v=s.v - h * dv)) / (2 * h)
+    np.testing.assert_allclose(np.sum(gv * dv), fd, rtol=rtol)
