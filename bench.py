@@ -152,7 +152,8 @@ def run_batched(P, torch, steps, warmup, seq_steps, n_sys=256):
     torch.cuda.empty_cache()
     return {"n_sys": n_sys, "n_total": n_tot, "steps": steps, "ms_per_step": ms,
             "particle_steps_per_s": n_tot / (ms * 1e-3),
-            "tiles": {"force_grid": tiles.force_grid, "nlist_waves": tiles.nlist_waves},
+            "tiles": {"force_grid": tiles.force_grid, "nlist_waves": tiles.nlist_waves,
+                      "nlist_kind": tiles.nlist_kind},
             "autotune_s": tune_s, "autotune_ms_per_step": timings,
             "sequential": {"steps": seq_steps, "ms_per_step": ms_seq,
                            "particle_steps_per_s": n_tot / (ms_seq * 1e-3)},

@@ -302,8 +302,12 @@ typedef struct dpd_tiles {
                                64 .. 8192 (0 = one per 4 chunks of 64 rows,
                                at most 2048)                                   */
     int32_t nlist_waves;    /* waves per workgroup of the list build: 1, 2 or 4
-                               (0 = 4); each wave owns one 2x2x2 cell block  */
-    int32_t reserved[2];    /* 0                                              */
+                               (0 = 4)                                         */
+    int32_t nlist_kind;     /* list builder: 0 = one lane per particle (used
+                               while the batch has fewer than 2^27 cells, else
+                               the block builder), 1 = one wave per 2x2x2
+                               cell block                                      */
+    int32_t reserved;       /* 0                                              */
 } dpd_tiles;
 
 /* Device bytes of the batch table for n_sys systems and n_total particles

@@ -81,7 +81,8 @@ class dpd_tiles(C.Structure):
     _fields_ = [
         ("force_grid", C.c_int32),
         ("nlist_waves", C.c_int32),
-        ("reserved", C.c_int32 * 2),
+        ("nlist_kind", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
 

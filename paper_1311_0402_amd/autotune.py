@@ -24,10 +24,12 @@ from .dpd import Batch, Tiles
 
 FORCE_GRIDS = (0, 512, 1024, 2048, 4096)
 NLIST_WAVES = (1, 2, 4)
+NLIST_KINDS = (0, 1)
 
 
 def default_candidates() -> List[Tiles]:
-    return [Tiles(force_grid=g, nlist_waves=w) for g in FORCE_GRIDS for w in NLIST_WAVES]
+    return [Tiles(force_grid=g, nlist_waves=w, nlist_kind=k)
+            for k in NLIST_KINDS for g in FORCE_GRIDS for w in NLIST_WAVES]
 
 
 def cache_path() -> str:
@@ -106,7 +108,7 @@ def tune(b: Batch, candidates: Optional[Iterable[Tiles]] = None, *, use_cache: b
     if use_cache:
         hit = _load_cache(path).get(key)
         if hit is not None:
-            t = Tiles(int(hit["force_grid"]), int(hit["nlist_waves"]))
+            t = Tiles(int(hit["force_grid"]), int(hit["nlist_waves"]), int(hit.get("nlist_kind", 0)))
             b.set_tiles(t)
             return t, {k: float(v) for k, v in hit.get("timings", {}).items()}
     cands = list(candidates) if candidates is not None else default_candidates()
@@ -116,14 +118,14 @@ def tune(b: Batch, candidates: Optional[Iterable[Tiles]] = None, *, use_cache: b
     for t in cands:
         ms = time_tiles(b, t, steps=steps)
         _restore(b, snap)
-        timings[f"{t.force_grid}/{t.nlist_waves}"] = ms
+        timings[f"{t.force_grid}/{t.nlist_waves}/{t.nlist_kind}"] = ms
         if ms < best_ms:
             best, best_ms = t, ms
     torch.cuda.synchronize()
     b.set_tiles(best)
     if use_cache:
         data = _load_cache(path)
-        data[key] = {"force_grid": best.force_grid, "nlist_waves": best.nlist_waves, "ms_per_step": best_ms,
-                     "timings": timings}
+        data[key] = {"force_grid": best.force_grid, "nlist_waves": best.nlist_waves,
+                     "nlist_kind": best.nlist_kind, "ms_per_step": best_ms, "timings": timings}
         _store_cache(path, data)
     return best, timings

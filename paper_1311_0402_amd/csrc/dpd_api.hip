@@ -181,6 +181,7 @@ struct Job {
     int32_t slab_k;      // neighbour slab width
     int32_t force_grid;  // persistent force workgroups (0 = default)
     int32_t nlist_waves; // waves per list-build workgroup
+    int32_t nlist_kind;  // 0: lane per particle (when ranks fit), 1: wave per 2x2x2 cell block
 };
 
 Job single_job(const KParams& kp, int32_t n)
@@ -194,6 +195,7 @@ Job single_job(const KParams& kp, int32_t n)
     j.slab_k = nlist_slab_width(n / vol, kp.rl2);
     j.force_grid = 0;
     j.nlist_waves = 4;
+    j.nlist_kind = 0;
     return j;
 }
 
@@ -266,10 +268,10 @@ int enqueue_reorder(const Job& job, const WsLayout& L, void* ws, const dpd_state
 int enqueue_nlist(const Job& job, const WsLayout& L, void* ws, const dpd_state* st,
                   const dpd_cells* cells, const float* x32, dpd_nlist* nl, int32_t* d_status, hipStream_t s)
 {
-    DPD_TRY(launch_nlist(job.kp, job.bv, job.n_blocks, st->n, st->x, x32, cells->cell_start,
-                         carve<int32_t>(ws, L.rank_tab), nl->offset, nl->index, nl->capacity,
+    DPD_TRY(launch_nlist(job.kp, job.bv, job.n_cells, job.n_blocks, st->n, st->x, x32, cells->cell_xyz,
+                         cells->cell_start, carve<int32_t>(ws, L.rank_tab), nl->offset, nl->index, nl->capacity,
                          carve<int32_t>(ws, L.slab), L.slab_k, carve<int32_t>(ws, L.slab_flag), d_status,
-                         carve<int32_t>(ws, L.scan_part), job.nlist_waves, s),
+                         carve<int32_t>(ws, L.scan_part), job.nlist_waves, job.nlist_kind, s),
             "neighbour list");
     return DPD_OK;
 }
@@ -329,7 +331,7 @@ BatchTable batch_table(int32_t n_sys, int64_t n_total)
 // Arguments a captured step depends on; a change means capturing again.
 struct GraphKey {
     int32_t precision;
-    int32_t force_grid, nlist_waves;
+    int32_t force_grid, nlist_waves, nlist_kind;
     dpd_state st;
     dpd_cells cells;
     dpd_nlist nl;
@@ -745,6 +747,7 @@ int dpd_batch_create(const dpd_params* per_sys, int32_t n_sys, const int64_t* sy
     job.slab_k = slab_k;
     job.force_grid = 0;
     job.nlist_waves = 4;
+    job.nlist_kind = 0;
     b->step_base = carve<uint64_t>(d_table, T.step_base);
 
     const hipStream_t s = as_stream(stream);
@@ -793,11 +796,14 @@ int dpd_batch_set_tiles(dpd_batch* b, const dpd_tiles* t)
         return fail(DPD_EINVAL, "force_grid must be 0 or in [64, %d]", kMaxForceGrid);
     if (t->nlist_waves != 0 && t->nlist_waves != 1 && t->nlist_waves != 2 && t->nlist_waves != 4)
         return fail(DPD_EINVAL, "nlist_waves must be 0, 1, 2 or 4");
-    if (t->reserved[0] || t->reserved[1]) return fail(DPD_EINVAL, "reserved fields must be 0");
+    if (t->nlist_kind != 0 && t->nlist_kind != 1) return fail(DPD_EINVAL, "nlist_kind must be 0 or 1");
+    if (t->reserved) return fail(DPD_EINVAL, "reserved field must be 0");
     const int32_t waves = t->nlist_waves ? t->nlist_waves : 4;
-    if (t->force_grid != b->job.force_grid || waves != b->job.nlist_waves) drop_graph(b);
+    if (t->force_grid != b->job.force_grid || waves != b->job.nlist_waves || t->nlist_kind != b->job.nlist_kind)
+        drop_graph(b);
     b->job.force_grid = t->force_grid;
     b->job.nlist_waves = waves;
+    b->job.nlist_kind = t->nlist_kind;
     return DPD_OK;
 }
 
@@ -807,6 +813,7 @@ int dpd_batch_get_tiles(const dpd_batch* b, dpd_tiles* t)
     std::memset(t, 0, sizeof(*t));
     t->force_grid = b->job.force_grid;
     t->nlist_waves = b->job.nlist_waves;
+    t->nlist_kind = b->job.nlist_kind;
     return DPD_OK;
 }
 
@@ -904,6 +911,7 @@ int dpd_batch_step(dpd_batch* b, int32_t precision, dpd_state* st, int32_t n_ste
     key.precision = precision;
     key.force_grid = b->job.force_grid;
     key.nlist_waves = b->job.nlist_waves;
+    key.nlist_kind = b->job.nlist_kind;
     key.st = *st; key.cells = *cells; key.nl = *nl;
     key.d_step = d_step; key.red = d_reductions; key.x32 = x32; key.v32 = v32; key.d_status = d_status;
     key.ws = ws; key.ws_bytes = ws_bytes;

@@ -131,6 +131,30 @@ DPD_HD int32_t bits_for(int32_t nmax)
     return b;
 }
 
+// Batcher's odd-even merge sorting network for n <= 64 keys, built at
+// compile time (iterative form: runs of length p are merged by comparators
+// k apart, k = p, p/2, ..., 1).  Comparator c orders keys a[c] < b[c].
+struct SortNet {
+    int count;
+    unsigned char a[512], b[512];
+};
+
+constexpr SortNet make_sort_net(int n)
+{
+    SortNet net{};
+    net.count = 0;
+    for (int p = 1; p < n; p <<= 1)
+        for (int k = p; k >= 1; k >>= 1)
+            for (int j = k % p; j <= n - 1 - k; j += 2 * k)
+                for (int i = 0; i <= (k - 1 < n - j - k - 1 ? k - 1 : n - j - k - 1); ++i)
+                    if ((i + j) / (2 * p) == (i + j + k) / (2 * p)) {
+                        net.a[net.count] = (unsigned char)(i + j);
+                        net.b[net.count] = (unsigned char)(i + j + k);
+                        ++net.count;
+                    }
+    return net;
+}
+
 DPD_HD uint32_t pack_cell(int32_t cx, int32_t cy, int32_t cz)
 {
     return (uint32_t)cx | ((uint32_t)cy << 10) | ((uint32_t)cz << 20);

@@ -68,10 +68,11 @@ int32_t nlist_slab_width(double density, double rl2);
 // whole list build: row sizes + slab rows, scan, capacity check, compaction
 // (or the direct pass when a row overflowed its slab row); n_blocks counts
 // the 2x2x2 cell blocks of all systems
-hipError_t launch_nlist(const KParams& kp, const BatchView& bv, int32_t n_blocks, int32_t n, const double* x,
-                        const float* x32, const int32_t* cell_start, const int32_t* rank_tab, int32_t* offset,
-                        int32_t* index, int64_t capacity, int32_t* slab, int32_t slab_k, int32_t* flag,
-                        int32_t* status, int32_t* scan_part, int waves, hipStream_t s);
+hipError_t launch_nlist(const KParams& kp, const BatchView& bv, int32_t n_cells, int32_t n_blocks, int32_t n,
+                        const double* x, const float* x32, const uint32_t* cell_xyz, const int32_t* cell_start,
+                        const int32_t* rank_tab, int32_t* offset, int32_t* index, int64_t capacity, int32_t* slab,
+                        int32_t slab_k, int32_t* flag, int32_t* status, int32_t* scan_part, int waves,
+                        int kind, hipStream_t s);
 hipError_t launch_nlist_check(int32_t n, const int32_t* offset, int64_t capacity, int32_t* status,
                               hipStream_t s);
 

@@ -109,17 +109,50 @@ __device__ __forceinline__ void add_bonds_body(const KParams& kp, const ForceArg
 
 constexpr int kChunk = kWave;
 
+// DPP lane moves (GFX9 data-parallel primitives): row_shr:d shifts inside
+// each 16-lane row, row_bcast:15 / row_bcast:31 hand lane 15 of a row (lane
+// 31) to the next row(s).  Lanes without a source read 0.
+constexpr int kDppRowShr = 0x110;
+constexpr int kDppBcast15 = 0x142;
+constexpr int kDppBcast31 = 0x143;
+
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ float dpp_move(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, kRowMask, 0xF, false));
+}
+
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, kCtrl, kRowMask, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), kCtrl, kRowMask, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Inclusive scan over lanes [ss, lane] of this lane's segment (segments are
+// runs of lanes; ss is the first lane of this lane's run).  Four shifts
+// inside 16-lane rows, then the row tails are carried across rows (lane 15
+// to row 1, lane 47 to row 3, then lane 31 to rows 2 and 3).  A fixed
+// order: every lane's sum is formed the same way on every call.
 template <typename T>
 __device__ __forceinline__ T seg_scan(T v, int lane, int ss)
 {
-    // inclusive scan over lanes [ss, lane] of this lane's segment
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const bool need = lane - d >= ss;
-        if (!__ballot(need)) break;                 // every segment already complete
-        const T t = __shfl_up(v, d, kWave);
-        v = need ? v + t : v;
-    }
+    const int in_row = lane & 15;
+    T t;
+    t = dpp_move<kDppRowShr | 1, 0xF>(v);
+    v = (in_row >= 1 && lane - 1 >= ss) ? v + t : v;
+    t = dpp_move<kDppRowShr | 2, 0xF>(v);
+    v = (in_row >= 2 && lane - 2 >= ss) ? v + t : v;
+    t = dpp_move<kDppRowShr | 4, 0xF>(v);
+    v = (in_row >= 4 && lane - 4 >= ss) ? v + t : v;
+    t = dpp_move<kDppRowShr | 8, 0xF>(v);
+    v = (in_row >= 8 && lane - 8 >= ss) ? v + t : v;
+    t = dpp_move<kDppBcast15, 0xA>(v);
+    v = (((lane >> 4) & 1) && ss <= (lane & ~15) - 1) ? v + t : v;
+    t = dpp_move<kDppBcast31, 0xC>(v);
+    v = (lane >= 32 && ss <= 31) ? v + t : v;
     return v;
 }
 

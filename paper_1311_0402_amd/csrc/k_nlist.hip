@@ -23,6 +23,14 @@
 // sizes; a scan makes the CSR offsets and a compaction copies the rows into
 // the CSR list.  Rows that do not fit the slab width send the build through
 // a second, direct pass instead (same walk, writing at the scanned offsets).
+//
+// Second work unit (the default while all ranks fit 27 bits): one lane per
+// particle i.  The lane ranks i's 27 stencil cells, sorts them by rank with
+// a fixed comparison network (Batcher's odd-even merge sort), and walks them
+// in that order, each cell's particles in index order, so its row comes out
+// ascending with no cross-lane work.  Lanes of a wave walk their own k-th
+// stencil cells together; the distance test is the same FP32 pre-test with
+// the same exact FP64 band rule.
 #include <climits>
 
 #include "dpd_launch.h"
@@ -227,6 +235,124 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist(KParams kp, BatchView bv, 
     }
 }
 
+// ---- lane-per-particle builder ----
+
+constexpr SortNet kNet27 = make_sort_net(27);
+static_assert(kNet27.count == 156, "27-key odd-even merge network");
+
+template <bool kDirect>
+__device__ __forceinline__ void nlist_lane(const KParams& kp, int32_t i, int32_t n, const double* __restrict__ x,
+                                           const float* __restrict__ x32, const uint32_t* __restrict__ cell_xyz,
+                                           const int32_t* __restrict__ cell_start,
+                                           const int32_t* __restrict__ rank_tab, int32_t* __restrict__ offset,
+                                           int32_t* __restrict__ index, int32_t* __restrict__ slab,
+                                           int32_t slab_k, int32_t* __restrict__ flag)
+{
+    const int64_t N = n;
+    const uint32_t me = cell_xyz[i];
+    const int32_t cx = (int32_t)(me & 1023u), cy = (int32_t)((me >> 10) & 1023u), cz = (int32_t)(me >> 20);
+    // stencil keys: rank << 5 | code, code = (dx+1) + 3 (dy+1) + 9 (dz+1)
+    uint32_t key[27];
+#pragma unroll
+    for (int c = 0; c < 27; ++c) {
+        const int dx = c % 3 - 1, dy = (c / 3) % 3 - 1, dz = c / 9 - 1;
+        const int32_t r = rank_tab[lin_cell(kp, wrap_cell(cx + dx, kp.nc[0]), wrap_cell(cy + dy, kp.nc[1]),
+                                            wrap_cell(cz + dz, kp.nc[2]))];
+        key[c] = ((uint32_t)r << 5) | (uint32_t)c;
+    }
+#pragma unroll
+    for (int c = 0; c < kNet27.count; ++c) {
+        const uint32_t u = key[kNet27.a[c]], v = key[kNet27.b[c]];
+        key[kNet27.a[c]] = u < v ? u : v;
+        key[kNet27.b[c]] = u < v ? v : u;
+    }
+    const float4 wi = reinterpret_cast<const float4*>(x32)[i];
+    const float4* __restrict__ xw = reinterpret_cast<const float4*>(x32);
+    const float cl0 = kp.cell_len32[0], cl1 = kp.cell_len32[1], cl2 = kp.cell_len32[2];
+    int32_t cnt = 0;
+    int32_t* __restrict__ out = kDirect ? index + offset[i] : slab + (int64_t)i * slab_k;
+    const int32_t cap = kDirect ? INT_MAX : slab_k;
+#pragma unroll
+    for (int q = 0; q < 27; ++q) {
+        const int32_t r = (int32_t)(key[q] >> 5);
+        const int c = (int)(key[q] & 31u);
+        const int32_t j0 = cell_start[r], j1 = cell_start[r + 1];
+        // i's cell-relative position minus the cell's whole-cell offset
+        const float qx = wi.x - (float)(c % 3 - 1) * cl0;
+        const float qy = wi.y - (float)((c / 3) % 3 - 1) * cl1;
+        const float qz = wi.z - (float)(c / 9 - 1) * cl2;
+        for (int32_t j = j0; j < j1; ++j) {
+            const float4 wj = xw[j];
+            const float dx = qx - wj.x, dy = qy - wj.y, dz = qz - wj.z;
+            const float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
+            bool hit = j != i && r2 < kp.list_lo32;
+            if (j != i && !hit && r2 < kp.list_hi32) hit = exact_hit(kp, x, N, i, j);
+            if (hit) {
+                if (cnt < cap) out[cnt] = j;
+                ++cnt;
+            }
+        }
+    }
+    if (!kDirect) {
+        offset[i] = cnt;
+        if (cnt > slab_k) atomicOr(flag, 1);
+    }
+}
+
+template <bool kDirect, bool kB, int kW>
+__global__ __launch_bounds__(kW * kWave) void k_nlist_lanes(KParams kp, BatchView bv, int32_t n,
+                                                            const double* __restrict__ x,
+                                                            const float* __restrict__ x32,
+                                                            const uint32_t* __restrict__ cell_xyz,
+                                                            const int32_t* __restrict__ cell_start,
+                                                            const int32_t* __restrict__ rank_tab,
+                                                            int32_t* __restrict__ offset,
+                                                            int32_t* __restrict__ index, int64_t capacity,
+                                                            int32_t* __restrict__ slab, int32_t slab_k,
+                                                            int32_t* __restrict__ flag)
+{
+    const int32_t i = xcd_logical_id(blockIdx.x, gridDim.x) * (kW * kWave) + threadIdx.x;
+    if (i >= n) return;
+    if (kDirect && (*flag == 0 || (int64_t)offset[n] > capacity)) return;
+    if constexpr (kB)
+        nlist_lane<kDirect>(bv.kps[bv.sys_of[i]], i, n, x, x32, cell_xyz, cell_start, rank_tab, offset, index,
+                            slab, slab_k, flag);
+    else
+        nlist_lane<kDirect>(kp, i, n, x, x32, cell_xyz, cell_start, rank_tab, offset, index, slab, slab_k, flag);
+}
+
+template <bool kDirect, int kW>
+void launch_nlist_lanes(const KParams& kp, const BatchView& bv, int32_t n, const double* x, const float* x32,
+                        const uint32_t* cell_xyz, const int32_t* cell_start, const int32_t* rank_tab,
+                        int32_t* offset, int32_t* index, int64_t capacity, int32_t* slab, int32_t slab_k,
+                        int32_t* flag, hipStream_t s)
+{
+    const dim3 grid(ceil_div(n, kW * kWave)), block(kW * kWave);
+    if (bv.kps)
+        hipLaunchKernelGGL((k_nlist_lanes<kDirect, true, kW>), grid, block, 0, s, kp, bv, n, x, x32, cell_xyz,
+                           cell_start, rank_tab, offset, index, capacity, slab, slab_k, flag);
+    else
+        hipLaunchKernelGGL((k_nlist_lanes<kDirect, false, kW>), grid, block, 0, s, kp, bv, n, x, x32, cell_xyz,
+                           cell_start, rank_tab, offset, index, capacity, slab, slab_k, flag);
+}
+
+template <bool kDirect>
+void launch_nlist_lanes(int waves, const KParams& kp, const BatchView& bv, int32_t n, const double* x,
+                        const float* x32, const uint32_t* cell_xyz, const int32_t* cell_start,
+                        const int32_t* rank_tab, int32_t* offset, int32_t* index, int64_t capacity,
+                        int32_t* slab, int32_t slab_k, int32_t* flag, hipStream_t s)
+{
+    if (waves == 1)
+        launch_nlist_lanes<kDirect, 1>(kp, bv, n, x, x32, cell_xyz, cell_start, rank_tab, offset, index, capacity,
+                                       slab, slab_k, flag, s);
+    else if (waves == 2)
+        launch_nlist_lanes<kDirect, 2>(kp, bv, n, x, x32, cell_xyz, cell_start, rank_tab, offset, index, capacity,
+                                       slab, slab_k, flag, s);
+    else
+        launch_nlist_lanes<kDirect, 4>(kp, bv, n, x, x32, cell_xyz, cell_start, rank_tab, offset, index, capacity,
+                                       slab, slab_k, flag, s);
+}
+
 template <bool kDirect, int kW>
 void launch_nlist_pass(const KParams& kp, const BatchView& bv, int32_t n_blocks, int32_t n, const double* x,
                        const float* x32, const int32_t* cell_start, const int32_t* rank_tab, int32_t* offset,
@@ -309,24 +435,35 @@ int32_t nlist_slab_width(double density, double rl2)
     return (k + 15) / 16 * 16;
 }
 
-hipError_t launch_nlist(const KParams& kp, const BatchView& bv, int32_t n_blocks, int32_t n, const double* x,
-                        const float* x32, const int32_t* cell_start, const int32_t* rank_tab, int32_t* offset,
-                        int32_t* index, int64_t capacity, int32_t* slab, int32_t slab_k, int32_t* flag,
-                        int32_t* status, int32_t* scan_part, int waves, hipStream_t s)
+hipError_t launch_nlist(const KParams& kp, const BatchView& bv, int32_t n_cells, int32_t n_blocks, int32_t n,
+                        const double* x, const float* x32, const uint32_t* cell_xyz, const int32_t* cell_start,
+                        const int32_t* rank_tab, int32_t* offset, int32_t* index, int64_t capacity, int32_t* slab,
+                        int32_t slab_k, int32_t* flag, int32_t* status, int32_t* scan_part, int waves,
+                        int kind, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipError_t e;
+    // the lane builder packs a rank and a 5-bit stencil code into 32 bits
+    const bool lanes = kind == 0 && cell_xyz && n_cells < (1 << 27);
     if ((e = launch_fill_i32(offset + n, 1, 0, s)) != hipSuccess) return e;
     if ((e = launch_fill_i32(flag, 1, 0, s)) != hipSuccess) return e;
-    launch_nlist_pass<false>(waves, kp, bv, n_blocks, n, x, x32, cell_start, rank_tab, offset, index, capacity,
-                             slab, slab_k, flag, s);
+    if (lanes)
+        launch_nlist_lanes<false>(waves, kp, bv, n, x, x32, cell_xyz, cell_start, rank_tab, offset, index, capacity,
+                                  slab, slab_k, flag, s);
+    else
+        launch_nlist_pass<false>(waves, kp, bv, n_blocks, n, x, x32, cell_start, rank_tab, offset, index, capacity,
+                                 slab, slab_k, flag, s);
     if ((e = launch_scan(offset, (int64_t)n + 1, scan_part, s)) != hipSuccess) return e;
     if ((e = launch_nlist_check(n, offset, capacity, status, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_nlist_compact, dim3(ceil_div(ceil_div(n, kWave), kWavesPerBlock)), dim3(kBlock), 0, s,
                        n, (const int32_t*)offset, capacity, (const int32_t*)slab, slab_k, (const int32_t*)flag,
                        index);
-    launch_nlist_pass<true>(waves, kp, bv, n_blocks, n, x, x32, cell_start, rank_tab, offset, index, capacity,
-                            slab, slab_k, flag, s);
+    if (lanes)
+        launch_nlist_lanes<true>(waves, kp, bv, n, x, x32, cell_xyz, cell_start, rank_tab, offset, index, capacity,
+                                 slab, slab_k, flag, s);
+    else
+        launch_nlist_pass<true>(waves, kp, bv, n_blocks, n, x, x32, cell_start, rank_tab, offset, index, capacity,
+                                slab, slab_k, flag, s);
     return hipGetLastError();
 }
 

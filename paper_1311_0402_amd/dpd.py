@@ -401,10 +401,11 @@ class Tiles:
 
     force_grid: int = 0
     nlist_waves: int = 0
+    nlist_kind: int = 0
 
     def c(self) -> _abi.dpd_tiles:
         t = _abi.dpd_tiles()
-        t.force_grid, t.nlist_waves = int(self.force_grid), int(self.nlist_waves)
+        t.force_grid, t.nlist_waves, t.nlist_kind = int(self.force_grid), int(self.nlist_waves), int(self.nlist_kind)
         return t
 
 
@@ -475,7 +476,7 @@ class Batch:
     def get_tiles(self) -> Tiles:
         t = _abi.dpd_tiles()
         check(lib().dpd_batch_get_tiles(self.handle, C.byref(t)), "dpd_batch_get_tiles")
-        return Tiles(int(t.force_grid), int(t.nlist_waves))
+        return Tiles(int(t.force_grid), int(t.nlist_waves), int(t.nlist_kind))
 
     # -- setup ----------------------------------------------------------
     def load(self, x, v, tag, typ, step: int = 0) -> None:

@@ -150,3 +150,48 @@ def test_counting_morton_rank_equals_sorted_rank():
         ref = oracle.morton_rank_table(np.array(g, dtype=np.int32))
         np.testing.assert_array_equal(vals[at:at + cnt], ref)
         at += cnt
+
+
+_NET_PROBE = r"""
+#include <cstdint>
+#include <cstdio>
+#include "dpd_common.h"
+// 0-1 principle, bit-sliced: bit b of word w is input vector (w * 64 + b);
+// lane q of that vector is bit q of the vector's number
+int main() {
+  constexpr dpd::SortNet net = dpd::make_sort_net(27);
+  const uint64_t total = 1ull << 27;
+  unsigned long long bad = 0;
+  for (uint64_t w = 0; w < total / 64; ++w) {
+    uint64_t v[27];
+    for (int q = 0; q < 27; ++q) {
+      uint64_t m = 0;
+      for (int b = 0; b < 64; ++b) m |= (((w * 64 + b) >> q) & 1ull) << b;
+      v[q] = m;
+    }
+    for (int c = 0; c < net.count; ++c) {
+      const uint64_t x = v[net.a[c]], y = v[net.b[c]];
+      v[net.a[c]] = x & y;
+      v[net.b[c]] = x | y;
+    }
+    for (int q = 0; q + 1 < 27; ++q) bad |= v[q] & ~v[q + 1];
+  }
+  std::printf("%d %llu\n", net.count, bad);
+  return 0;
+}
+"""
+
+
+def test_stencil_sorting_network_sorts_every_input():
+    """The 27-key comparison network the lane list builder sorts its stencil
+    with (host build of the same header) sorts all 2^27 zero-one inputs, so by
+    the zero-one principle it sorts every input."""
+    with tempfile.TemporaryDirectory() as td:
+        src = os.path.join(td, "n.cpp")
+        exe = os.path.join(td, "n")
+        open(src, "w").write(_NET_PROBE)
+        subprocess.run(["g++", "-O2", "-std=c++17", "-I",
+                        os.path.join(ROOT, "paper_1311_0402_amd", "csrc"), src, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True, timeout=300).stdout.split()
+    assert int(out[0]) == 156
+    assert int(out[1]) == 0

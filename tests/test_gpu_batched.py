@@ -143,20 +143,26 @@ def test_graph_replay_equals_eager_and_is_resumable():
 
 
 def test_tiles_do_not_change_results():
+    """Launch shapes and both list builders give bitwise the same lists and
+    trajectories."""
     systems = _systems(_spec(n_sys=5, seed=44))
     ref = None
     for tiles in [P.Tiles(), P.Tiles(force_grid=64, nlist_waves=1), P.Tiles(force_grid=4096, nlist_waves=2),
-                  P.Tiles(force_grid=700, nlist_waves=4)]:
+                  P.Tiles(force_grid=700, nlist_waves=4, nlist_kind=1), P.Tiles(nlist_waves=1, nlist_kind=1)]:
         b = _batch(systems, P.MIXED)
         b.set_tiles(tiles)
+        b.rebuild()
+        torch.cuda.synchronize()
+        nnz = int(b.nlist.offset[b.n].item())
+        lists = [b.nlist.offset.cpu().numpy(), b.nlist.index[:nnz].cpu().numpy()]
         b.step(3, use_graph=True)
         torch.cuda.synchronize()
-        out = [t.cpu().numpy() for t in (b.state.x, b.state.v, b.state.f)]
+        out = lists + [t.cpu().numpy() for t in (b.state.x, b.state.v, b.state.f)]
         if ref is None:
             ref = out
         else:
             for u, w in zip(ref, out):
-                np.testing.assert_array_equal(u, w)
+                np.testing.assert_array_equal(u, w, err_msg=str(tiles))
         b.close()
 
 
@@ -175,18 +181,20 @@ def test_batch_argument_errors():
         b.set_tiles(P.Tiles(force_grid=10))
     with pytest.raises(P.DPDError):
         b.set_tiles(P.Tiles(nlist_waves=3))
-    assert b.get_tiles() == P.Tiles(0, 4)
+    with pytest.raises(P.DPDError):
+        b.set_tiles(P.Tiles(nlist_kind=2))
+    assert b.get_tiles() == P.Tiles(0, 4, 0)
 
 
 def test_autotune_restores_state_and_caches(tmp_path, monkeypatch):
     from paper_1311_0402_amd import autotune
     monkeypatch.setenv("DPD_AUTOTUNE_CACHE", str(tmp_path / "autotune.json"))
     systems = _systems(_spec(n_sys=4, seed=46))
-    cands = [P.Tiles(0, 4), P.Tiles(512, 1), P.Tiles(2048, 2)]
+    cands = [P.Tiles(0, 4), P.Tiles(512, 1), P.Tiles(2048, 2, 1)]
     b = _batch(systems, P.MIXED)
     best, timings = autotune.tune(b, candidates=cands, steps=2)
     assert best in cands and len(timings) == len(cands)
-    assert b.get_tiles() == P.Tiles(best.force_grid, best.nlist_waves or 4)
+    assert b.get_tiles() == P.Tiles(best.force_grid, best.nlist_waves or 4, best.nlist_kind)
     assert int(b.d_step.item()) == 0
     ref = _batch(systems, P.MIXED)
     b.step(3)
