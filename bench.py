@@ -160,6 +160,68 @@ def run_batched(P, torch, steps, warmup, seq_steps, n_sys=256):
             "speedup_vs_sequential": ms_seq / ms}
 
 
+def run_adjoint(P, torch, steps=50, ckpt=10):
+    """Force-matching loss over a 50-step trajectory of the 512,000-particle
+    A/B mixture (checkpoints every 10 steps): forward and backward times,
+    their ratio and the peak device memory of the backward pass."""
+    import dpd_inputs as di
+    from paper_1311_0402_amd import adjoint as A
+    s = di.binary_mixture(n=512_000, seed=6)
+    spec = A.TrajectorySpec(params=P.Params.like(s), tag=s.tag, type=s.type, steps=steps, checkpoint=ckpt)
+    a_ref = float(np.random.default_rng(7).uniform(25.0, 50.0))
+    x0 = torch.tensor(s.x, device="cuda")
+    v0 = torch.tensor(s.v, device="cuda")
+    with torch.no_grad():
+        T = A.trajectory_forces(torch.tensor([[25.0, a_ref], [a_ref, 25.0]], dtype=torch.float64),
+                                torch.tensor(s.gamma), x0, v0, spec)
+    out = {}
+    for rep in range(2):                         # the first repetition warms up
+        a = torch.tensor(s.a, dtype=torch.float64, requires_grad=True)
+        g = torch.tensor(s.gamma, dtype=torch.float64, requires_grad=True)
+        xr = x0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        torch.cuda.reset_peak_memory_stats()
+        t0 = time.perf_counter()
+        loss = A.force_matching_loss(a, g, xr, v0, spec, T)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        out = {"n": s.n, "steps": steps, "checkpoint": ckpt, "forward_s": t1 - t0, "backward_s": t2 - t1,
+               "backward_over_forward": (t2 - t1) / (t1 - t0),
+               "peak_device_bytes": int(torch.cuda.max_memory_allocated()),
+               "loss": float(loss.item()), "grad_a_AB": float(a.grad[0, 1].item())}
+    del T, x0, v0
+    torch.cuda.empty_cache()
+    return out
+
+
+COPY_BYTES = 1 << 30
+
+
+def run_counters(P, torch, sysd):
+    """Two steps per precision (the kernels whose counters are read), then a
+    plain device-to-device copy of COPY_BYTES whose FETCH_SIZE / WRITE_SIZE
+    calibrate the counters against bytes actually moved."""
+    for prec in (P.FP64, P.MIXED):
+        sim = P.System(P.Params.like(sysd), sysd.n, prec)
+        sim.load(sysd.x, sysd.v, sysd.tag, sysd.type, step=0)
+        sim.step(2)
+        torch.cuda.synchronize()
+        sim.check_status()
+        log(f"counters: precision {prec} nnz {int(sim.nlist.offset[sysd.n].item())}")
+        del sim
+        torch.cuda.empty_cache()
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"counters: copied {COPY_BYTES} bytes")
+    print(json.dumps({"counters_run": True, "copy_bytes": COPY_BYTES}), flush=True)
+
+
 def cpu_baseline(sysd):
     """The CPU oracle on a bounded sample: whole oracle time steps (cell-list
     neighbour search, all host threads) on a slab of the same workload."""
@@ -195,7 +257,11 @@ def main():
     ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--counters", action="store_true",
+                    help="short run for hardware counters: 2 steps per precision, then a plain "
+                         "device copy of COPY_BYTES as the counter calibration; prints no bench line")
     ap.add_argument("--batched-steps", type=int, default=100)
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -209,6 +275,9 @@ def main():
     t0 = time.perf_counter()
     sysd = di.amphiphile(n=args.n, seed=3)
     log(f"generated {sysd.n} particles, box {sysd.box[0]:.3f}, in {time.perf_counter() - t0:.1f}s")
+    if args.counters:
+        run_counters(P, torch, sysd)
+        return
 
     results = {}
     for prec in (["fp64", "mixed"] if args.precision == "both" else [args.precision]):
@@ -220,6 +289,12 @@ def main():
         bt = results["batched"]
         log(f"batched: {bt['ms_per_step']:.3f} ms/step for {bt['n_total']} particles in {bt['n_sys']} systems "
             f"(tiles {bt['tiles']}); sequential {bt['sequential']['ms_per_step']:.3f} ms/step")
+
+    if not args.no_adjoint:
+        results["adjoint"] = run_adjoint(P, torch)
+        ad = results["adjoint"]
+        log(f"adjoint: forward {ad['forward_s']:.3f} s, backward {ad['backward_s']:.3f} s "
+            f"(ratio {ad['backward_over_forward']:.2f}), peak {ad['peak_device_bytes'] / 2**30:.2f} GiB")
 
     head = results.get("mixed") or results["fp64"]
     head_name = "mixed" if "mixed" in results else "fp64"

@@ -309,7 +309,7 @@ int check_nlist(const dpd_nlist* nl, int32_t n)
 // cell / block offsets, the particle -> system map and a step-counter
 // snapshot that numbers the rows of the per-step statistics.
 struct BatchTable {
-    size_t kps, p_off, c_off, b_off, sys_of, step_base, total;
+    size_t kps, p_off, c_off, b_off, ch_off, sys_of, step_base, total;
 };
 
 BatchTable batch_table(int32_t n_sys, int64_t n_total)
@@ -322,6 +322,7 @@ BatchTable batch_table(int32_t n_sys, int64_t n_total)
     t.p_off = take((ns + 1) * sizeof(int32_t));
     t.c_off = take((ns + 1) * sizeof(int32_t));
     t.b_off = take((ns + 1) * sizeof(int32_t));
+    t.ch_off = take((ns + 1) * sizeof(int32_t));
     t.sys_of = take((size_t)(n_total > 0 ? n_total : 1) * sizeof(uint16_t));
     t.step_base = take(sizeof(uint64_t));
     t.total = o;
@@ -347,7 +348,7 @@ struct dpd_batch {
     int64_t n_total = 0;
     dpd::Job job;                      // shared KParams (system 0) + BatchView + totals + tiles
     std::vector<dpd::KParams> kps;     // host copies (the device table is filled from these)
-    std::vector<int32_t> p_off, c_off, b_off;
+    std::vector<int32_t> p_off, c_off, b_off, ch_off;
     uint64_t* step_base = nullptr;     // device
     hipGraphExec_t exec = nullptr;     // cached one-step graph
     hipStream_t capture = nullptr;     // stream the graph is captured on
@@ -698,8 +699,9 @@ int dpd_batch_create(const dpd_params* per_sys, int32_t n_sys, const int64_t* sy
     b->p_off.resize(n_sys + 1);
     b->c_off.resize(n_sys + 1);
     b->b_off.resize(n_sys + 1);
+    b->ch_off.resize(n_sys + 1);
     const dpd_params& p0 = per_sys[0];
-    int64_t c_tot = 0, b_tot = 0;
+    int64_t c_tot = 0, b_tot = 0, ch_tot = 0;
     int32_t slab_k = 0;
     for (int32_t q = 0; q < n_sys; ++q) {
         const dpd_params& p = per_sys[q];
@@ -721,6 +723,8 @@ int dpd_batch_create(const dpd_params* per_sys, int32_t n_sys, const int64_t* sy
         b->p_off[q] = k.p_off;
         b->c_off[q] = k.c_off;
         b->b_off[q] = k.b_off;
+        b->ch_off[q] = (int32_t)ch_tot;
+        ch_tot += (ns + kWave - 1) / kWave;
         c_tot += k.n_cells;
         b_tot += k.n_blocks;
         if (c_tot >= ((int64_t)1 << 31) - 1 || b_tot >= ((int64_t)1 << 31)) return fail(DPD_EINVAL, "too many cells");
@@ -731,6 +735,7 @@ int dpd_batch_create(const dpd_params* per_sys, int32_t n_sys, const int64_t* sy
     b->p_off[n_sys] = (int32_t)n_total;
     b->c_off[n_sys] = (int32_t)c_tot;
     b->b_off[n_sys] = (int32_t)b_tot;
+    b->ch_off[n_sys] = (int32_t)ch_tot;
 
     Job& job = b->job;
     job.kp = b->kps[0];
@@ -740,6 +745,8 @@ int dpd_batch_create(const dpd_params* per_sys, int32_t n_sys, const int64_t* sy
     job.bv.p_off = carve<int32_t>(d_table, T.p_off);
     job.bv.c_off = carve<int32_t>(d_table, T.c_off);
     job.bv.b_off = carve<int32_t>(d_table, T.b_off);
+    job.bv.ch_off = carve<int32_t>(d_table, T.ch_off);
+    job.bv.n_chunks = (int32_t)ch_tot;
     job.bv.sys_of = carve<uint16_t>(d_table, T.sys_of);
     job.bv.n_sys = n_sys;
     job.n_cells = (int32_t)c_tot;
@@ -758,6 +765,8 @@ int dpd_batch_create(const dpd_params* per_sys, int32_t n_sys, const int64_t* sy
     DPD_TRY(hipMemcpyAsync(carve<void>(d_table, T.c_off), b->c_off.data(), (n_sys + 1) * sizeof(int32_t),
                            hipMemcpyHostToDevice, s), "copy batch table");
     DPD_TRY(hipMemcpyAsync(carve<void>(d_table, T.b_off), b->b_off.data(), (n_sys + 1) * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s), "copy batch table");
+    DPD_TRY(hipMemcpyAsync(carve<void>(d_table, T.ch_off), b->ch_off.data(), (n_sys + 1) * sizeof(int32_t),
                            hipMemcpyHostToDevice, s), "copy batch table");
     DPD_TRY(launch_sys_map(job.bv, (int32_t)n_total, carve<uint16_t>(d_table, T.sys_of), s), "system map");
     // the host vectors feed asynchronous copies: they must not move before

@@ -168,8 +168,10 @@ struct BatchView {
     const int32_t* p_off;
     const int32_t* c_off;
     const int32_t* b_off;
+    const int32_t* ch_off;   // 64-row force chunks, numbered system by system
     const uint16_t* sys_of;
     int32_t n_sys;
+    int32_t n_chunks;        // ch_off[n_sys]
 };
 
 #if defined(__HIPCC__)

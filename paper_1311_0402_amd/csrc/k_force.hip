@@ -162,11 +162,23 @@ struct PairJob {
     int32_t rstart, rend;  // this lane's row (lane < ni)
 };
 
-__device__ __forceinline__ PairJob chunk_job(const ForceArgs& a, int32_t c, bool ok, int lane)
+// chunk c: 64 rows from i0 (fewer at the end of the particle range).  In a
+// batch, chunks are numbered system by system from each system's first
+// particle, so every row is grouped, and its sum ordered, exactly as in the
+// system's own single-system run.
+template <bool kB>
+__device__ __forceinline__ PairJob chunk_job(const BatchView& bv, const ForceArgs& a, int32_t c, bool ok, int lane)
 {
     PairJob j;
-    j.i0 = c * kChunk;
-    j.ni = a.n - j.i0 < kChunk ? a.n - j.i0 : kChunk;
+    int32_t end = a.n;
+    if constexpr (kB) {
+        const int32_t sy = find_segment(bv.ch_off, bv.n_sys, c);
+        j.i0 = bv.p_off[sy] + (c - bv.ch_off[sy]) * kChunk;
+        end = bv.p_off[sy + 1];
+    } else {
+        j.i0 = c * kChunk;
+    }
+    j.ni = end - j.i0 < kChunk ? end - j.i0 : kChunk;
     const int32_t own = j.i0 + (lane < j.ni ? lane : j.ni - 1);
     j.e0 = ok ? a.offset[j.i0] : 0;
     j.e1 = ok ? a.offset[j.i0 + j.ni] : 0;
@@ -177,16 +189,28 @@ __device__ __forceinline__ PairJob chunk_job(const ForceArgs& a, int32_t c, bool
     return j;
 }
 
-// row (0..63) of entry e: number of rows whose end is <= e
-__device__ __forceinline__ int32_t row_of(int32_t rend, int32_t e)
+// Row of this lane's entry e = eb + lane, and the lane where that row's part
+// of the batch starts.  Rows are the chunk's lanes 0..ni-1 with contiguous,
+// ascending entry ranges; the rows overlapping the batch are ra..rb-1
+// (uniform, from two ballots) and the wave steps through their ends with
+// readlane, so no lane waits on a shuffle chain.
+struct RowPos {
+    int32_t r, ss;
+};
+
+__device__ __forceinline__ RowPos row_pos(const PairJob& jb, int32_t eb, int lane)
 {
-    int32_t r = 0;
-#pragma unroll
-    for (int step = 32; step > 0; step >>= 1) {
-        const int32_t probe = __shfl(rend, r + step - 1, kWave);
-        r = (probe <= e) ? r + step : r;
+    const bool own = lane < jb.ni;
+    const int32_t ra = (int32_t)__popcll(__ballot(own && jb.rend <= eb));
+    const int32_t rb = (int32_t)__popcll(__ballot(own && jb.rstart < eb + kWave));
+    const int32_t e = eb + lane;
+    RowPos p{ra, 0};
+    for (int32_t q = ra; q < rb; ++q) {
+        const int32_t t = __builtin_amdgcn_readlane(jb.rend, q);
+        if (e >= t) { p.r = q + 1; p.ss = t - eb; }
     }
-    return r < kWave ? r : kWave - 1;
+    p.r = p.r < jb.ni ? p.r : jb.ni - 1;       // lanes past the last entry
+    return p;
 }
 
 // lane holding the last entry of this lane's row inside batch [eb, eb+64),
@@ -212,7 +236,10 @@ __device__ __forceinline__ bool pair64(const KParams& P, const double* A, const 
     const double r2 = dist2(dx, dy, dz);
     if (!(r2 < P.rc2)) return false;
     const double rr = sqrt(r2);
-    const double ex = dx / rr, ey = dy / rr, ez = dz / rr;
+    // one correctly rounded reciprocal for the three components (within an
+    // ulp of the three quotients)
+    const double inv_r = 1.0 / rr;
+    const double ex = dx * inv_r, ey = dy * inv_r, ez = dz * inv_r;
     const double wc = 1.0 - rr * P.inv_rc;
     const double wr = weight_r(wc, kWMode, P.s);
     const double wd = wr * wr;
@@ -247,12 +274,13 @@ __global__ __launch_bounds__(kBlock) void k_force_fp64(KParams kp, BatchView bv,
     const bool want_np = a.npair != nullptr;
     double pe_tot = 0.0, np_tot = 0.0;
     for (int32_t c = c_begin; c < c_end; ++c) {
-        const PairJob jb = chunk_job(a, c, ok, lane);
+        const PairJob jb = chunk_job<kB>(bv, a, c, ok, lane);
         double fx = 0.0, fy = 0.0, fz = 0.0, pe_row = 0.0, np_row = 0.0;
         for (int32_t eb = jb.e0; eb < jb.e1; eb += kWave) {
             const int32_t e = eb + lane;
             const bool valid = e < jb.e1;
-            const int32_t r = row_of(jb.rend, e);
+            const RowPos rp = row_pos(jb, eb, lane);
+            const int32_t r = rp.r;
             const int32_t i = jb.i0 + r;
             const int32_t j = valid ? a.index[e] : i;
             double px = 0.0, py = 0.0, pz = 0.0, pp = 0.0, pn = 0.0;
@@ -268,8 +296,7 @@ __global__ __launch_bounds__(kBlock) void k_force_fp64(KParams kp, BatchView bv,
                 np_tot += pn;
             }
             pe_tot += pp;
-            const int32_t ss0 = __shfl(jb.rstart, r, kWave) - eb;
-            const int ss = ss0 > 0 ? ss0 : 0;
+            const int ss = rp.ss;
             px = seg_scan(px, lane, ss);
             py = seg_scan(py, lane, ss);
             pz = seg_scan(pz, lane, ss);
@@ -392,12 +419,13 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
     const float4* __restrict__ vw = reinterpret_cast<const float4*>(a.v32);
     double pe_tot = 0.0, np_tot = 0.0;
     for (int32_t c = c_begin; c < c_end; ++c) {
-        const PairJob jb = chunk_job(a, c, ok, lane);
+        const PairJob jb = chunk_job<kB>(bv, a, c, ok, lane);
         float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, pe_row = 0.f, np_row = 0.f;
         for (int32_t eb = jb.e0; eb < jb.e1; eb += kWave) {
             const int32_t e = eb + lane;
             const bool valid = e < jb.e1;
-            const int32_t r = row_of(jb.rend, e);
+            const RowPos rp = row_pos(jb, eb, lane);
+            const int32_t r = rp.r;
             const int32_t i = jb.i0 + r;
             const int32_t j = valid ? a.index[e] : i;
             float px = 0.f, py = 0.f, pz = 0.f, pp = 0.f, pn = 0.f;
@@ -413,8 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
                 np_tot += pn;
             }
             pe_tot += pp;
-            const int32_t ss0 = __shfl(jb.rstart, r, kWave) - eb;
-            const int ss = ss0 > 0 ? ss0 : 0;
+            const int ss = rp.ss;
             px = seg_scan(px, lane, ss);
             py = seg_scan(py, lane, ss);
             pz = seg_scan(pz, lane, ss);
@@ -475,7 +502,7 @@ template <bool kB>
 void launch_forces_t(const KParams& kp, const BatchView& bv, int precision, const ForceArgs& a, hipStream_t s)
 {
     const dim3 grid(force_grid(a)), block(kBlock);
-    const int32_t chunks = ceil_div(a.n, kChunk);
+    const int32_t chunks = bv.kps ? bv.n_chunks : ceil_div(a.n, kChunk);
     if (precision == 0) {
         switch (kp.wmode) {
         case 0: hipLaunchKernelGGL((k_force_fp64<0, kB>), grid, block, 0, s, kp, bv, a, chunks); break;

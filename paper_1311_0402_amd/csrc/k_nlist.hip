@@ -281,8 +281,11 @@ __device__ __forceinline__ void nlist_lane(const KParams& kp, int32_t i, int32_t
         const float qx = wi.x - (float)(c % 3 - 1) * cl0;
         const float qy = wi.y - (float)((c / 3) % 3 - 1) * cl1;
         const float qz = wi.z - (float)(c / 9 - 1) * cl2;
+        // the next candidate's load is issued before this one is tested
+        float4 wn = xw[j0 < j1 ? j0 : i];
         for (int32_t j = j0; j < j1; ++j) {
-            const float4 wj = xw[j];
+            const float4 wj = wn;
+            wn = xw[j + 1 < j1 ? j + 1 : j];
             const float dx = qx - wj.x, dy = qy - wj.y, dz = qz - wj.z;
             const float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
             bool hit = j != i && r2 < kp.list_lo32;
@@ -403,15 +406,16 @@ __global__ __launch_bounds__(kBlock) void k_nlist_compact(int32_t n, const int32
     int32_t rstart = lane == 0 ? e0 : prev;
     if (lane >= ni) { rstart = e1; rend = e1; }
     for (int32_t eb = e0; eb < e1; eb += kWave) {
+        // rows ra..rb-1 overlap this batch; walk their ends with readlane
         const int32_t e = eb + lane;
-        int32_t r = 0;
-#pragma unroll
-        for (int step = 32; step > 0; step >>= 1) {
-            const int32_t probe = __shfl(rend, r + step - 1, kWave);
-            r = (probe <= e) ? r + step : r;
+        const int32_t ra = (int32_t)__popcll(__ballot(lane < ni && rend <= eb));
+        const int32_t rb = (int32_t)__popcll(__ballot(lane < ni && rstart < eb + kWave));
+        int32_t r = ra;
+        int32_t rs = __builtin_amdgcn_readlane(rstart, ra < kWave ? ra : kWave - 1);
+        for (int32_t q = ra; q < rb; ++q) {
+            const int32_t t = __builtin_amdgcn_readlane(rend, q);
+            if (e >= t) { r = q + 1; rs = t; }
         }
-        r = r < kWave ? r : kWave - 1;
-        const int32_t rs = __shfl(rstart, r, kWave);
         if (e < e1) index[e] = slab[(i0 + r) * slab_k + (e - rs)];
     }
 }

@@ -59,10 +59,9 @@ hipError_t launch_rank_table(const KParams& kp, const BatchView& bv, int32_t c_t
     return hipGetLastError();
 }
 
-__device__ __forceinline__ void bin_one(const KParams& P, int32_t n, int32_t i, const double* __restrict__ x,
-                                        const int32_t* __restrict__ rank_tab, int32_t* __restrict__ key,
-                                        int32_t* __restrict__ slot, uint32_t* __restrict__ cxyz,
-                                        int32_t* __restrict__ counts)
+__device__ __forceinline__ int32_t bin_one(const KParams& P, int32_t n, int32_t i, const double* __restrict__ x,
+                                           const int32_t* __restrict__ rank_tab, int32_t* __restrict__ key,
+                                           uint32_t* __restrict__ cxyz)
 {
     const int32_t cx = cell_coord(x[i], P.inv_cell[0], P.nc[0]);
     const int32_t cy = cell_coord(x[(int64_t)n + i], P.inv_cell[1], P.nc[1]);
@@ -70,9 +69,13 @@ __device__ __forceinline__ void bin_one(const KParams& P, int32_t n, int32_t i, 
     const int32_t r = rank_tab[P.c_off + cx + P.nc[0] * (cy + P.nc[1] * cz)];
     key[i] = r;
     cxyz[i] = pack_cell(cx, cy, cz);
-    slot[i] = atomicAdd(&counts[r], 1);
+    return r;
 }
 
+// Cell of every particle and a provisional slot inside it.  The state comes
+// in nearly sorted (last step's order), so neighbouring lanes mostly share a
+// cell: each run of equal keys in consecutive lanes takes its slots with one
+// atomic.  Slots only need to be distinct; the final in-cell order is by tag.
 template <bool kB>
 __global__ __launch_bounds__(kBlock) void k_bin(KParams kp, BatchView bv, int32_t n, const double* __restrict__ x,
                                                 const int32_t* __restrict__ rank_tab,
@@ -80,9 +83,25 @@ __global__ __launch_bounds__(kBlock) void k_bin(KParams kp, BatchView bv, int32_
                                                 uint32_t* __restrict__ cxyz, int32_t* __restrict__ counts)
 {
     const int32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    if constexpr (kB) bin_one(bv.kps[bv.sys_of[i]], n, i, x, rank_tab, key, slot, cxyz, counts);
-    else bin_one(kp, n, i, x, rank_tab, key, slot, cxyz, counts);
+    const bool live = i < n;
+    int32_t r = -1;
+    if (live) {
+        if constexpr (kB) r = bin_one(bv.kps[bv.sys_of[i]], n, i, x, rank_tab, key, cxyz);
+        else r = bin_one(kp, n, i, x, rank_tab, key, cxyz);
+    }
+    const int lane = (int)lane_id();
+    const int32_t prev = __shfl_up(r, 1, kWave);
+    const bool head = live && (lane == 0 || prev != r);
+    // live lanes are a prefix of the wave; the first dead lane ends the last run
+    const uint64_t bounds = __ballot(head) | ~__ballot(live);
+    const uint64_t le = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
+    const int start = 63 - __clzll(bounds & le);
+    const uint64_t after = bounds & ~le;
+    const int end = after ? __ffsll((long long)after) - 1 : kWave;
+    int32_t base = 0;
+    if (head) base = atomicAdd(&counts[r], end - start);
+    base = __shfl(base, start, kWave);
+    if (live) slot[i] = base + (lane - start);
 }
 
 hipError_t launch_bin(const KParams& kp, const BatchView& bv, int32_t n, const double* x, const int32_t* rank_tab,
