@@ -29,6 +29,35 @@ HBM_PEAK_GBS = 8000.0
 PHASES = ["vv1", "reorder", "nlist", "forces", "vv2_stats"]
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_traffic_amphiphile16M.json")
+FORCE_SOURCES = [os.path.join(ROOT, "paper_1311_0402_amd", "csrc", f)
+                 for f in ("k_force.hip", "dpd_common.h", "dpd_launch.h")]
+
+
+def force_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in FORCE_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(precision):
+    """HBM bytes per force launch from the committed FETCH_SIZE / WRITE_SIZE
+    runs (calibrated against a plain copy), or None when there are none or
+    the force kernel's sources changed since they were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != force_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(precision)
+    return None if k is None else float(k["bytes_per_launch"])
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -303,8 +332,8 @@ def main():
     fb = head["force_bytes"]
     achieved = fb / (head["force_ms"] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": "forces", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "dominant_phase": dom}
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(head_name),
+                "algorithmic_bytes": fb, "dominant_phase": dom}
     line = {
         "metric": METRIC,
         "value": head["particle_steps_per_s"],

@@ -272,20 +272,27 @@ __device__ __forceinline__ void nlist_lane(const KParams& kp, int32_t i, int32_t
     int32_t cnt = 0;
     int32_t* __restrict__ out = kDirect ? index + offset[i] : slab + (int64_t)i * slab_k;
     const int32_t cap = kDirect ? INT_MAX : slab_k;
+    // Loads run one step ahead: the next cell's bounds are requested when a
+    // cell starts, and each candidate's position (the next cell's first one
+    // at a cell's last candidate) before the current one is tested.
+    int32_t j0 = cell_start[key[0] >> 5], j1 = cell_start[(key[0] >> 5) + 1];
+    float4 wn = xw[j0 < j1 ? j0 : i];
 #pragma unroll
     for (int q = 0; q < 27; ++q) {
-        const int32_t r = (int32_t)(key[q] >> 5);
+        int32_t j0n = 0, j1n = 0;
+        if (q + 1 < 27) {
+            const int32_t rn = (int32_t)(key[q + 1] >> 5);
+            j0n = cell_start[rn];
+            j1n = cell_start[rn + 1];
+        }
         const int c = (int)(key[q] & 31u);
-        const int32_t j0 = cell_start[r], j1 = cell_start[r + 1];
         // i's cell-relative position minus the cell's whole-cell offset
         const float qx = wi.x - (float)(c % 3 - 1) * cl0;
         const float qy = wi.y - (float)((c / 3) % 3 - 1) * cl1;
         const float qz = wi.z - (float)(c / 9 - 1) * cl2;
-        // the next candidate's load is issued before this one is tested
-        float4 wn = xw[j0 < j1 ? j0 : i];
         for (int32_t j = j0; j < j1; ++j) {
             const float4 wj = wn;
-            wn = xw[j + 1 < j1 ? j + 1 : j];
+            wn = xw[j + 1 < j1 ? j + 1 : (j0n < j1n ? j0n : i)];
             const float dx = qx - wj.x, dy = qy - wj.y, dz = qz - wj.z;
             const float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
             bool hit = j != i && r2 < kp.list_lo32;
@@ -295,6 +302,9 @@ __device__ __forceinline__ void nlist_lane(const KParams& kp, int32_t i, int32_t
                 ++cnt;
             }
         }
+        if (j0 == j1) wn = xw[j0n < j1n ? j0n : i];      // an empty cell issued nothing ahead
+        j0 = j0n;
+        j1 = j1n;
     }
     if (!kDirect) {
         offset[i] = cnt;

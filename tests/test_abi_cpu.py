@@ -195,3 +195,42 @@ def test_stencil_sorting_network_sorts_every_input():
         out = subprocess.run([exe], capture_output=True, text=True, check=True, timeout=300).stdout.split()
     assert int(out[0]) == 156
     assert int(out[1]) == 0
+
+
+def test_batch_create_validates_before_touching_memory():
+    """dpd_batch_create rejects bad batches before any copy or launch: sizes,
+    offsets, table size and alignment, bonds, fields systems must share."""
+    lib = _abi.lib()
+    assert lib.dpd_batch_table_bytes(0, 10) == 0
+    assert lib.dpd_batch_table_bytes(3, 2) == 0                 # fewer particles than systems
+    assert lib.dpd_batch_table_bytes(70000, 10 ** 6) == 0       # beyond the uint16 system map
+    need = lib.dpd_batch_table_bytes(3, 3000)
+    assert need > 0
+    ps = (_abi.dpd_params * 3)(*[_params().c() for _ in range(3)])
+    off = np.array([0, 1000, 2000, 3000], dtype=np.int64)
+    fake = 1 << 20                   # 256-aligned address that is never dereferenced
+    h = C.c_void_p()
+
+    def create(params, offsets, table=fake, nbytes=need):
+        return lib.dpd_batch_create(params, 3, offsets.ctypes.data, table, nbytes, None, C.byref(h))
+
+    assert create(ps, np.array([0, 1000, 1000, 3000], dtype=np.int64)) == _abi.DPD_EINVAL
+    assert b"empty" in lib.dpd_last_error()
+    assert create(ps, np.array([5, 1000, 2000, 3000], dtype=np.int64)) == _abi.DPD_EINVAL
+    assert create(ps, off, table=None) == _abi.DPD_EINVAL
+    assert create(ps, off, table=fake + 8) == _abi.DPD_EINVAL
+    assert create(ps, off, nbytes=need - 1) == _abi.DPD_ECAPACITY
+    bad = (_abi.dpd_params * 3)(*[_params().c() for _ in range(3)])
+    bad[1].dt = 0.02
+    assert create(bad, off) == _abi.DPD_EUNSUPPORTED
+    assert b"system 1" in lib.dpd_last_error()
+    partner = np.zeros(2000, dtype=np.int32)
+    bonded = (_abi.dpd_params * 3)(*[_params().c() for _ in range(3)])
+    bonded[2].bond_partner = partner.ctypes.data
+    assert create(bonded, off) == _abi.DPD_EUNSUPPORTED
+    small = (_abi.dpd_params * 3)(*[_params().c() for _ in range(3)])
+    small[0].box[1] = 2.0
+    assert create(small, off) == _abi.DPD_EINVAL
+    assert b"system 0" in lib.dpd_last_error()
+    assert h.value is None
+    lib.dpd_batch_destroy(None)
