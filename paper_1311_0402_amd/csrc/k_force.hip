@@ -344,14 +344,29 @@ __device__ __forceinline__ int cell_delta(int32_t ci, int32_t cj, int32_t n)
 
 // One pair in the mixed form.  xw[i] = (x, y, z offsets inside the cell,
 // tag bits), vw[i] = (predicted velocity, cell bits), both float4.
+// The operands of one mixed-form pair, loaded a batch ahead of their use.
+struct PairIn {
+    float4 pi, qi, pj, qj;
+    int32_t ti, tj;
+};
+
+__device__ __forceinline__ PairIn load_pair(const ForceArgs& a, const float4* __restrict__ xw,
+                                            const float4* __restrict__ vw, int32_t i, int32_t j)
+{
+    PairIn in;
+    in.pi = xw[i]; in.qi = vw[i];
+    in.pj = xw[j]; in.qj = vw[j];
+    in.ti = a.type[i]; in.tj = a.type[j];
+    return in;
+}
+
 template <int kWMode, typename Tab>
 __device__ __forceinline__ bool pair32(const KParams& P, const Tab* A, const Tab* G, const Tab* S,
-                                       const ForceArgs& a, const float4* __restrict__ xw,
-                                       const float4* __restrict__ vw, int64_t N, int32_t i, int32_t j,
+                                       const ForceArgs& a, const PairIn& in, int64_t N, int32_t i, int32_t j,
                                        uint64_t step, float& px, float& py, float& pz, float& pp)
 {
-    const float4 pi = xw[i], qi = vw[i];
-    const float4 pj = xw[j], qj = vw[j];
+    const float4 pi = in.pi, qi = in.qi;
+    const float4 pj = in.pj, qj = in.qj;
     const uint32_t ci = __float_as_uint(qi.w), cj = __float_as_uint(qj.w);
     const float ox = (float)cell_delta((int32_t)(ci & 1023u), (int32_t)(cj & 1023u), P.nc[0]) * P.cell_len32[0];
     const float oy = (float)cell_delta((int32_t)((ci >> 10) & 1023u), (int32_t)((cj >> 10) & 1023u), P.nc[1]) * P.cell_len32[1];
@@ -384,7 +399,7 @@ __device__ __forceinline__ bool pair32(const KParams& P, const Tab* A, const Tab
     const float wr = weight_r32(wc, kWMode, (float)P.s);
     const float wd = wr * wr;
     const float ev = ex * (qi.x - qj.x) + ey * (qi.y - qj.y) + ez * (qi.z - qj.z);
-    const int tp = a.type[i] * P.n_types + a.type[j];
+    const int tp = in.ti * P.n_types + in.tj;
     const float xi_ij = gauss32(pair_words(__float_as_uint(pi.w), __float_as_uint(pj.w), step, P.seed_lo, P.seed_hi));
     const float at = (float)A[tp], gt = (float)G[tp], st = (float)S[tp];
     const float phi = at * wc - gt * wd * ev + st * wr * xi_ij;
@@ -421,27 +436,42 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
     for (int32_t c = c_begin; c < c_end; ++c) {
         const PairJob jb = chunk_job<kB>(bv, a, c, ok, lane);
         float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, pe_row = 0.f, np_row = 0.f;
+        // software pipeline: the list entry two batches ahead and the pair
+        // operands one batch ahead are requested before a batch is evaluated
+        RowPos rp = row_pos(jb, jb.e0, lane);
+        int32_t i_cur = jb.i0 + rp.r;
+        int32_t j_cur = jb.e0 + lane < jb.e1 ? a.index[jb.e0 + lane] : i_cur;
+        int32_t j_nxt = jb.e0 + kWave + lane < jb.e1 ? a.index[jb.e0 + kWave + lane] : -1;
+        PairIn in = load_pair(a, xw, vw, i_cur, j_cur);
         for (int32_t eb = jb.e0; eb < jb.e1; eb += kWave) {
             const int32_t e = eb + lane;
             const bool valid = e < jb.e1;
-            const RowPos rp = row_pos(jb, eb, lane);
-            const int32_t r = rp.r;
-            const int32_t i = jb.i0 + r;
-            const int32_t j = valid ? a.index[e] : i;
+            const int32_t i = i_cur, j = j_cur;
+            const RowPos rp_cur = rp;
+            const PairIn cur = in;
+            // requests for the next batches
+            if (eb + kWave < jb.e1) {
+                rp = row_pos(jb, eb + kWave, lane);
+                i_cur = jb.i0 + rp.r;
+                j_cur = j_nxt >= 0 ? j_nxt : i_cur;
+                in = load_pair(a, xw, vw, i_cur, j_cur);
+                const int32_t e2 = eb + 2 * kWave + lane;
+                j_nxt = e2 < jb.e1 ? a.index[e2] : -1;
+            }
             float px = 0.f, py = 0.f, pz = 0.f, pp = 0.f, pn = 0.f;
             if (valid) {
                 bool hit;
                 if constexpr (kB) {
                     const KParams& P = bv.kps[bv.sys_of[i]];
-                    hit = pair32<kWMode>(P, P.a, P.g, P.srdt, a, xw, vw, N, i, j, step, px, py, pz, pp);
+                    hit = pair32<kWMode>(P, P.a, P.g, P.srdt, a, cur, N, i, j, step, px, py, pz, pp);
                 } else {
-                    hit = pair32<kWMode>(kp, s_a, s_g, s_s, a, xw, vw, N, i, j, step, px, py, pz, pp);
+                    hit = pair32<kWMode>(kp, s_a, s_g, s_s, a, cur, N, i, j, step, px, py, pz, pp);
                 }
                 pn = hit ? 1.f : 0.f;
                 np_tot += pn;
             }
             pe_tot += pp;
-            const int ss = rp.ss;
+            const int ss = rp_cur.ss;
             px = seg_scan(px, lane, ss);
             py = seg_scan(py, lane, ss);
             pz = seg_scan(pz, lane, ss);
