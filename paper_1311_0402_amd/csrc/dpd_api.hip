@@ -266,12 +266,13 @@ int enqueue_reorder(const Job& job, const WsLayout& L, void* ws, const dpd_state
 }
 
 int enqueue_nlist(const Job& job, const WsLayout& L, void* ws, const dpd_state* st,
-                  const dpd_cells* cells, const float* x32, dpd_nlist* nl, int32_t* d_status, hipStream_t s)
+                  const dpd_cells* cells, const float* x32, dpd_nlist* nl, int32_t* d_status, hipStream_t s,
+                  bool compact = true)
 {
     DPD_TRY(launch_nlist(job.kp, job.bv, job.n_cells, job.n_blocks, st->n, st->x, x32, cells->cell_xyz,
                          cells->cell_start, carve<int32_t>(ws, L.rank_tab), nl->offset, nl->index, nl->capacity,
                          carve<int32_t>(ws, L.slab), L.slab_k, carve<int32_t>(ws, L.slab_flag), d_status,
-                         carve<int32_t>(ws, L.scan_part), job.nlist_waves, job.nlist_kind, s),
+                         carve<int32_t>(ws, L.scan_part), job.nlist_waves, job.nlist_kind, compact, s),
             "neighbour list");
     return DPD_OK;
 }
@@ -406,6 +407,9 @@ int enqueue_batch_step(const dpd_batch* bt, const WsLayout& L, void* ws, int32_t
     a.fred_part = nullptr;
     a.status = d_status;
     a.grid = job.force_grid;
+    a.slab = carve<int32_t>(ws, L.slab);
+    a.slab_k = L.slab_k;
+    a.slab_flag = carve<int32_t>(ws, L.slab_flag);
     int rc;
     DPD_TRY(launch_vv1(kp, job.bv, n, st->x, st->v, st->f, st->tag, st->type, b.x, b.v, bvt, b.tag, b.type, s),
             "vv1");
@@ -517,6 +521,7 @@ int dpd_forces(const dpd_params* p, int32_t precision, const dpd_state* sorted, 
     a.fred_part = stats ? carve<double>(ws, L.fred_part) : nullptr;
     a.status = d_status;
     a.grid = 0;
+    a.slab = nullptr; a.slab_k = 0; a.slab_flag = nullptr;
     const BatchView none{};
     DPD_TRY(launch_forces(kp, none, precision, a, s), "forces");
     if (stats)
@@ -568,6 +573,9 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
     a.fred_part = carve<double>(ws, L.fred_part);
     a.status = d_status;
     a.grid = 0;
+    a.slab = carve<int32_t>(ws, L.slab);
+    a.slab_k = L.slab_k;
+    a.slab_flag = carve<int32_t>(ws, L.slab_flag);
     double* red_part = carve<double>(ws, L.red_part);
     double* fsum_part = carve<double>(ws, L.fsum_part);
     const bool mixed = precision == DPD_MIXED;
@@ -583,7 +591,9 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
         rc = enqueue_reorder(job, L, ws, &b, bvt, st, vt_sorted, cells, x32, mixed ? v32 : nullptr, s);
         if (rc) return rc;
         DPD_TRY(mark(k, 2), "event");
-        rc = enqueue_nlist(job, L, ws, st, cells, x32, nl, d_status, s);
+        // inside a call the force pass reads the builder's slab; the CSR list
+        // is written for the last step, which the caller sees
+        rc = enqueue_nlist(job, L, ws, st, cells, x32, nl, d_status, s, k == n_steps - 1);
         if (rc) return rc;
         DPD_TRY(mark(k, 3), "event");
         DPD_TRY(launch_forces(kp, job.bv, precision, a, s), "forces");
@@ -884,6 +894,7 @@ int dpd_batch_forces(const dpd_batch* b, int32_t precision, const dpd_state* sor
     a.f = f_out; a.pe = pe_out; a.npair = nullptr; a.fred_part = nullptr;
     a.status = d_status;
     a.grid = b->job.force_grid;
+    a.slab = nullptr; a.slab_k = 0; a.slab_flag = nullptr;
     DPD_TRY(launch_forces(b->job.kp, b->job.bv, precision, a, as_stream(stream)), "forces");
     return DPD_OK;
 }

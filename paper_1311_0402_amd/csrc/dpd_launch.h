@@ -72,7 +72,7 @@ hipError_t launch_nlist(const KParams& kp, const BatchView& bv, int32_t n_cells,
                         const double* x, const float* x32, const uint32_t* cell_xyz, const int32_t* cell_start,
                         const int32_t* rank_tab, int32_t* offset, int32_t* index, int64_t capacity, int32_t* slab,
                         int32_t slab_k, int32_t* flag, int32_t* status, int32_t* scan_part, int waves,
-                        int kind, hipStream_t s);
+                        int kind, bool compact, hipStream_t s);
 hipError_t launch_nlist_check(int32_t n, const int32_t* offset, int64_t capacity, int32_t* status,
                               hipStream_t s);
 
@@ -89,6 +89,9 @@ struct ForceArgs {
     double* fred_part;                            // [grid][2]: PE, pair count
     int32_t* status;                              // nullable
     int32_t grid;                                 // persistent workgroups (0 = force_blocks(n))
+    const int32_t* slab;                          // nullable: the list builder's slab (rows at i * slab_k),
+    int32_t slab_k;                               //   read instead of index while *slab_flag == 0
+    const int32_t* slab_flag;
 };
 hipError_t launch_forces(const KParams& kp, const BatchView& bv, int precision, const ForceArgs& a,
                          hipStream_t s);

@@ -196,6 +196,7 @@ __device__ __forceinline__ PairJob chunk_job(const BatchView& bv, const ForceArg
 // readlane, so no lane waits on a shuffle chain.
 struct RowPos {
     int32_t r, ss;
+    int32_t start;       // first entry of the row (absolute)
 };
 
 __device__ __forceinline__ RowPos row_pos(const PairJob& jb, int32_t eb, int lane)
@@ -204,13 +205,27 @@ __device__ __forceinline__ RowPos row_pos(const PairJob& jb, int32_t eb, int lan
     const int32_t ra = (int32_t)__popcll(__ballot(own && jb.rend <= eb));
     const int32_t rb = (int32_t)__popcll(__ballot(own && jb.rstart < eb + kWave));
     const int32_t e = eb + lane;
-    RowPos p{ra, 0};
+    RowPos p{ra, 0, __builtin_amdgcn_readlane(jb.rstart, ra < kWave ? ra : kWave - 1)};
     for (int32_t q = ra; q < rb; ++q) {
         const int32_t t = __builtin_amdgcn_readlane(jb.rend, q);
-        if (e >= t) { p.r = q + 1; p.ss = t - eb; }
+        if (e >= t) { p.r = q + 1; p.ss = t - eb; p.start = t; }
     }
     p.r = p.r < jb.ni ? p.r : jb.ni - 1;       // lanes past the last entry
     return p;
+}
+
+// Entry e of the chunk's rows: from the builder's fixed-width slab while it
+// holds every row (row i at slab[i * K]), else from the CSR list.
+__device__ __forceinline__ int32_t entry_at(const int32_t* __restrict__ slab, int32_t slab_k,
+                                            const ForceArgs& a, const PairJob& jb, const RowPos& rp, int32_t e)
+{
+    return slab ? slab[(int64_t)(jb.i0 + rp.r) * slab_k + (e - rp.start)] : a.index[e];
+}
+
+// the slab when it is usable for this launch, else null
+__device__ __forceinline__ const int32_t* usable_slab(const ForceArgs& a)
+{
+    return (a.slab && *a.slab_flag == 0) ? a.slab : nullptr;
 }
 
 // lane holding the last entry of this lane's row inside batch [eb, eb+64),
@@ -273,6 +288,7 @@ __global__ __launch_bounds__(kBlock) void k_force_fp64(KParams kp, BatchView bv,
     const bool want_pe = a.pe != nullptr;
     const bool want_np = a.npair != nullptr;
     double pe_tot = 0.0, np_tot = 0.0;
+    const int32_t* __restrict__ slab = usable_slab(a);
     for (int32_t c = c_begin; c < c_end; ++c) {
         const PairJob jb = chunk_job<kB>(bv, a, c, ok, lane);
         double fx = 0.0, fy = 0.0, fz = 0.0, pe_row = 0.0, np_row = 0.0;
@@ -282,7 +298,7 @@ __global__ __launch_bounds__(kBlock) void k_force_fp64(KParams kp, BatchView bv,
             const RowPos rp = row_pos(jb, eb, lane);
             const int32_t r = rp.r;
             const int32_t i = jb.i0 + r;
-            const int32_t j = valid ? a.index[e] : i;
+            const int32_t j = valid ? entry_at(slab, a.slab_k, a, jb, rp, e) : i;
             double px = 0.0, py = 0.0, pz = 0.0, pp = 0.0, pn = 0.0;
             if (valid) {
                 bool hit;
@@ -432,6 +448,7 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
     const bool want_np = a.npair != nullptr;
     const float4* __restrict__ xw = reinterpret_cast<const float4*>(a.x32);
     const float4* __restrict__ vw = reinterpret_cast<const float4*>(a.v32);
+    const int32_t* __restrict__ slab = usable_slab(a);
     double pe_tot = 0.0, np_tot = 0.0;
     for (int32_t c = c_begin; c < c_end; ++c) {
         const PairJob jb = chunk_job<kB>(bv, a, c, ok, lane);
@@ -439,9 +456,11 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
         // software pipeline: the list entry two batches ahead and the pair
         // operands one batch ahead are requested before a batch is evaluated
         RowPos rp = row_pos(jb, jb.e0, lane);
+        RowPos rp_nxt = row_pos(jb, jb.e0 + kWave, lane);
         int32_t i_cur = jb.i0 + rp.r;
-        int32_t j_cur = jb.e0 + lane < jb.e1 ? a.index[jb.e0 + lane] : i_cur;
-        int32_t j_nxt = jb.e0 + kWave + lane < jb.e1 ? a.index[jb.e0 + kWave + lane] : -1;
+        int32_t j_cur = jb.e0 + lane < jb.e1 ? entry_at(slab, a.slab_k, a, jb, rp, jb.e0 + lane) : i_cur;
+        int32_t j_nxt = jb.e0 + kWave + lane < jb.e1
+                            ? entry_at(slab, a.slab_k, a, jb, rp_nxt, jb.e0 + kWave + lane) : -1;
         PairIn in = load_pair(a, xw, vw, i_cur, j_cur);
         for (int32_t eb = jb.e0; eb < jb.e1; eb += kWave) {
             const int32_t e = eb + lane;
@@ -451,12 +470,17 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
             const PairIn cur = in;
             // requests for the next batches
             if (eb + kWave < jb.e1) {
-                rp = row_pos(jb, eb + kWave, lane);
+                rp = rp_nxt;
                 i_cur = jb.i0 + rp.r;
                 j_cur = j_nxt >= 0 ? j_nxt : i_cur;
                 in = load_pair(a, xw, vw, i_cur, j_cur);
                 const int32_t e2 = eb + 2 * kWave + lane;
-                j_nxt = e2 < jb.e1 ? a.index[e2] : -1;
+                if (eb + 2 * kWave < jb.e1) {
+                    rp_nxt = row_pos(jb, eb + 2 * kWave, lane);
+                    j_nxt = e2 < jb.e1 ? entry_at(slab, a.slab_k, a, jb, rp_nxt, e2) : -1;
+                } else {
+                    j_nxt = -1;
+                }
             }
             float px = 0.f, py = 0.f, pz = 0.f, pp = 0.f, pn = 0.f;
             if (valid) {

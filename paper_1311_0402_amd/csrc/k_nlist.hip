@@ -453,7 +453,7 @@ hipError_t launch_nlist(const KParams& kp, const BatchView& bv, int32_t n_cells,
                         const double* x, const float* x32, const uint32_t* cell_xyz, const int32_t* cell_start,
                         const int32_t* rank_tab, int32_t* offset, int32_t* index, int64_t capacity, int32_t* slab,
                         int32_t slab_k, int32_t* flag, int32_t* status, int32_t* scan_part, int waves,
-                        int kind, hipStream_t s)
+                        int kind, bool compact, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipError_t e;
@@ -469,9 +469,12 @@ hipError_t launch_nlist(const KParams& kp, const BatchView& bv, int32_t n_cells,
                                  slab, slab_k, flag, s);
     if ((e = launch_scan(offset, (int64_t)n + 1, scan_part, s)) != hipSuccess) return e;
     if ((e = launch_nlist_check(n, offset, capacity, status, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_nlist_compact, dim3(ceil_div(ceil_div(n, kWave), kWavesPerBlock)), dim3(kBlock), 0, s,
-                       n, (const int32_t*)offset, capacity, (const int32_t*)slab, slab_k, (const int32_t*)flag,
-                       index);
+    // without compaction the CSR index is left unwritten unless a row
+    // overflowed the slab (then the direct pass below writes it)
+    if (compact)
+        hipLaunchKernelGGL(k_nlist_compact, dim3(ceil_div(ceil_div(n, kWave), kWavesPerBlock)), dim3(kBlock), 0,
+                           s, n, (const int32_t*)offset, capacity, (const int32_t*)slab, slab_k,
+                           (const int32_t*)flag, index);
     if (lanes)
         launch_nlist_lanes<true>(waves, kp, bv, n, x, x32, cell_xyz, cell_start, rank_tab, offset, index, capacity,
                                  slab, slab_k, flag, s);

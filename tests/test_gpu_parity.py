@@ -238,6 +238,24 @@ def test_step_deterministic_and_resumable():
         np.testing.assert_array_equal(u, w)
 
 
+@pytest.mark.parametrize("precision", [P.FP64, P.MIXED])
+def test_steps_in_one_call_equal_single_step_calls(precision):
+    """Inside one dpd_step call the force pass reads the builder's slab (the
+    CSR list is written only for the last step); twelve steps in one call
+    equal twelve one-step calls bit for bit, lists included."""
+    s = di.amphiphile(n=6000, seed=21)
+    a = _sorted_system(s, precision)
+    a.step(12)
+    b = _sorted_system(s, precision)
+    for _ in range(12):
+        b.step(1)
+    torch.cuda.synchronize()
+    for u, w in zip(a.host_state(), b.host_state()):
+        np.testing.assert_array_equal(u, w)
+    for u, w in zip(a.host_nlist(), b.host_nlist()):
+        np.testing.assert_array_equal(u, w)
+
+
 def test_step_mixed_tracks_fp64():
     s = di.small_fluid(4)
     a = _sorted_system(s, precision=P.MIXED)
