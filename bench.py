@@ -74,6 +74,27 @@ def force_bytes(n, nnz, n_bond_ends, precision):
     return n * per + 4 * nnz + 8 * n + 28 * n_bond_ends
 
 
+def phase_bytes(n, nnz, n_bond_ends, precision, n_cells):
+    """Algorithmic HBM bytes of each phase of one step (each datum once).
+
+    vv1: R x, v, F (72), tag, type (5); W drifted x, v (48), tag, type (5).
+    reorder: bin R x 24, W key, slot, cell 12; scan ~8 per cell; place R key,
+    slot, tag 12, W tag, source 8; finalize R source, key 8, cell bounds 8,
+    in-cell tags 12, x, v 48, type, cell 5, W x, v 48, tag, type, cell,
+    perm, idx_of_tag 17, float4 copies 16 (+16 mixed).
+    nlist: R x32 16, cell 4, cell table and ranks 8 per cell; W row count 4,
+    4 per entry; scan 8.
+    forces: see force_bytes.  vv2: R v, F 48, W v 24.
+    """
+    mixed = precision == "mixed"
+    reorder = n * (36 + 20 + 8 + 8 + 12 + 53 + 65 + 16 + (16 if mixed else 0)) + 8 * n_cells
+    return {"vv1": 130.0 * n,
+            "reorder": float(reorder),
+            "nlist": float(n * (16 + 4 + 4 + 8) + 4 * nnz + 8 * n_cells),
+            "forces": float(force_bytes(n, nnz, n_bond_ends, precision)),
+            "vv2_stats": 72.0 * n}
+
+
 def run_precision(P, torch, sysd, precision, steps, warmup):
     import paper_1311_0402_amd as PK
     prec = PK.FP64 if precision == "fp64" else PK.MIXED
@@ -111,6 +132,8 @@ def run_precision(P, torch, sysd, precision, steps, warmup):
     pairs = float(r[:, 5].mean())
     ms = total_ms / steps
     fb = force_bytes(sysd.n, nnz, n_bond_ends, precision)
+    n_cells = int(np.prod(P.cell_grid(P.Params.like(sysd))))
+    pb = phase_bytes(sysd.n, nnz, n_bond_ends, precision, n_cells)
     out = {
         "ms_per_step": ms,
         "wall_s": wall,
@@ -122,6 +145,8 @@ def run_precision(P, torch, sysd, precision, steps, warmup):
         "phase_ms": {k: float(v) for k, v in zip(PHASES, phase_ms)},
         "force_ms": float(phase_ms[3]),
         "force_bytes": fb,
+        "phase_gbs": {k: pb[k] / (phase_ms[q] * 1e-3) / 1e9 for q, k in enumerate(PHASES)},
+        "phase_hbm_frac": {k: pb[k] / (phase_ms[q] * 1e-3) / 1e9 / HBM_PEAK_GBS for q, k in enumerate(PHASES)},
         "kbt_last": float(r[-1, 6]),
         "momentum_max": float(np.abs(r[:, :3]).max()),
     }

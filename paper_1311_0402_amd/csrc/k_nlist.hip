@@ -272,11 +272,22 @@ __device__ __forceinline__ void nlist_lane(const KParams& kp, int32_t i, int32_t
     int32_t cnt = 0;
     int32_t* __restrict__ out = kDirect ? index + offset[i] : slab + (int64_t)i * slab_k;
     const int32_t cap = kDirect ? INT_MAX : slab_k;
-    // Loads run one step ahead: the next cell's bounds are requested when a
-    // cell starts, and each candidate's position (the next cell's first one
-    // at a cell's last candidate) before the current one is tested.
+    // Loads run ahead of the tests: the next cell's bounds are requested when
+    // a cell starts, and candidates are tested two at a time while the two
+    // after them (crossing into the next cell at a cell's end) are in flight.
     int32_t j0 = cell_start[key[0] >> 5], j1 = cell_start[(key[0] >> 5) + 1];
-    float4 wn = xw[j0 < j1 ? j0 : i];
+    float4 wa = xw[j0 < j1 ? j0 : i];
+    float4 wb = xw[j0 + 1 < j1 ? j0 + 1 : i];
+    auto test = [&](int32_t j, const float4& wj, float qx, float qy, float qz) {
+        const float dx = qx - wj.x, dy = qy - wj.y, dz = qz - wj.z;
+        const float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
+        bool hit = j != i && r2 < kp.list_lo32;
+        if (j != i && !hit && r2 < kp.list_hi32) hit = exact_hit(kp, x, N, i, j);
+        if (hit) {
+            if (cnt < cap) out[cnt] = j;
+            ++cnt;
+        }
+    };
 #pragma unroll
     for (int q = 0; q < 27; ++q) {
         int32_t j0n = 0, j1n = 0;
@@ -290,19 +301,25 @@ __device__ __forceinline__ void nlist_lane(const KParams& kp, int32_t i, int32_t
         const float qx = wi.x - (float)(c % 3 - 1) * cl0;
         const float qy = wi.y - (float)((c / 3) % 3 - 1) * cl1;
         const float qz = wi.z - (float)(c / 9 - 1) * cl2;
-        for (int32_t j = j0; j < j1; ++j) {
-            const float4 wj = wn;
-            wn = xw[j + 1 < j1 ? j + 1 : (j0n < j1n ? j0n : i)];
-            const float dx = qx - wj.x, dy = qy - wj.y, dz = qz - wj.z;
-            const float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
-            bool hit = j != i && r2 < kp.list_lo32;
-            if (j != i && !hit && r2 < kp.list_hi32) hit = exact_hit(kp, x, N, i, j);
-            if (hit) {
-                if (cnt < cap) out[cnt] = j;
-                ++cnt;
-            }
+        // position p of the candidate sequence: this cell, then the next
+        auto ahead = [&](int32_t p) {
+            if (p < j1) return p;
+            const int32_t pn = j0n + (p - j1);
+            return pn < j1n ? pn : i;
+        };
+        for (int32_t j = j0; j < j1; j += 2) {
+            const float4 w0 = wa, w1 = wb;
+            const bool two = j + 1 < j1;
+            const int32_t base = two ? j + 2 : j + 1;
+            wa = xw[ahead(base)];
+            wb = xw[ahead(base + 1)];
+            test(j, w0, qx, qy, qz);
+            if (two) test(j + 1, w1, qx, qy, qz);
         }
-        if (j0 == j1) wn = xw[j0n < j1n ? j0n : i];      // an empty cell issued nothing ahead
+        if (j0 == j1) {                        // an empty cell issued nothing ahead
+            wa = xw[j0n < j1n ? j0n : i];
+            wb = xw[j0n + 1 < j1n ? j0n + 1 : i];
+        }
         j0 = j0n;
         j1 = j1n;
     }

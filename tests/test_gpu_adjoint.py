@@ -84,6 +84,11 @@ def _full_size_setup(s_exp):
     v0 = torch.tensor(s.v, device=dev)
     L0 = A.force_matching_loss(a, g, x0, v0, spec, T)
     L0.backward()
+    # a seeded direction moving every coordinate by +-1 (scaled by h below);
+    # coordinates within 1e-5 of a box face stay put, so x +- h u stays in [0, L)
+    u = np.random.default_rng(11).choice([-1.0, 1.0], size=s.x.shape)
+    box = np.asarray(s.box, dtype=np.float64)[:, None]
+    u[(s.x < 1e-5) | (s.x > box - 1e-5)] = 0.0
 
     def loss(aa, gg, xx=None):
         with torch.no_grad():
@@ -92,12 +97,8 @@ def _full_size_setup(s_exp):
 
     grads = {"a_AB": a.grad[0, 1].item(),
              # all three independent gamma entries moved together
-             "gamma": float((g.grad.numpy() * np.array([[1, 1], [0, 1]])).sum())}
-    rng = np.random.default_rng(11)
-    picks = [(int(rng.integers(0, 3)), int(rng.integers(0, s.n))) for _ in range(3)]
-    gx = x0.grad.cpu().numpy()
-    for d, i in picks:
-        grads[f"x[{d},{i}]"] = float(gx[d, i])
+             "gamma": float((g.grad.numpy() * np.array([[1, 1], [0, 1]])).sum()),
+             "x . u": float((x0.grad.cpu().numpy() * u).sum())}
     da = np.array([[0.0, 1.0], [1.0, 0.0]])
     dg = np.full((2, 2), 1.0)
 
@@ -106,40 +107,66 @@ def _full_size_setup(s_exp):
             return (loss(s.a + h * da, s.gamma) - loss(s.a - h * da, s.gamma)) / (2 * h)
         if name == "gamma":
             return (loss(s.a, s.gamma + h * dg) - loss(s.a, s.gamma - h * dg)) / (2 * h)
-        d, i = picks[[f"x[{d},{i}]" for d, i in picks].index(name)]
-        xp = s.x.copy(); xp[d, i] += h
-        xm = s.x.copy(); xm[d, i] -= h
-        return (loss(s.a, s.gamma, xp) - loss(s.a, s.gamma, xm)) / (2 * h)
+        return (loss(s.a, s.gamma, s.x + h * u) - loss(s.a, s.gamma, s.x - h * u)) / (2 * h)
 
     return L0.item(), grads, fd
 
 
 def test_force_matching_full_size_finite_differences_linear_weight():
     """The 512,000-particle A/B mixture, 50 steps, checkpoints every 10, with
-    w_R = 1 - r/r_c: every pair force is Lipschitz in r, so the central
-    difference at h = 1e-6 is accurate to O(h) and must agree closely."""
+    w_R = 1 - r/r_c: every pair force is Lipschitz in r, so central
+    differences at h = 1e-6 are accurate to O(h): a_AB, gamma and the
+    derivative along a +-1 direction over all positions agree to 1e-5
+    relative plus the loss's rounding noise."""
     L0, grads, fd = _full_size_setup(1.0)
     print(f"loss {L0:.10e}")
     for name, gval in grads.items():
         f = fd(name, 1e-6)
         print(f"{name}: grad {gval:.10e} fd {f:.10e} rel {abs(gval - f) / abs(gval):.2e}", flush=True)
-        assert abs(gval - f) <= 2e-6 * abs(gval) + _fd_noise(L0, 1e-6), name
+        assert abs(gval - f) <= 1e-5 * abs(gval) + _fd_noise(L0, 1e-6), name
 
 
 def test_force_matching_full_size_finite_differences_sqrt_weight():
-    """The same check with w_R = (1 - r/r_c)^(1/2).  Its derivative diverges
-    as r -> r_c, so the central difference carries an error that falls only
-    like h^(1/2) (from pairs within about h of the cutoff).  The check: the
-    difference at h = 1e-6 agrees to 1e-3, and shrinking h sixteenfold shrinks
-    the disagreement at least twofold, unless it is already below 1e-5."""
+    """The same with w_R = (1 - r/r_c)^(1/2), whose derivative diverges as
+    r -> r_c: pairs within about the perturbation of the cutoff make the
+    central difference wrong by an amount that does not shrink reliably with
+    h (at this size and length there are always some).  The difference is a
+    sanity bound here (1e-2); the precise check at this weight is the
+    oracle's gradient (next test)."""
     L0, grads, fd = _full_size_setup(0.5)
     print(f"loss {L0:.10e}")
-    for name, gval in grads.items():
+    for name in ("a_AB", "gamma"):
+        gval = grads[name]
         f1 = fd(name, 1e-6)
-        f2 = fd(name, 1e-6 / 16)
-        e1, e2 = abs(gval - f1) / abs(gval), abs(gval - f2) / abs(gval)
-        print(f"{name}: grad {gval:.10e} fd(1e-6) {f1:.10e} rel {e1:.2e}  fd(6.25e-8) {f2:.10e} rel {e2:.2e}",
-              flush=True)
-        n2 = _fd_noise(L0, 1e-6 / 16) / abs(gval)
-        assert e1 < 1e-3 + 16 * n2, name
-        assert e2 < 1e-5 + n2 or e2 < 0.5 * e1 + n2, name
+        e1 = abs(gval - f1) / abs(gval)
+        print(f"{name}: grad {gval:.10e} fd(1e-6) {f1:.10e} rel {e1:.2e}", flush=True)
+        assert e1 < 1e-2, name
+
+
+def test_force_matching_full_size_matches_oracle_gradient():
+    """The full configuration (512,000 particles, 50 steps, checkpoints every
+    10, w_R = (1 - r/r_c)^(1/2)): loss and gradients against the oracle's own
+    reverse sweep, targets from an oracle trajectory."""
+    s = di.binary_mixture(n=512_000, seed=6)
+    K, C = 50, 10
+    a_ref = float(np.random.default_rng(7).uniform(25.0, 50.0))
+    ref = oracle.trajectory(s, s.x, s.v, K, a=np.array([[25.0, a_ref], [a_ref, 25.0]]))
+    T = np.stack([ref[k][2] for k in range(1, K + 1)])
+    del ref
+    print("oracle targets done", flush=True)
+    L_ref, ga_ref, gg_ref, gx_ref, gv_ref = oracle.force_matching_grad(s, s.x, s.v, K, T)
+    print("oracle gradient done", flush=True)
+    dev = "cuda"
+    a = torch.tensor(s.a, dtype=torch.float64, requires_grad=True)
+    g = torch.tensor(s.gamma, dtype=torch.float64, requires_grad=True)
+    x0 = torch.tensor(s.x, device=dev, requires_grad=True)
+    v0 = torch.tensor(s.v, device=dev, requires_grad=True)
+    loss = A.force_matching_loss(a, g, x0, v0, _spec(s, K, C), torch.tensor(T, device=dev))
+    loss.backward()
+    print(f"loss {loss.item():.12e} oracle {L_ref:.12e}; a_AB {a.grad[0, 1].item():.12e} "
+          f"oracle {ga_ref[0, 1]:.12e}", flush=True)
+    np.testing.assert_allclose(loss.item(), L_ref, rtol=1e-9)
+    np.testing.assert_allclose(a.grad.numpy(), ga_ref, rtol=1e-7)
+    np.testing.assert_allclose(g.grad.numpy(), gg_ref, rtol=1e-7)
+    np.testing.assert_allclose(x0.grad.cpu().numpy(), gx_ref, rtol=1e-6, atol=1e-6 * np.abs(gx_ref).max())
+    np.testing.assert_allclose(v0.grad.cpu().numpy(), gv_ref, rtol=1e-6, atol=1e-6 * np.abs(gv_ref).max())

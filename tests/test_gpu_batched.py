@@ -120,7 +120,11 @@ def test_batch_steps_equal_single_systems(precision):
         # momentum sums cancel: compare them on the scale of sum |v|
         vscale = np.abs(v).sum()
         np.testing.assert_allclose(red[:, k, :3], r1[:, :3], rtol=0, atol=1e-12 * vscale)
-        np.testing.assert_allclose(red[:, k, 3:7], r1[:, 3:7], rtol=1e-12)
+        np.testing.assert_allclose(red[:, k, [3, 5, 6]], r1[:, [3, 5, 6]], rtol=1e-12)
+        # potential energy: FP64 pair terms sum to 1e-12 either way; in the
+        # mixed form each pair's share is an FP32 value and the batch adds
+        # FP32 row sums where the single run adds the pair values in FP64
+        np.testing.assert_allclose(red[:, k, 4], r1[:, 4], rtol=1e-12 if precision == P.FP64 else 2e-6)
 
 
 def test_graph_replay_equals_eager_and_is_resumable():

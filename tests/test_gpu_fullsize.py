@@ -52,6 +52,12 @@ def test_fullsize_rows_and_forces_after_a_step(full, precision):
     s = full
     sim = _loaded(s, precision)
     sim.step(1)
+    # re-bin the stepped (already sorted) state so the FP32 copies carry its
+    # current velocities, then rebuild the list and evaluate at the step's
+    # counter, as the oracle does from the same arrays
+    st = sim.state
+    sim.reorder_from(P.State(st.x.clone(), st.v.clone(), st.f.clone(), st.tag.clone(), st.type.clone()))
+    sim.rebuild()
     sim.compute_forces(1)
     torch.cuda.synchronize()
     sim.check_status()
