@@ -109,6 +109,33 @@ __device__ __forceinline__ void add_bonds_body(const KParams& kp, const ForceArg
 
 constexpr int kChunk = kWave;
 
+// Chunks of this wave in the persistent grid.  Each XCD takes a contiguous
+// share of the chunks (in proportion to its waves) and its waves take them
+// interleaved (wave j of the XCD: j, j + W, j + 2W, ...), so at any moment
+// an XCD's waves work on neighbouring chunks and the j-side gathers of one
+// wave find the neighbourhood its siblings already brought into that XCD's
+// L2.  Workgroups are dealt to the XCDs round-robin by their index.
+struct ChunkWalk {
+    int32_t first, end, stride;
+};
+
+__device__ __forceinline__ ChunkWalk chunk_walk(int32_t n_chunks)
+{
+    const int32_t groups = (int32_t)gridDim.x, p = (int32_t)blockIdx.x;
+    const int32_t q = groups / 8, r = groups % 8;
+    const int32_t xcd = p % 8, k = p / 8;
+    const int32_t g0 = xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q;   // the XCD's first group
+    const int32_t gx = q + (xcd < r ? 1 : 0);                                  // groups on the XCD
+    const int32_t wpg = kBlock / kWave;
+    const int64_t waves = (int64_t)groups * wpg;
+    const int64_t w0 = (int64_t)g0 * wpg, wx = (int64_t)gx * wpg;
+    ChunkWalk cw;
+    cw.first = (int32_t)(n_chunks * w0 / waves) + k * wpg + (int32_t)(threadIdx.x / kWave);
+    cw.end = (int32_t)(n_chunks * (w0 + wx) / waves);
+    cw.stride = (int32_t)wx;
+    return cw;
+}
+
 // DPP lane moves (GFX9 data-parallel primitives): row_shr:d shifts inside
 // each 16-lane row, row_bcast:15 / row_bcast:31 hand lane 15 of a row (lane
 // 31) to the next row(s).  Lanes without a source read 0.
@@ -279,9 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_force_fp64(KParams kp, BatchView bv,
         __syncthreads();
     }
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
-    const int64_t w = (int64_t)xcd_logical_id(blockIdx.x, gridDim.x) * (kBlock / kWave) + threadIdx.x / kWave;
-    const int32_t c_begin = (int32_t)(n_chunks * w / waves), c_end = (int32_t)(n_chunks * (w + 1) / waves);
+    const ChunkWalk cw = chunk_walk(n_chunks);
     const int64_t N = a.n;
     const uint64_t step = (a.d_step ? *a.d_step : 0ull) + a.step_add;
     const bool ok = (int64_t)a.offset[a.n] <= a.capacity;
@@ -289,7 +314,7 @@ __global__ __launch_bounds__(kBlock) void k_force_fp64(KParams kp, BatchView bv,
     const bool want_np = a.npair != nullptr;
     double pe_tot = 0.0, np_tot = 0.0;
     const int32_t* __restrict__ slab = usable_slab(a);
-    for (int32_t c = c_begin; c < c_end; ++c) {
+    for (int32_t c = cw.first; c < cw.end; c += cw.stride) {
         const PairJob jb = chunk_job<kB>(bv, a, c, ok, lane);
         double fx = 0.0, fy = 0.0, fz = 0.0, pe_row = 0.0, np_row = 0.0;
         for (int32_t eb = jb.e0; eb < jb.e1; eb += kWave) {
@@ -438,9 +463,7 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
         __syncthreads();
     }
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
-    const int64_t w = (int64_t)xcd_logical_id(blockIdx.x, gridDim.x) * (kBlock / kWave) + threadIdx.x / kWave;
-    const int32_t c_begin = (int32_t)(n_chunks * w / waves), c_end = (int32_t)(n_chunks * (w + 1) / waves);
+    const ChunkWalk cw = chunk_walk(n_chunks);
     const int64_t N = a.n;
     const uint64_t step = (a.d_step ? *a.d_step : 0ull) + a.step_add;
     const bool ok = (int64_t)a.offset[a.n] <= a.capacity;
@@ -450,7 +473,7 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
     const float4* __restrict__ vw = reinterpret_cast<const float4*>(a.v32);
     const int32_t* __restrict__ slab = usable_slab(a);
     double pe_tot = 0.0, np_tot = 0.0;
-    for (int32_t c = c_begin; c < c_end; ++c) {
+    for (int32_t c = cw.first; c < cw.end; c += cw.stride) {
         const PairJob jb = chunk_job<kB>(bv, a, c, ok, lane);
         float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, pe_row = 0.f, np_row = 0.f;
         // software pipeline: the list entry two batches ahead and the pair
