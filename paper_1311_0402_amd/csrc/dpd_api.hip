@@ -410,6 +410,7 @@ int enqueue_batch_step(const dpd_batch* bt, const WsLayout& L, void* ws, int32_t
     a.slab = carve<int32_t>(ws, L.slab);
     a.slab_k = L.slab_k;
     a.slab_flag = carve<int32_t>(ws, L.slab_flag);
+    a.slab_coded = nlist_slab_coded(job.nlist_kind, cells->cell_xyz, job.n_cells, n) ? 1 : 0;
     int rc;
     DPD_TRY(launch_vv1(kp, job.bv, n, st->x, st->v, st->f, st->tag, st->type, b.x, b.v, bvt, b.tag, b.type, s),
             "vv1");
@@ -521,7 +522,7 @@ int dpd_forces(const dpd_params* p, int32_t precision, const dpd_state* sorted, 
     a.fred_part = stats ? carve<double>(ws, L.fred_part) : nullptr;
     a.status = d_status;
     a.grid = 0;
-    a.slab = nullptr; a.slab_k = 0; a.slab_flag = nullptr;
+    a.slab = nullptr; a.slab_k = 0; a.slab_flag = nullptr; a.slab_coded = 0;
     const BatchView none{};
     DPD_TRY(launch_forces(kp, none, precision, a, s), "forces");
     if (stats)
@@ -576,6 +577,7 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
     a.slab = carve<int32_t>(ws, L.slab);
     a.slab_k = L.slab_k;
     a.slab_flag = carve<int32_t>(ws, L.slab_flag);
+    a.slab_coded = nlist_slab_coded(job.nlist_kind, cells->cell_xyz, job.n_cells, n) ? 1 : 0;
     double* red_part = carve<double>(ws, L.red_part);
     double* fsum_part = carve<double>(ws, L.fsum_part);
     const bool mixed = precision == DPD_MIXED;
@@ -894,7 +896,7 @@ int dpd_batch_forces(const dpd_batch* b, int32_t precision, const dpd_state* sor
     a.f = f_out; a.pe = pe_out; a.npair = nullptr; a.fred_part = nullptr;
     a.status = d_status;
     a.grid = b->job.force_grid;
-    a.slab = nullptr; a.slab_k = 0; a.slab_flag = nullptr;
+    a.slab = nullptr; a.slab_k = 0; a.slab_flag = nullptr; a.slab_coded = 0;
     DPD_TRY(launch_forces(b->job.kp, b->job.bv, precision, a, as_stream(stream)), "forces");
     return DPD_OK;
 }

@@ -65,6 +65,12 @@ hipError_t launch_finalize(const KParams& kp, const BatchView& bv, int32_t n, co
 
 // ---- neighbour list (k_nlist.hip) ----
 int32_t nlist_slab_width(double density, double rl2);
+// Slab entries of the lane builder, when n < 2^26: bits 0..25 hold j, bits
+// 26..31 the offset of j's cell from i's cell, (dx+1) | (dy+1) << 2 |
+// (dz+1) << 4, so the mixed force pass needs no cell arithmetic.
+constexpr int kSlabCodeShift = 26;
+constexpr int32_t kSlabJMask = (1 << kSlabCodeShift) - 1;
+
 // whole list build: row sizes + slab rows, scan, capacity check, compaction
 // (or the direct pass when a row overflowed its slab row); n_blocks counts
 // the 2x2x2 cell blocks of all systems
@@ -73,6 +79,8 @@ hipError_t launch_nlist(const KParams& kp, const BatchView& bv, int32_t n_cells,
                         const int32_t* rank_tab, int32_t* offset, int32_t* index, int64_t capacity, int32_t* slab,
                         int32_t slab_k, int32_t* flag, int32_t* status, int32_t* scan_part, int waves,
                         int kind, bool compact, hipStream_t s);
+// whether that build leaves coded slab entries (the lane builder for n < 2^26)
+bool nlist_slab_coded(int kind, const uint32_t* cell_xyz, int32_t n_cells, int32_t n);
 hipError_t launch_nlist_check(int32_t n, const int32_t* offset, int64_t capacity, int32_t* status,
                               hipStream_t s);
 
@@ -92,6 +100,7 @@ struct ForceArgs {
     const int32_t* slab;                          // nullable: the list builder's slab (rows at i * slab_k),
     int32_t slab_k;                               //   read instead of index while *slab_flag == 0
     const int32_t* slab_flag;
+    int32_t slab_coded;                           // slab entries carry the stencil offset (see below)
 };
 hipError_t launch_forces(const KParams& kp, const BatchView& bv, int precision, const ForceArgs& a,
                          hipStream_t s);

@@ -183,6 +183,31 @@ __device__ __forceinline__ T seg_scan(T v, int lane, int ss)
     return v;
 }
 
+// Inclusive prefix sum over all 64 lanes (no segments): shifts inside the
+// 16-lane rows, then the row tails carried across rows.  Lanes without a
+// source add 0, so no selects are needed.  A row of the batch is then the
+// difference of two prefix values.
+template <typename T>
+__device__ __forceinline__ T wave_prefix(T v)
+{
+    v += dpp_move<kDppRowShr | 1, 0xF>(v);
+    v += dpp_move<kDppRowShr | 2, 0xF>(v);
+    v += dpp_move<kDppRowShr | 4, 0xF>(v);
+    v += dpp_move<kDppRowShr | 8, 0xF>(v);
+    v += dpp_move<kDppBcast15, 0xA>(v);
+    v += dpp_move<kDppBcast31, 0xC>(v);
+    return v;
+}
+
+// this row's part of batch [eb, eb+64) from the prefix values: lanes
+// [first, last] (last = row_end_lane), zero when the row has no entry there
+__device__ __forceinline__ float row_part(float prefix, int32_t first, int32_t last)
+{
+    const float hi = __shfl(prefix, last < 0 ? 0 : last, kWave);
+    const float lo = __shfl(prefix, first > 0 ? first - 1 : 0, kWave);
+    return last < 0 ? 0.f : (first > 0 ? hi - lo : hi);
+}
+
 struct PairJob {
     int32_t i0, ni;      // first particle of the chunk, particles in it
     int32_t e0, e1;      // its CSR entries
@@ -247,6 +272,17 @@ __device__ __forceinline__ int32_t entry_at(const int32_t* __restrict__ slab, in
                                             const ForceArgs& a, const PairJob& jb, const RowPos& rp, int32_t e)
 {
     return slab ? slab[(int64_t)(jb.i0 + rp.r) * slab_k + (e - rp.start)] : a.index[e];
+}
+
+// a slab entry's particle index and stencil code (-1: not coded)
+__device__ __forceinline__ int32_t entry_j(int32_t raw, bool coded)
+{
+    return coded ? (raw & kSlabJMask) : raw;
+}
+
+__device__ __forceinline__ int32_t entry_code(int32_t raw, bool coded)
+{
+    return coded ? (int32_t)((uint32_t)raw >> kSlabCodeShift) : -1;
 }
 
 // the slab when it is usable for this launch, else null
@@ -314,6 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_force_fp64(KParams kp, BatchView bv,
     const bool want_np = a.npair != nullptr;
     double pe_tot = 0.0, np_tot = 0.0;
     const int32_t* __restrict__ slab = usable_slab(a);
+    const bool coded = slab && a.slab_coded;
     for (int32_t c = cw.first; c < cw.end; c += cw.stride) {
         const PairJob jb = chunk_job<kB>(bv, a, c, ok, lane);
         double fx = 0.0, fy = 0.0, fz = 0.0, pe_row = 0.0, np_row = 0.0;
@@ -323,7 +360,7 @@ __global__ __launch_bounds__(kBlock) void k_force_fp64(KParams kp, BatchView bv,
             const RowPos rp = row_pos(jb, eb, lane);
             const int32_t r = rp.r;
             const int32_t i = jb.i0 + r;
-            const int32_t j = valid ? entry_at(slab, a.slab_k, a, jb, rp, e) : i;
+            const int32_t j = valid ? entry_j(entry_at(slab, a.slab_k, a, jb, rp, e), coded) : i;
             double px = 0.0, py = 0.0, pz = 0.0, pp = 0.0, pn = 0.0;
             if (valid) {
                 bool hit;
@@ -404,14 +441,24 @@ __device__ __forceinline__ PairIn load_pair(const ForceArgs& a, const float4* __
 template <int kWMode, typename Tab>
 __device__ __forceinline__ bool pair32(const KParams& P, const Tab* A, const Tab* G, const Tab* S,
                                        const ForceArgs& a, const PairIn& in, int64_t N, int32_t i, int32_t j,
-                                       uint64_t step, float& px, float& py, float& pz, float& pp)
+                                       int32_t code, bool coded, uint64_t step, float& px, float& py, float& pz,
+                                       float& pp)
 {
     const float4 pi = in.pi, qi = in.qi;
     const float4 pj = in.pj, qj = in.qj;
-    const uint32_t ci = __float_as_uint(qi.w), cj = __float_as_uint(qj.w);
-    const float ox = (float)cell_delta((int32_t)(ci & 1023u), (int32_t)(cj & 1023u), P.nc[0]) * P.cell_len32[0];
-    const float oy = (float)cell_delta((int32_t)((ci >> 10) & 1023u), (int32_t)((cj >> 10) & 1023u), P.nc[1]) * P.cell_len32[1];
-    const float oz = (float)cell_delta((int32_t)(ci >> 20), (int32_t)(cj >> 20), P.nc[2]) * P.cell_len32[2];
+    // whole-cell offset of i's cell from j's: from the list entry's stencil
+    // code when it has one, else from the two cells' coordinates
+    float ox, oy, oz;
+    if (coded) {
+        ox = (float)(1 - (code & 3)) * P.cell_len32[0];
+        oy = (float)(1 - ((code >> 2) & 3)) * P.cell_len32[1];
+        oz = (float)(1 - (code >> 4)) * P.cell_len32[2];
+    } else {
+        const uint32_t ci = __float_as_uint(qi.w), cj = __float_as_uint(qj.w);
+        ox = (float)cell_delta((int32_t)(ci & 1023u), (int32_t)(cj & 1023u), P.nc[0]) * P.cell_len32[0];
+        oy = (float)cell_delta((int32_t)((ci >> 10) & 1023u), (int32_t)((cj >> 10) & 1023u), P.nc[1]) * P.cell_len32[1];
+        oz = (float)cell_delta((int32_t)(ci >> 20), (int32_t)(cj >> 20), P.nc[2]) * P.cell_len32[2];
+    }
     const float dx = (pi.x - pj.x) + ox;
     const float dy = (pi.y - pj.y) + oy;
     const float dz = (pi.z - pj.z) + oz;
@@ -472,6 +519,7 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
     const float4* __restrict__ xw = reinterpret_cast<const float4*>(a.x32);
     const float4* __restrict__ vw = reinterpret_cast<const float4*>(a.v32);
     const int32_t* __restrict__ slab = usable_slab(a);
+    const bool coded = slab && a.slab_coded;
     double pe_tot = 0.0, np_tot = 0.0;
     for (int32_t c = cw.first; c < cw.end; c += cw.stride) {
         const PairJob jb = chunk_job<kB>(bv, a, c, ok, lane);
@@ -481,28 +529,29 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
         RowPos rp = row_pos(jb, jb.e0, lane);
         RowPos rp_nxt = row_pos(jb, jb.e0 + kWave, lane);
         int32_t i_cur = jb.i0 + rp.r;
-        int32_t j_cur = jb.e0 + lane < jb.e1 ? entry_at(slab, a.slab_k, a, jb, rp, jb.e0 + lane) : i_cur;
-        int32_t j_nxt = jb.e0 + kWave + lane < jb.e1
-                            ? entry_at(slab, a.slab_k, a, jb, rp_nxt, jb.e0 + kWave + lane) : -1;
+        const int32_t raw0 = jb.e0 + lane < jb.e1 ? entry_at(slab, a.slab_k, a, jb, rp, jb.e0 + lane) : i_cur;
+        int32_t j_cur = entry_j(raw0, coded), code_cur = entry_code(raw0, coded);
+        int32_t raw_nxt = jb.e0 + kWave + lane < jb.e1
+                              ? entry_at(slab, a.slab_k, a, jb, rp_nxt, jb.e0 + kWave + lane) : 0;
+        bool has_nxt = jb.e0 + kWave + lane < jb.e1;
         PairIn in = load_pair(a, xw, vw, i_cur, j_cur);
         for (int32_t eb = jb.e0; eb < jb.e1; eb += kWave) {
             const int32_t e = eb + lane;
             const bool valid = e < jb.e1;
-            const int32_t i = i_cur, j = j_cur;
-            const RowPos rp_cur = rp;
+            const int32_t i = i_cur, j = j_cur, code = code_cur;
             const PairIn cur = in;
             // requests for the next batches
             if (eb + kWave < jb.e1) {
                 rp = rp_nxt;
                 i_cur = jb.i0 + rp.r;
-                j_cur = j_nxt >= 0 ? j_nxt : i_cur;
+                j_cur = has_nxt ? entry_j(raw_nxt, coded) : i_cur;
+                code_cur = entry_code(raw_nxt, coded);
                 in = load_pair(a, xw, vw, i_cur, j_cur);
                 const int32_t e2 = eb + 2 * kWave + lane;
+                has_nxt = e2 < jb.e1;
                 if (eb + 2 * kWave < jb.e1) {
                     rp_nxt = row_pos(jb, eb + 2 * kWave, lane);
-                    j_nxt = e2 < jb.e1 ? entry_at(slab, a.slab_k, a, jb, rp_nxt, e2) : -1;
-                } else {
-                    j_nxt = -1;
+                    raw_nxt = has_nxt ? entry_at(slab, a.slab_k, a, jb, rp_nxt, e2) : 0;
                 }
             }
             float px = 0.f, py = 0.f, pz = 0.f, pp = 0.f, pn = 0.f;
@@ -510,25 +559,26 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
                 bool hit;
                 if constexpr (kB) {
                     const KParams& P = bv.kps[bv.sys_of[i]];
-                    hit = pair32<kWMode>(P, P.a, P.g, P.srdt, a, cur, N, i, j, step, px, py, pz, pp);
+                    hit = pair32<kWMode>(P, P.a, P.g, P.srdt, a, cur, N, i, j, code, coded, step, px, py, pz, pp);
                 } else {
-                    hit = pair32<kWMode>(kp, s_a, s_g, s_s, a, cur, N, i, j, step, px, py, pz, pp);
+                    hit = pair32<kWMode>(kp, s_a, s_g, s_s, a, cur, N, i, j, code, coded, step, px, py, pz, pp);
                 }
                 pn = hit ? 1.f : 0.f;
                 np_tot += pn;
             }
             pe_tot += pp;
-            const int ss = rp_cur.ss;
-            px = seg_scan(px, lane, ss);
-            py = seg_scan(py, lane, ss);
-            pz = seg_scan(pz, lane, ss);
-            if (want_pe) pp = seg_scan(pp, lane, ss);
-            if (want_np) pn = seg_scan(pn, lane, ss);
+            // the FP32 prefix values stay within a few hundred, so a row's
+            // part, their difference, carries an error of a few ulp of that
+            px = wave_prefix(px);
+            py = wave_prefix(py);
+            pz = wave_prefix(pz);
+            if (want_pe) pp = wave_prefix(pp);
+            if (want_np) pn = wave_prefix(pn);
             const int32_t src = row_end_lane(jb, eb);
-            const int32_t sl = src < 0 ? 0 : src;
-            const float tx = __shfl(px, sl, kWave), ty = __shfl(py, sl, kWave), tz = __shfl(pz, sl, kWave);
-            const float tp2 = want_pe ? __shfl(pp, sl, kWave) : 0.f;
-            const float tn = want_np ? __shfl(pn, sl, kWave) : 0.f;
+            const int32_t first = jb.rstart - eb;
+            const float tx = row_part(px, first, src), ty = row_part(py, first, src), tz = row_part(pz, first, src);
+            const float tp2 = want_pe ? row_part(pp, first, src) : 0.f;
+            const float tn = want_np ? row_part(pn, first, src) : 0.f;
             if (src >= 0) {
                 two_sum_add(sx, cx, tx);
                 two_sum_add(sy, cy, ty);

@@ -272,19 +272,20 @@ __device__ __forceinline__ void nlist_lane(const KParams& kp, int32_t i, int32_t
     int32_t cnt = 0;
     int32_t* __restrict__ out = kDirect ? index + offset[i] : slab + (int64_t)i * slab_k;
     const int32_t cap = kDirect ? INT_MAX : slab_k;
+    const bool coded = !kDirect && n <= kSlabJMask;
     // Loads run ahead of the tests: the next cell's bounds are requested when
     // a cell starts, and candidates are tested two at a time while the two
     // after them (crossing into the next cell at a cell's end) are in flight.
     int32_t j0 = cell_start[key[0] >> 5], j1 = cell_start[(key[0] >> 5) + 1];
     float4 wa = xw[j0 < j1 ? j0 : i];
     float4 wb = xw[j0 + 1 < j1 ? j0 + 1 : i];
-    auto test = [&](int32_t j, const float4& wj, float qx, float qy, float qz) {
+    auto test = [&](int32_t j, const float4& wj, float qx, float qy, float qz, uint32_t tagc) {
         const float dx = qx - wj.x, dy = qy - wj.y, dz = qz - wj.z;
         const float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
         bool hit = j != i && r2 < kp.list_lo32;
         if (j != i && !hit && r2 < kp.list_hi32) hit = exact_hit(kp, x, N, i, j);
         if (hit) {
-            if (cnt < cap) out[cnt] = j;
+            if (cnt < cap) out[cnt] = (int32_t)((uint32_t)j | tagc);
             ++cnt;
         }
     };
@@ -297,6 +298,9 @@ __device__ __forceinline__ void nlist_lane(const KParams& kp, int32_t i, int32_t
             j1n = cell_start[rn + 1];
         }
         const int c = (int)(key[q] & 31u);
+        const uint32_t tagc = coded ? ((uint32_t)(c % 3) | ((uint32_t)((c / 3) % 3) << 2) |
+                                       ((uint32_t)(c / 9) << 4)) << kSlabCodeShift
+                                    : 0u;
         // i's cell-relative position minus the cell's whole-cell offset
         const float qx = wi.x - (float)(c % 3 - 1) * cl0;
         const float qy = wi.y - (float)((c / 3) % 3 - 1) * cl1;
@@ -313,8 +317,8 @@ __device__ __forceinline__ void nlist_lane(const KParams& kp, int32_t i, int32_t
             const int32_t base = two ? j + 2 : j + 1;
             wa = xw[ahead(base)];
             wb = xw[ahead(base + 1)];
-            test(j, w0, qx, qy, qz);
-            if (two) test(j + 1, w1, qx, qy, qz);
+            test(j, w0, qx, qy, qz, tagc);
+            if (two) test(j + 1, w1, qx, qy, qz, tagc);
         }
         if (j0 == j1) {                        // an empty cell issued nothing ahead
             wa = xw[j0n < j1n ? j0n : i];
@@ -424,6 +428,7 @@ __global__ __launch_bounds__(kBlock) void k_nlist_compact(int32_t n, const int32
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t i0 = ((int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave) * kWave;
+    const int32_t mask = n <= kSlabJMask ? kSlabJMask : -1;      // strips coded stencil offsets
     if (i0 >= n || *flag != 0 || (int64_t)offset[n] > capacity) return;
     const int32_t ni = n - i0 < kWave ? (int32_t)(n - i0) : kWave;
     const int32_t own = (int32_t)i0 + (lane < ni ? lane : ni - 1);
@@ -443,7 +448,7 @@ __global__ __launch_bounds__(kBlock) void k_nlist_compact(int32_t n, const int32
             const int32_t t = __builtin_amdgcn_readlane(rend, q);
             if (e >= t) { r = q + 1; rs = t; }
         }
-        if (e < e1) index[e] = slab[(i0 + r) * slab_k + (e - rs)];
+        if (e < e1) index[e] = slab[(i0 + r) * slab_k + (e - rs)] & mask;
     }
 }
 
@@ -464,6 +469,11 @@ int32_t nlist_slab_width(double density, double rl2)
     int32_t k = (int32_t)(2.5 * mean + 24.0);
     k = k < 48 ? 48 : k;
     return (k + 15) / 16 * 16;
+}
+
+bool nlist_slab_coded(int kind, const uint32_t* cell_xyz, int32_t n_cells, int32_t n)
+{
+    return kind == 0 && cell_xyz && n_cells < (1 << 27) && n <= kSlabJMask;
 }
 
 hipError_t launch_nlist(const KParams& kp, const BatchView& bv, int32_t n_cells, int32_t n_blocks, int32_t n,
