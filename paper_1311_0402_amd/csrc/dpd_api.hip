@@ -406,7 +406,7 @@ int enqueue_batch_step(const dpd_batch* bt, const WsLayout& L, void* ws, int32_t
     a.npair = carve<int32_t>(ws, L.np_part);
     a.fred_part = nullptr;
     a.status = d_status;
-    a.grid = job.force_grid;
+    a.grid = job.force_grid > 0 ? job.force_grid : force_blocks(n, precision);
     a.slab = carve<int32_t>(ws, L.slab);
     a.slab_k = L.slab_k;
     a.slab_flag = carve<int32_t>(ws, L.slab_flag);
@@ -521,7 +521,7 @@ int dpd_forces(const dpd_params* p, int32_t precision, const dpd_state* sorted, 
     a.npair = nullptr;
     a.fred_part = stats ? carve<double>(ws, L.fred_part) : nullptr;
     a.status = d_status;
-    a.grid = 0;
+    a.grid = force_blocks(n, precision);
     a.slab = nullptr; a.slab_k = 0; a.slab_flag = nullptr; a.slab_coded = 0;
     const BatchView none{};
     DPD_TRY(launch_forces(kp, none, precision, a, s), "forces");
@@ -573,7 +573,7 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
     a.f = st->f; a.pe = nullptr; a.npair = nullptr;
     a.fred_part = carve<double>(ws, L.fred_part);
     a.status = d_status;
-    a.grid = 0;
+    a.grid = force_blocks(n, precision);
     a.slab = carve<int32_t>(ws, L.slab);
     a.slab_k = L.slab_k;
     a.slab_flag = carve<int32_t>(ws, L.slab_flag);
@@ -768,6 +768,8 @@ int dpd_batch_create(const dpd_params* per_sys, int32_t n_sys, const int64_t* sy
     job.nlist_waves = 4;
     job.nlist_kind = 0;
     b->step_base = carve<uint64_t>(d_table, T.step_base);
+    (void)force_blocks((int32_t)n_total, DPD_FP64);      // occupancy queries happen here, not under capture
+    (void)force_blocks((int32_t)n_total, DPD_MIXED);
 
     const hipStream_t s = as_stream(stream);
     DPD_TRY(hipMemcpyAsync(carve<void>(d_table, T.kps), b->kps.data(), n_sys * sizeof(KParams),
@@ -895,7 +897,7 @@ int dpd_batch_forces(const dpd_batch* b, int32_t precision, const dpd_state* sor
     a.d_step = nullptr; a.step_add = step;
     a.f = f_out; a.pe = pe_out; a.npair = nullptr; a.fred_part = nullptr;
     a.status = d_status;
-    a.grid = b->job.force_grid;
+    a.grid = b->job.force_grid > 0 ? b->job.force_grid : force_blocks(n, precision);
     a.slab = nullptr; a.slab_k = 0; a.slab_flag = nullptr; a.slab_coded = 0;
     DPD_TRY(launch_forces(b->job.kp, b->job.bv, precision, a, as_stream(stream)), "forces");
     return DPD_OK;

@@ -96,7 +96,7 @@ struct ForceArgs {
     int32_t* npair;                               // nullable: pairs inside r_c per particle
     double* fred_part;                            // [grid][2]: PE, pair count
     int32_t* status;                              // nullable
-    int32_t grid;                                 // persistent workgroups (0 = force_blocks(n))
+    int32_t grid;                                 // persistent workgroups (> 0)
     const int32_t* slab;                          // nullable: the list builder's slab (rows at i * slab_k),
     int32_t slab_k;                               //   read instead of index while *slab_flag == 0
     const int32_t* slab_flag;
@@ -104,9 +104,11 @@ struct ForceArgs {
 };
 hipError_t launch_forces(const KParams& kp, const BatchView& bv, int precision, const ForceArgs& a,
                          hipStream_t s);
-int force_blocks(int32_t n);
 constexpr int kMaxForceGrid = 8192;
-inline int force_grid(const ForceArgs& a) { return a.grid > 0 ? a.grid : force_blocks(a.n); }
+// default persistent grid of the force pass (the workgroups resident at once)
+int force_blocks(int32_t n, int precision);
+// the grid a launch uses: ForceArgs.grid, set by the caller (> 0)
+inline int force_grid(const ForceArgs& a) { return a.grid; }
 
 // ---- integration and reductions (k_integrate.hip) ----
 hipError_t launch_vv1(const KParams& kp, const BatchView& bat, int32_t n, const double* x, const double* v,

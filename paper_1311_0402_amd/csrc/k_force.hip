@@ -612,15 +612,30 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
 
 }  // namespace
 
-// Persistent grid: enough workgroups to fill the chip several times over,
-// never more than there are 64-particle chunks to hand out.
-int force_blocks(int32_t n)
+// Persistent grid: as many workgroups as the chip holds at once (occupancy
+// of the kernel times the compute units, cached per device and precision),
+// never more than there are 64-particle chunks to hand out.  With every
+// wave resident, an XCD's waves move through its chunks together.
+int force_blocks(int32_t n, int precision)
 {
+    static int cache[16][2] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) dev = 0;
+    const int pr = precision ? 1 : 0;
+    if (cache[dev][pr] == 0) {
+        int per_cu = 0, cus = 0;
+        const void* f = pr ? reinterpret_cast<const void*>(&k_force_mixed<0, false>)
+                           : reinterpret_cast<const void*>(&k_force_fp64<0, false>);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kBlock, 0) != hipSuccess || per_cu < 1)
+            per_cu = 4;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+        const int full = per_cu * cus;
+        cache[dev][pr] = full < kMaxForceGrid ? full : kMaxForceGrid;
+    }
     const int chunks = ceil_div(n > 0 ? n : 1, kChunk);
-    const int waves_per_block = kBlock / kWave;
-    const int max_blocks = 256 * 8;
-    const int blocks = ceil_div(chunks, waves_per_block);
-    return blocks < max_blocks ? blocks : max_blocks;
+    const int blocks = ceil_div(chunks, kBlock / kWave);
+    return blocks < cache[dev][pr] ? blocks : cache[dev][pr];
 }
 
 namespace {
