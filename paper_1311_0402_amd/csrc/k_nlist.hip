@@ -274,8 +274,9 @@ __device__ __forceinline__ void nlist_lane(const KParams& kp, int32_t i, int32_t
     const int32_t cap = kDirect ? INT_MAX : slab_k;
     const bool coded = !kDirect && n <= kSlabJMask;
     // Loads run ahead of the tests: the next cell's bounds are requested when
-    // a cell starts, and candidates are tested two at a time while the two
-    // after them (crossing into the next cell at a cell's end) are in flight.
+    // a cell starts, candidates are tested two at a time while the two after
+    // them are in flight, and a cell's first two are requested as the
+    // previous cell ends.
     int32_t j0 = cell_start[key[0] >> 5], j1 = cell_start[(key[0] >> 5) + 1];
     float4 wa = xw[j0 < j1 ? j0 : i];
     float4 wb = xw[j0 + 1 < j1 ? j0 + 1 : i];
@@ -305,25 +306,19 @@ __device__ __forceinline__ void nlist_lane(const KParams& kp, int32_t i, int32_t
         const float qx = wi.x - (float)(c % 3 - 1) * cl0;
         const float qy = wi.y - (float)((c / 3) % 3 - 1) * cl1;
         const float qz = wi.z - (float)(c / 9 - 1) * cl2;
-        // position p of the candidate sequence: this cell, then the next
-        auto ahead = [&](int32_t p) {
-            if (p < j1) return p;
-            const int32_t pn = j0n + (p - j1);
-            return pn < j1n ? pn : i;
-        };
         for (int32_t j = j0; j < j1; j += 2) {
             const float4 w0 = wa, w1 = wb;
             const bool two = j + 1 < j1;
-            const int32_t base = two ? j + 2 : j + 1;
-            wa = xw[ahead(base)];
-            wb = xw[ahead(base + 1)];
+            // the pair after this one inside the cell (clamped to its last
+            // candidate; the next cell's first two are requested below)
+            const int32_t last = j1 - 1;
+            wa = xw[j + 2 < last ? j + 2 : last];
+            wb = xw[j + 3 < last ? j + 3 : last];
             test(j, w0, qx, qy, qz, tagc);
             if (two) test(j + 1, w1, qx, qy, qz, tagc);
         }
-        if (j0 == j1) {                        // an empty cell issued nothing ahead
-            wa = xw[j0n < j1n ? j0n : i];
-            wb = xw[j0n + 1 < j1n ? j0n + 1 : i];
-        }
+        wa = xw[j0n < j1n ? j0n : i];
+        wb = xw[j0n + 1 < j1n ? j0n + 1 : i];
         j0 = j0n;
         j1 = j1n;
     }
