@@ -218,6 +218,7 @@ WsLayout ws_layout(const Job& job, int32_t n)
     w.cxyz = take(N * sizeof(uint32_t));
     w.tmp_tag = take(N * sizeof(uint32_t));
     w.tmp_src = take(N * sizeof(int32_t));
+    w.tmp_key = take(N * sizeof(int32_t));
     const int64_t scan_items = (int64_t)(n > n_cells ? n : n_cells) + 1;
     w.scan_part = take((size_t)ceil_div(scan_items, kScanTile) * sizeof(int32_t) + 64);
     w.rank_tab = take((size_t)(n_cells > 0 ? n_cells : 1) * sizeof(int32_t));
@@ -250,18 +251,19 @@ int enqueue_reorder(const Job& job, const WsLayout& L, void* ws, const dpd_state
     uint32_t* cxyz = carve<uint32_t>(ws, L.cxyz);
     uint32_t* tmp_tag = carve<uint32_t>(ws, L.tmp_tag);
     int32_t* tmp_src = carve<int32_t>(ws, L.tmp_src);
+    int32_t* tmp_key = carve<int32_t>(ws, L.tmp_key);
     int32_t* part = carve<int32_t>(ws, L.scan_part);
     const int32_t* rank_tab = carve<int32_t>(ws, L.rank_tab);
     DPD_TRY(launch_fill_i32(cells->cell_start, (int64_t)job.n_cells + 1, 0, s), "fill cell counts");
     DPD_TRY(launch_bin(job.kp, job.bv, n, in->x, rank_tab, key, slot, cxyz, cells->cell_start, s), "bin");
     DPD_TRY(launch_scan(cells->cell_start, (int64_t)job.n_cells + 1, part, s), "scan cells");
-    DPD_TRY(launch_place(n, key, slot, cells->cell_start, in->tag, tmp_tag, tmp_src, s), "place");
+    DPD_TRY(launch_place(n, key, slot, cells->cell_start, in->tag, tmp_tag, tmp_src, tmp_key, s), "place");
     GatherArgs g;
     g.x_in = in->x; g.v_in = in->v; g.vt_in = vt_in; g.type_in = in->type; g.cxyz_in = cxyz;
     g.x_out = out->x; g.v_out = out->v; g.vt_out = vt_out; g.tag_out = out->tag; g.type_out = out->type;
     g.cell_xyz = cells->cell_xyz; g.perm = cells->perm; g.idx_of_tag = cells->idx_of_tag;
     g.x32 = x32; g.v32 = v32;
-    DPD_TRY(launch_finalize(job.kp, job.bv, n, key, cells->cell_start, tmp_tag, tmp_src, g, s), "finalize");
+    DPD_TRY(launch_finalize(job.kp, job.bv, n, tmp_key, cells->cell_start, tmp_tag, tmp_src, g, s), "finalize");
     return DPD_OK;
 }
 

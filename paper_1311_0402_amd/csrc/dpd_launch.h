@@ -23,7 +23,7 @@ struct WsLayout {
     size_t bx, bv, bvt, btag, btype;   // post-drift, pre-reorder state (step)
     size_t vt_sorted;                  // reordered predicted velocity (lambda != 1/2)
     size_t key, slot, cxyz;            // binning: cell rank, slot in cell, cell coords
-    size_t tmp_tag, tmp_src;           // scatter before the in-cell tag order
+    size_t tmp_tag, tmp_src, tmp_key;  // scatter before the in-cell tag order
     size_t scan_part;                  // partial sums of the device-wide scan
     size_t rank_tab;                   // Morton rank of every cell (row-major cell index)
     size_t slab;                       // neighbour rows before compaction, K slots per particle
@@ -51,7 +51,7 @@ hipError_t launch_bin(const KParams& kp, const BatchView& bv, int32_t n, const d
 // in-place exclusive scan of data[0 .. count); partials needs ceil(count/kScanTile) ints
 hipError_t launch_scan(int32_t* data, int64_t count, int32_t* partials, hipStream_t s);
 hipError_t launch_place(int32_t n, const int32_t* key, const int32_t* slot, const int32_t* cell_start,
-                        const uint32_t* tag, uint32_t* tmp_tag, int32_t* tmp_src, hipStream_t s);
+                        const uint32_t* tag, uint32_t* tmp_tag, int32_t* tmp_src, int32_t* tmp_key, hipStream_t s);
 struct GatherArgs {
     const double* x_in; const double* v_in; const double* vt_in; const uint8_t* type_in;
     const uint32_t* cxyz_in;
@@ -59,7 +59,7 @@ struct GatherArgs {
     uint32_t* cell_xyz; int32_t* perm; int32_t* idx_of_tag;
     float* x32; float* v32;
 };
-hipError_t launch_finalize(const KParams& kp, const BatchView& bv, int32_t n, const int32_t* key,
+hipError_t launch_finalize(const KParams& kp, const BatchView& bv, int32_t n, const int32_t* tmp_key,
                            const int32_t* cell_start, const uint32_t* tmp_tag, const int32_t* tmp_src,
                            const GatherArgs& g, hipStream_t s);
 

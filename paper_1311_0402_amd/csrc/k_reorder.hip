@@ -234,60 +234,67 @@ __global__ __launch_bounds__(kBlock) void k_place(int32_t n, const int32_t* __re
                                                   const int32_t* __restrict__ slot,
                                                   const int32_t* __restrict__ cell_start,
                                                   const uint32_t* __restrict__ tag,
-                                                  uint32_t* __restrict__ tmp_tag, int32_t* __restrict__ tmp_src)
+                                                  uint32_t* __restrict__ tmp_tag, int32_t* __restrict__ tmp_src,
+                                                  int32_t* __restrict__ tmp_key)
 {
     const int32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    const int32_t pos = cell_start[key[i]] + slot[i];
+    const int32_t k = key[i];
+    const int32_t pos = cell_start[k] + slot[i];
     tmp_tag[pos] = tag[i];
     tmp_src[pos] = i;
+    tmp_key[pos] = k;
 }
 
 hipError_t launch_place(int32_t n, const int32_t* key, const int32_t* slot, const int32_t* cell_start,
-                        const uint32_t* tag, uint32_t* tmp_tag, int32_t* tmp_src, hipStream_t s)
+                        const uint32_t* tag, uint32_t* tmp_tag, int32_t* tmp_src, int32_t* tmp_key, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_place, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, n, key, slot, cell_start,
-                       tag, tmp_tag, tmp_src);
+                       tag, tmp_tag, tmp_src, tmp_key);
     return hipGetLastError();
 }
 
 __device__ __forceinline__ void finalize_one(const KParams& P, int32_t n, int32_t p,
-                                             const int32_t* __restrict__ key,
+                                             const int32_t* __restrict__ tmp_key,
                                              const int32_t* __restrict__ cell_start,
                                              const uint32_t* __restrict__ tmp_tag,
                                              const int32_t* __restrict__ tmp_src, const GatherArgs& g)
 {
+    // everything that depends only on the source is requested before the
+    // in-cell rank (which needs the cell's bounds and tags)
     const int32_t src = tmp_src[p];
-    const int32_t c = key[src];
-    const int32_t lo = cell_start[c], hi = cell_start[c + 1];
+    const int32_t c = tmp_key[p];
     const uint32_t t = tmp_tag[p];
-    int32_t below = 0;
-    for (int32_t q = lo; q < hi; ++q) below += (tmp_tag[q] < t) ? 1 : 0;
-    const int32_t dst = lo + below;
     const int64_t N = n;
-    g.perm[dst] = src;
-    g.tag_out[dst] = t;
-    g.type_out[dst] = g.type_in[src];
-    const uint32_t packed = g.cxyz_in[src];
-    g.cell_xyz[dst] = packed;
-    // tags are numbered per system (0 .. n_local - 1)
-    const uint32_t n_tags = (uint32_t)(P.n_local > 0 ? P.n_local : n);
-    if (g.idx_of_tag && t < n_tags) g.idx_of_tag[P.p_off + t] = dst;
-    double xs[3], vs[3];
+    double xs[3], vs[3], vts[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         xs[k] = g.x_in[k * N + src];
         vs[k] = g.v_in[k * N + src];
+        vts[k] = g.vt_in ? g.vt_in[k * N + src] : 0.0;
+    }
+    const uint8_t ty = g.type_in[src];
+    const uint32_t packed = g.cxyz_in[src];
+    const int32_t lo = cell_start[c], hi = cell_start[c + 1];
+    int32_t below = 0;
+    for (int32_t q = lo; q < hi; ++q) below += (tmp_tag[q] < t) ? 1 : 0;
+    const int32_t dst = lo + below;
+    g.perm[dst] = src;
+    g.tag_out[dst] = t;
+    g.type_out[dst] = ty;
+    g.cell_xyz[dst] = packed;
+    // tags are numbered per system (0 .. n_local - 1)
+    const uint32_t n_tags = (uint32_t)(P.n_local > 0 ? P.n_local : n);
+    if (g.idx_of_tag && t < n_tags) g.idx_of_tag[P.p_off + t] = dst;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
         g.x_out[k * N + dst] = xs[k];
         g.v_out[k * N + dst] = vs[k];
     }
     if (g.vt_in) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            vs[k] = g.vt_in[k * N + src];
-            g.vt_out[k * N + dst] = vs[k];
-        }
+        for (int k = 0; k < 3; ++k) g.vt_out[k * N + dst] = vts[k];
     }
     if (g.x32) {
         const int32_t cc[3] = {(int32_t)(packed & 1023u), (int32_t)((packed >> 10) & 1023u),
@@ -300,10 +307,12 @@ __device__ __forceinline__ void finalize_one(const KParams& P, int32_t n, int32_
         reinterpret_cast<float4*>(g.x32)[dst] = w;
     }
     if (g.v32) {
+        // the predicted velocity: v~ when it is kept apart, else v
+        const double* vv = g.vt_in ? vts : vs;
         float4 w;
-        w.x = (float)vs[0];
-        w.y = (float)vs[1];
-        w.z = (float)vs[2];
+        w.x = (float)vv[0];
+        w.y = (float)vv[1];
+        w.z = (float)vv[2];
         w.w = __uint_as_float(packed);
         reinterpret_cast<float4*>(g.v32)[dst] = w;
     }
@@ -311,7 +320,7 @@ __device__ __forceinline__ void finalize_one(const KParams& P, int32_t n, int32_
 
 template <bool kB>
 __global__ __launch_bounds__(kBlock) void k_finalize(KParams kp, BatchView bv, int32_t n,
-                                                     const int32_t* __restrict__ key,
+                                                     const int32_t* __restrict__ tmp_key,
                                                      const int32_t* __restrict__ cell_start,
                                                      const uint32_t* __restrict__ tmp_tag,
                                                      const int32_t* __restrict__ tmp_src, GatherArgs g)
@@ -319,20 +328,20 @@ __global__ __launch_bounds__(kBlock) void k_finalize(KParams kp, BatchView bv, i
     const int32_t p = blockIdx.x * kBlock + threadIdx.x;
     if (p >= n) return;
     // a particle never leaves its system, so position p and its source share it
-    if constexpr (kB) finalize_one(bv.kps[bv.sys_of[p]], n, p, key, cell_start, tmp_tag, tmp_src, g);
-    else finalize_one(kp, n, p, key, cell_start, tmp_tag, tmp_src, g);
+    if constexpr (kB) finalize_one(bv.kps[bv.sys_of[p]], n, p, tmp_key, cell_start, tmp_tag, tmp_src, g);
+    else finalize_one(kp, n, p, tmp_key, cell_start, tmp_tag, tmp_src, g);
 }
 
-hipError_t launch_finalize(const KParams& kp, const BatchView& bv, int32_t n, const int32_t* key,
+hipError_t launch_finalize(const KParams& kp, const BatchView& bv, int32_t n, const int32_t* tmp_key,
                            const int32_t* cell_start, const uint32_t* tmp_tag, const int32_t* tmp_src,
                            const GatherArgs& g, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     if (bv.kps)
-        hipLaunchKernelGGL(k_finalize<true>, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, kp, bv, n, key,
+        hipLaunchKernelGGL(k_finalize<true>, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, kp, bv, n, tmp_key,
                            cell_start, tmp_tag, tmp_src, g);
     else
-        hipLaunchKernelGGL(k_finalize<false>, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, kp, bv, n, key,
+        hipLaunchKernelGGL(k_finalize<false>, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, kp, bv, n, tmp_key,
                            cell_start, tmp_tag, tmp_src, g);
     return hipGetLastError();
 }
