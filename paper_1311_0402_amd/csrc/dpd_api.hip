@@ -199,7 +199,9 @@ Job single_job(const KParams& kp, int32_t n)
     return j;
 }
 
-WsLayout ws_layout(const Job& job, int32_t n)
+// aos: also lay out the packed FP64 copies the FP64 step reads (placed
+// last, so every other offset is the same either way)
+WsLayout ws_layout(const Job& job, int32_t n, bool aos = false)
 {
     WsLayout w;
     size_t o = 0;
@@ -232,18 +234,20 @@ WsLayout ws_layout(const Job& job, int32_t n)
     // per-particle potential energy and pair counts (per-system statistics of a batch)
     w.pe_part = take(N * sizeof(double));
     w.np_part = take(N * sizeof(int32_t));
+    w.x64 = aos ? take(N * 4 * sizeof(double)) : 0;
+    w.v64 = aos ? take(N * 4 * sizeof(double)) : 0;
     w.total = o;
     return w;
 }
 
-WsLayout ws_layout(const KParams& kp, int32_t n) { return ws_layout(single_job(kp, n), n); }
+WsLayout ws_layout(const KParams& kp, int32_t n, bool aos) { return ws_layout(single_job(kp, n), n, aos); }
 
 namespace {
 
 // binning + reordering from `in` into `out` (shared by dpd_bin_reorder and dpd_step)
 int enqueue_reorder(const Job& job, const WsLayout& L, void* ws, const dpd_state* in,
                     const double* vt_in, dpd_state* out, double* vt_out, dpd_cells* cells,
-                    float* x32, float* v32, hipStream_t s)
+                    float* x32, float* v32, hipStream_t s, bool aos = false)
 {
     const int32_t n = in->n;
     int32_t* key = carve<int32_t>(ws, L.key);
@@ -263,6 +267,8 @@ int enqueue_reorder(const Job& job, const WsLayout& L, void* ws, const dpd_state
     g.x_out = out->x; g.v_out = out->v; g.vt_out = vt_out; g.tag_out = out->tag; g.type_out = out->type;
     g.cell_xyz = cells->cell_xyz; g.perm = cells->perm; g.idx_of_tag = cells->idx_of_tag;
     g.x32 = x32; g.v32 = v32;
+    g.x64 = aos ? carve<double>(ws, L.x64) : nullptr;
+    g.v64 = aos ? carve<double>(ws, L.v64) : nullptr;
     DPD_TRY(launch_finalize(job.kp, job.bv, n, tmp_key, cells->cell_start, tmp_tag, tmp_src, g, s), "finalize");
     return DPD_OK;
 }
@@ -413,10 +419,14 @@ int enqueue_batch_step(const dpd_batch* bt, const WsLayout& L, void* ws, int32_t
     a.slab_k = L.slab_k;
     a.slab_flag = carve<int32_t>(ws, L.slab_flag);
     a.slab_coded = nlist_slab_coded(job.nlist_kind, cells->cell_xyz, job.n_cells, n) ? 1 : 0;
+    const bool aos = precision == DPD_FP64;
+    a.x64 = aos ? carve<double>(ws, L.x64) : nullptr;
+    a.v64 = aos ? carve<double>(ws, L.v64) : nullptr;
     int rc;
     DPD_TRY(launch_vv1(kp, job.bv, n, st->x, st->v, st->f, st->tag, st->type, b.x, b.v, bvt, b.tag, b.type, s),
             "vv1");
-    if ((rc = enqueue_reorder(job, L, ws, &b, bvt, st, vt_sorted, cells, x32, mixed ? v32 : nullptr, s))) return rc;
+    if ((rc = enqueue_reorder(job, L, ws, &b, bvt, st, vt_sorted, cells, x32, mixed ? v32 : nullptr, s, aos)))
+        return rc;
     if ((rc = enqueue_nlist(job, L, ws, st, cells, x32, nl, d_status, s))) return rc;
     DPD_TRY(launch_forces(kp, job.bv, precision, a, s), "forces");
     DPD_TRY(launch_vv2(kp, n, st->v, st->f, carve<double>(ws, L.red_part), nullptr, 0,
@@ -452,7 +462,7 @@ size_t dpd_workspace_bytes(const dpd_params* p, int32_t n, int32_t precision)
 {
     KParams k;
     if (n < 0 || (precision != DPD_FP64 && precision != DPD_MIXED) || make_kparams(p, &k) != DPD_OK) return 0;
-    return ws_layout(k, n).total;
+    return ws_layout(k, n, precision == DPD_FP64).total;
 }
 
 int dpd_bin_reorder(const dpd_params* p, const dpd_state* in, dpd_state* out, dpd_cells* cells,
@@ -525,6 +535,7 @@ int dpd_forces(const dpd_params* p, int32_t precision, const dpd_state* sorted, 
     a.status = d_status;
     a.grid = force_blocks(n, precision);
     a.slab = nullptr; a.slab_k = 0; a.slab_flag = nullptr; a.slab_coded = 0;
+    a.x64 = nullptr; a.v64 = nullptr;
     const BatchView none{};
     DPD_TRY(launch_forces(kp, none, precision, a, s), "forces");
     if (stats)
@@ -550,7 +561,8 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
     if (n > 0 && !x32) return fail(DPD_EINVAL, "x32 is NULL (the list build needs it)");
     if (precision == DPD_MIXED && n > 0 && !v32) return fail(DPD_EINVAL, "mixed precision needs v32");
     const Job job = single_job(kp, n);
-    const WsLayout L = ws_layout(job, n);
+    const bool aos = precision == DPD_FP64;
+    const WsLayout L = ws_layout(job, n, aos);
     if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
     if (n == 0 || n_steps == 0) return DPD_OK;
     const hipStream_t s = as_stream(stream);
@@ -580,6 +592,8 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
     a.slab_k = L.slab_k;
     a.slab_flag = carve<int32_t>(ws, L.slab_flag);
     a.slab_coded = nlist_slab_coded(job.nlist_kind, cells->cell_xyz, job.n_cells, n) ? 1 : 0;
+    a.x64 = aos ? carve<double>(ws, L.x64) : nullptr;
+    a.v64 = aos ? carve<double>(ws, L.v64) : nullptr;
     double* red_part = carve<double>(ws, L.red_part);
     double* fsum_part = carve<double>(ws, L.fsum_part);
     const bool mixed = precision == DPD_MIXED;
@@ -592,7 +606,7 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
         DPD_TRY(mark(k, 0), "event");
         DPD_TRY(launch_vv1(kp, job.bv, n, st->x, st->v, st->f, st->tag, st->type, b.x, b.v, bvt, b.tag, b.type, s), "vv1");
         DPD_TRY(mark(k, 1), "event");
-        rc = enqueue_reorder(job, L, ws, &b, bvt, st, vt_sorted, cells, x32, mixed ? v32 : nullptr, s);
+        rc = enqueue_reorder(job, L, ws, &b, bvt, st, vt_sorted, cells, x32, mixed ? v32 : nullptr, s, aos);
         if (rc) return rc;
         DPD_TRY(mark(k, 2), "event");
         // inside a call the force pass reads the builder's slab; the CSR list
@@ -811,7 +825,7 @@ int dpd_batch_sizes(const dpd_batch* b, int64_t* n_total, int64_t* n_cells_total
 size_t dpd_batch_workspace_bytes(const dpd_batch* b, int32_t precision)
 {
     if (!b || (precision != DPD_FP64 && precision != DPD_MIXED)) return 0;
-    return ws_layout(b->job, (int32_t)b->n_total).total;
+    return ws_layout(b->job, (int32_t)b->n_total, precision == DPD_FP64).total;
 }
 
 int dpd_batch_set_tiles(dpd_batch* b, const dpd_tiles* t)
@@ -901,6 +915,7 @@ int dpd_batch_forces(const dpd_batch* b, int32_t precision, const dpd_state* sor
     a.status = d_status;
     a.grid = b->job.force_grid > 0 ? b->job.force_grid : force_blocks(n, precision);
     a.slab = nullptr; a.slab_k = 0; a.slab_flag = nullptr; a.slab_coded = 0;
+    a.x64 = nullptr; a.v64 = nullptr;
     DPD_TRY(launch_forces(b->job.kp, b->job.bv, precision, a, as_stream(stream)), "forces");
     return DPD_OK;
 }
@@ -919,7 +934,7 @@ int dpd_batch_step(dpd_batch* b, int32_t precision, dpd_state* st, int32_t n_ste
     if ((rc = check_cells(cells, n, false)) || (rc = check_nlist(nl, n))) return rc;
     if (!x32) return fail(DPD_EINVAL, "x32 is NULL (the list build needs it)");
     if (precision == DPD_MIXED && !v32) return fail(DPD_EINVAL, "mixed precision needs v32");
-    const WsLayout L = ws_layout(b->job, n);
+    const WsLayout L = ws_layout(b->job, n, precision == DPD_FP64);
     if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
     if (n_steps == 0) return DPD_OK;
     const hipStream_t s = as_stream(stream);

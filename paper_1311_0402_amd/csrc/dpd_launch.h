@@ -34,11 +34,12 @@ struct WsLayout {
     size_t fsum_part;                  // force partials folded to kRedBlocks columns
     size_t bwd_part;                   // adjoint partials (type-pair matrices)
     size_t pe_part;                    // per-particle potential energy (batch statistics)
+    size_t x64, v64;                   // packed FP64 copies for the FP64 step (0 when not laid out)
     size_t np_part;                    // per-particle pair count (batch statistics)
     size_t total;
 };
 
-WsLayout ws_layout(const KParams& kp, int32_t n);
+WsLayout ws_layout(const KParams& kp, int32_t n, bool aos = false);
 
 // ---- reorder (k_reorder.hip) ----
 hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t s);
@@ -58,6 +59,7 @@ struct GatherArgs {
     double* x_out; double* v_out; double* vt_out; uint32_t* tag_out; uint8_t* type_out;
     uint32_t* cell_xyz; int32_t* perm; int32_t* idx_of_tag;
     float* x32; float* v32;
+    double* x64; double* v64;       // nullable: packed FP64 copies, double4 per particle
 };
 hipError_t launch_finalize(const KParams& kp, const BatchView& bv, int32_t n, const int32_t* tmp_key,
                            const int32_t* cell_start, const uint32_t* tmp_tag, const int32_t* tmp_src,
@@ -101,6 +103,8 @@ struct ForceArgs {
     int32_t slab_k;                               //   read instead of index while *slab_flag == 0
     const int32_t* slab_flag;
     int32_t slab_coded;                           // slab entries carry the stencil offset (see below)
+    const double* x64;                            // nullable: (x, y, z, tag bits) per sorted particle
+    const double* v64;                            //   and (v~, type bits), double4 each (FP64 pass)
 };
 hipError_t launch_forces(const KParams& kp, const BatchView& bv, int precision, const ForceArgs& a,
                          hipStream_t s);

@@ -303,14 +303,41 @@ __device__ __forceinline__ int32_t row_end_lane(const PairJob& jb, int32_t eb)
 // One pair (FP64): force contribution on i and its half of the pair
 // potential.  P supplies geometry and cutoff; A / G / S the type tables
 // (a, gamma, sigma / sqrt(dt)).
+// One particle's operands of the FP64 pair: from the packed copies when
+// the step wrote them, else from the state's arrays.
+struct Op64 {
+    double x, y, z, vx, vy, vz;
+    uint32_t tag;
+    int32_t type;
+};
+
+__device__ __forceinline__ Op64 load_op64(const ForceArgs& a, int64_t N, int32_t i)
+{
+    Op64 o;
+    if (a.x64) {
+        const double4 p = reinterpret_cast<const double4*>(a.x64)[i];
+        const double4 q = reinterpret_cast<const double4*>(a.v64)[i];
+        o.x = p.x; o.y = p.y; o.z = p.z;
+        o.vx = q.x; o.vy = q.y; o.vz = q.z;
+        o.tag = (uint32_t)__double_as_longlong(p.w);
+        o.type = (int32_t)__double_as_longlong(q.w);
+    } else {
+        o.x = a.x[i]; o.y = a.x[N + i]; o.z = a.x[2 * N + i];
+        o.vx = a.v[i]; o.vy = a.v[N + i]; o.vz = a.v[2 * N + i];
+        o.tag = a.tag[i];
+        o.type = a.type[i];
+    }
+    return o;
+}
+
 template <int kWMode>
 __device__ __forceinline__ bool pair64(const KParams& P, const double* A, const double* G, const double* S,
-                                       const ForceArgs& a, int64_t N, int32_t i, int32_t j, uint64_t step,
+                                       const Op64& oi, const Op64& oj, uint64_t step,
                                        double& px, double& py, double& pz, double& pp)
 {
-    const double dx = min_image(a.x[i] - a.x[j], P.L[0], P.halfL[0]);
-    const double dy = min_image(a.x[N + i] - a.x[N + j], P.L[1], P.halfL[1]);
-    const double dz = min_image(a.x[2 * N + i] - a.x[2 * N + j], P.L[2], P.halfL[2]);
+    const double dx = min_image(oi.x - oj.x, P.L[0], P.halfL[0]);
+    const double dy = min_image(oi.y - oj.y, P.L[1], P.halfL[1]);
+    const double dz = min_image(oi.z - oj.z, P.L[2], P.halfL[2]);
     const double r2 = dist2(dx, dy, dz);
     if (!(r2 < P.rc2)) return false;
     const double rr = sqrt(r2);
@@ -321,9 +348,9 @@ __device__ __forceinline__ bool pair64(const KParams& P, const double* A, const 
     const double wc = 1.0 - rr * P.inv_rc;
     const double wr = weight_r(wc, kWMode, P.s);
     const double wd = wr * wr;
-    const double ev = ex * (a.v[i] - a.v[j]) + ey * (a.v[N + i] - a.v[N + j]) + ez * (a.v[2 * N + i] - a.v[2 * N + j]);
-    const int tp = a.type[i] * P.n_types + a.type[j];
-    const double xi_ij = gauss64(pair_words(a.tag[i], a.tag[j], step, P.seed_lo, P.seed_hi));
+    const double ev = ex * (oi.vx - oj.vx) + ey * (oi.vy - oj.vy) + ez * (oi.vz - oj.vz);
+    const int tp = oi.type * P.n_types + oj.type;
+    const double xi_ij = gauss64(pair_words(oi.tag, oj.tag, step, P.seed_lo, P.seed_hi));
     const double phi = A[tp] * wc - G[tp] * wd * ev + S[tp] * wr * xi_ij;
     px = phi * ex; py = phi * ey; pz = phi * ez;
     pp = 0.25 * A[tp] * P.r_c * wc * wc;
@@ -366,9 +393,11 @@ __global__ __launch_bounds__(kBlock) void k_force_fp64(KParams kp, BatchView bv,
                 bool hit;
                 if constexpr (kB) {
                     const KParams& P = bv.kps[bv.sys_of[i]];
-                    hit = pair64<kWMode>(P, P.a, P.g, P.srdt, a, N, i, j, step, px, py, pz, pp);
+                    hit = pair64<kWMode>(P, P.a, P.g, P.srdt, load_op64(a, N, i), load_op64(a, N, j), step,
+                                         px, py, pz, pp);
                 } else {
-                    hit = pair64<kWMode>(kp, s_a, s_g, s_s, a, N, i, j, step, px, py, pz, pp);
+                    hit = pair64<kWMode>(kp, s_a, s_g, s_s, load_op64(a, N, i), load_op64(a, N, j), step,
+                                         px, py, pz, pp);
                 }
                 pn = hit ? 1.0 : 0.0;
                 np_tot += pn;

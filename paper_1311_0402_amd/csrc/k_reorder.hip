@@ -306,6 +306,16 @@ __device__ __forceinline__ void finalize_one(const KParams& P, int32_t n, int32_
         w.w = __uint_as_float(t);
         reinterpret_cast<float4*>(g.x32)[dst] = w;
     }
+    if (g.x64) {
+        // packed FP64 copies for the FP64 force pass: position and tag, the
+        // velocity the forces see and the type
+        const double* vv = g.vt_in ? vts : vs;
+        double4 px, pv;
+        px.x = xs[0]; px.y = xs[1]; px.z = xs[2]; px.w = __longlong_as_double((long long)t);
+        pv.x = vv[0]; pv.y = vv[1]; pv.z = vv[2]; pv.w = __longlong_as_double((long long)ty);
+        reinterpret_cast<double4*>(g.x64)[dst] = px;
+        reinterpret_cast<double4*>(g.v64)[dst] = pv;
+    }
     if (g.v32) {
         // the predicted velocity: v~ when it is kept apart, else v
         const double* vv = g.vt_in ? vts : vs;
