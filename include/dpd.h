@@ -303,12 +303,15 @@ typedef struct dpd_tiles {
     int32_t force_grid;     /* workgroups of the persistent force pass,
                                64 .. 8192 (0 = one per 4 chunks of 64 rows,
                                at most 2048)                                   */
-    int32_t nlist_waves;    /* waves per workgroup of the list build: 1, 2 or 4
-                               (0 = 4)                                         */
-    int32_t nlist_kind;     /* list builder: 0 = one lane per particle (used
-                               while the batch has fewer than 2^27 cells, else
-                               the block builder), 1 = one wave per 2x2x2
-                               cell block                                      */
+    int32_t nlist_waves;    /* waves per workgroup of the block and lane list
+                               builders: 1, 2 or 4 (0 = 4); the tile builder
+                               sizes its workgroups from the density          */
+    int32_t nlist_kind;     /* list builder: 0 = one workgroup per 8x4x4-cell
+                               tile with its neighbourhood staged in LDS,
+                               2 = one lane per particle over global memory
+                               (0 and 2 while the batch has fewer than 2^27
+                               cells, else the block builder), 1 = one wave
+                               per 2x2x2 cell block                            */
     int32_t reserved;       /* 0                                              */
 } dpd_tiles;
 

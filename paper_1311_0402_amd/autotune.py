@@ -24,7 +24,7 @@ from .dpd import Batch, Tiles
 
 FORCE_GRIDS = (0, 512, 1024, 2048, 4096)
 NLIST_WAVES = (1, 2, 4)
-NLIST_KINDS = (0, 1)
+NLIST_KINDS = (0, 1, 2)
 
 
 def default_candidates() -> List[Tiles]:

@@ -98,11 +98,24 @@ int make_kparams(const dpd_params* p, KParams* k)
     }
     k->nbits_b = bits_for(bmax);
     k->n_blocks = (int32_t)nblk;
+    const int32_t tdim[3] = {kTileX, kTileY, kTileZ};
+    int64_t ntile = 1;
+    k->tile_ok = 1;
+    for (int d = 0; d < 3; ++d) {
+        k->nt[d] = (k->nc[d] + tdim[d] - 1) / tdim[d];
+        ntile *= k->nt[d];
+        if (k->nc[d] < tdim[d] + 2) k->tile_ok = 0;
+    }
+    k->n_tiles = (int32_t)ntile;
     k->rl2 = r_list * r_list;
     // FP32 separations from cell offsets are within ~3e-6 r_list^2 of the
     // FP64 value (offsets below 4 cells); the band is ten times wider
     k->list_lo32 = (float)(k->rl2 * (1.0 - std::ldexp(1.0, -15)));
     k->list_hi32 = (float)(k->rl2 * (1.0 + std::ldexp(1.0, -15)));
+    // tile-frame positions reach 6 cell lengths from the frame origin: FP32
+    // separations are within ~2e-5 r_list^2 there; the band is ~6x wider
+    k->tile_lo32 = (float)(k->rl2 * (1.0 - std::ldexp(1.0, -13)));
+    k->tile_hi32 = (float)(k->rl2 * (1.0 + std::ldexp(1.0, -13)));
     k->rc2 = p->r_c * p->r_c;
     k->r_c = p->r_c;
     k->inv_rc = 1.0 / p->r_c;
@@ -178,10 +191,11 @@ struct Job {
     BatchView bv;
     int32_t n_cells;     // cells of all systems
     int32_t n_blocks;    // 2x2x2 list blocks of all systems
+    int32_t n_tiles;     // list-build tiles of all systems
     int32_t slab_k;      // neighbour slab width
     int32_t force_grid;  // persistent force workgroups (0 = default)
     int32_t nlist_waves; // waves per list-build workgroup
-    int32_t nlist_kind;  // 0: lane per particle (when ranks fit), 1: wave per 2x2x2 cell block
+    int32_t nlist_kind;  // 0: tile builder, 1: wave per 2x2x2 cell block, 2: lane per particle
 };
 
 Job single_job(const KParams& kp, int32_t n)
@@ -191,6 +205,7 @@ Job single_job(const KParams& kp, int32_t n)
     std::memset(&j.bv, 0, sizeof(j.bv));
     j.n_cells = kp.n_cells;
     j.n_blocks = kp.n_blocks;
+    j.n_tiles = kp.n_tiles;
     const double vol = kp.L[0] * kp.L[1] * kp.L[2];
     j.slab_k = nlist_slab_width(n / vol, kp.rl2);
     j.force_grid = 0;
@@ -277,7 +292,7 @@ int enqueue_nlist(const Job& job, const WsLayout& L, void* ws, const dpd_state* 
                   const dpd_cells* cells, const float* x32, dpd_nlist* nl, int32_t* d_status, hipStream_t s,
                   bool compact = true)
 {
-    DPD_TRY(launch_nlist(job.kp, job.bv, job.n_cells, job.n_blocks, st->n, st->x, x32, cells->cell_xyz,
+    DPD_TRY(launch_nlist(job.kp, job.bv, job.n_cells, job.n_blocks, job.n_tiles, st->n, st->x, x32, cells->cell_xyz,
                          cells->cell_start, carve<int32_t>(ws, L.rank_tab), nl->offset, nl->index, nl->capacity,
                          carve<int32_t>(ws, L.slab), L.slab_k, carve<int32_t>(ws, L.slab_flag), d_status,
                          carve<int32_t>(ws, L.scan_part), job.nlist_waves, job.nlist_kind, compact, s),
@@ -318,7 +333,7 @@ int check_nlist(const dpd_nlist* nl, int32_t n)
 // cell / block offsets, the particle -> system map and a step-counter
 // snapshot that numbers the rows of the per-step statistics.
 struct BatchTable {
-    size_t kps, p_off, c_off, b_off, ch_off, sys_of, step_base, total;
+    size_t kps, p_off, c_off, b_off, t_off, ch_off, sys_of, step_base, total;
 };
 
 BatchTable batch_table(int32_t n_sys, int64_t n_total)
@@ -331,6 +346,7 @@ BatchTable batch_table(int32_t n_sys, int64_t n_total)
     t.p_off = take((ns + 1) * sizeof(int32_t));
     t.c_off = take((ns + 1) * sizeof(int32_t));
     t.b_off = take((ns + 1) * sizeof(int32_t));
+    t.t_off = take((ns + 1) * sizeof(int32_t));
     t.ch_off = take((ns + 1) * sizeof(int32_t));
     t.sys_of = take((size_t)(n_total > 0 ? n_total : 1) * sizeof(uint16_t));
     t.step_base = take(sizeof(uint64_t));
@@ -357,7 +373,7 @@ struct dpd_batch {
     int64_t n_total = 0;
     dpd::Job job;                      // shared KParams (system 0) + BatchView + totals + tiles
     std::vector<dpd::KParams> kps;     // host copies (the device table is filled from these)
-    std::vector<int32_t> p_off, c_off, b_off, ch_off;
+    std::vector<int32_t> p_off, c_off, b_off, t_off, ch_off;
     uint64_t* step_base = nullptr;     // device
     hipGraphExec_t exec = nullptr;     // cached one-step graph
     hipStream_t capture = nullptr;     // stream the graph is captured on
@@ -727,9 +743,10 @@ int dpd_batch_create(const dpd_params* per_sys, int32_t n_sys, const int64_t* sy
     b->p_off.resize(n_sys + 1);
     b->c_off.resize(n_sys + 1);
     b->b_off.resize(n_sys + 1);
+    b->t_off.resize(n_sys + 1);
     b->ch_off.resize(n_sys + 1);
     const dpd_params& p0 = per_sys[0];
-    int64_t c_tot = 0, b_tot = 0, ch_tot = 0;
+    int64_t c_tot = 0, b_tot = 0, t_tot = 0, ch_tot = 0;
     int32_t slab_k = 0;
     for (int32_t q = 0; q < n_sys; ++q) {
         const dpd_params& p = per_sys[q];
@@ -747,15 +764,19 @@ int dpd_batch_create(const dpd_params* per_sys, int32_t n_sys, const int64_t* sy
         k.p_off = (int32_t)sys_offset[q];
         k.c_off = (int32_t)c_tot;
         k.b_off = (int32_t)b_tot;
+        k.t_off = (int32_t)t_tot;
         k.n_local = ns;
         b->p_off[q] = k.p_off;
         b->c_off[q] = k.c_off;
         b->b_off[q] = k.b_off;
+        b->t_off[q] = k.t_off;
         b->ch_off[q] = (int32_t)ch_tot;
         ch_tot += (ns + kWave - 1) / kWave;
         c_tot += k.n_cells;
         b_tot += k.n_blocks;
-        if (c_tot >= ((int64_t)1 << 31) - 1 || b_tot >= ((int64_t)1 << 31)) return fail(DPD_EINVAL, "too many cells");
+        t_tot += k.n_tiles;
+        if (c_tot >= ((int64_t)1 << 31) - 1 || b_tot >= ((int64_t)1 << 31) || t_tot >= ((int64_t)1 << 31))
+            return fail(DPD_EINVAL, "too many cells");
         const double vol = k.L[0] * k.L[1] * k.L[2];
         const int32_t w = nlist_slab_width(ns / vol, k.rl2);
         slab_k = w > slab_k ? w : slab_k;
@@ -763,22 +784,25 @@ int dpd_batch_create(const dpd_params* per_sys, int32_t n_sys, const int64_t* sy
     b->p_off[n_sys] = (int32_t)n_total;
     b->c_off[n_sys] = (int32_t)c_tot;
     b->b_off[n_sys] = (int32_t)b_tot;
+    b->t_off[n_sys] = (int32_t)t_tot;
     b->ch_off[n_sys] = (int32_t)ch_tot;
 
     Job& job = b->job;
     job.kp = b->kps[0];
-    job.kp.p_off = job.kp.c_off = job.kp.b_off = 0;
+    job.kp.p_off = job.kp.c_off = job.kp.b_off = job.kp.t_off = 0;
     job.kp.n_local = 0;
     job.bv.kps = carve<KParams>(d_table, T.kps);
     job.bv.p_off = carve<int32_t>(d_table, T.p_off);
     job.bv.c_off = carve<int32_t>(d_table, T.c_off);
     job.bv.b_off = carve<int32_t>(d_table, T.b_off);
+    job.bv.t_off = carve<int32_t>(d_table, T.t_off);
     job.bv.ch_off = carve<int32_t>(d_table, T.ch_off);
     job.bv.n_chunks = (int32_t)ch_tot;
     job.bv.sys_of = carve<uint16_t>(d_table, T.sys_of);
     job.bv.n_sys = n_sys;
     job.n_cells = (int32_t)c_tot;
     job.n_blocks = (int32_t)b_tot;
+    job.n_tiles = (int32_t)t_tot;
     job.slab_k = slab_k;
     job.force_grid = 0;
     job.nlist_waves = 4;
@@ -795,6 +819,8 @@ int dpd_batch_create(const dpd_params* per_sys, int32_t n_sys, const int64_t* sy
     DPD_TRY(hipMemcpyAsync(carve<void>(d_table, T.c_off), b->c_off.data(), (n_sys + 1) * sizeof(int32_t),
                            hipMemcpyHostToDevice, s), "copy batch table");
     DPD_TRY(hipMemcpyAsync(carve<void>(d_table, T.b_off), b->b_off.data(), (n_sys + 1) * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s), "copy batch table");
+    DPD_TRY(hipMemcpyAsync(carve<void>(d_table, T.t_off), b->t_off.data(), (n_sys + 1) * sizeof(int32_t),
                            hipMemcpyHostToDevice, s), "copy batch table");
     DPD_TRY(hipMemcpyAsync(carve<void>(d_table, T.ch_off), b->ch_off.data(), (n_sys + 1) * sizeof(int32_t),
                            hipMemcpyHostToDevice, s), "copy batch table");
@@ -835,7 +861,7 @@ int dpd_batch_set_tiles(dpd_batch* b, const dpd_tiles* t)
         return fail(DPD_EINVAL, "force_grid must be 0 or in [64, %d]", kMaxForceGrid);
     if (t->nlist_waves != 0 && t->nlist_waves != 1 && t->nlist_waves != 2 && t->nlist_waves != 4)
         return fail(DPD_EINVAL, "nlist_waves must be 0, 1, 2 or 4");
-    if (t->nlist_kind != 0 && t->nlist_kind != 1) return fail(DPD_EINVAL, "nlist_kind must be 0 or 1");
+    if (t->nlist_kind < 0 || t->nlist_kind > 2) return fail(DPD_EINVAL, "nlist_kind must be 0, 1 or 2");
     if (t->reserved) return fail(DPD_EINVAL, "reserved field must be 0");
     const int32_t waves = t->nlist_waves ? t->nlist_waves : 4;
     if (t->force_grid != b->job.force_grid || waves != b->job.nlist_waves || t->nlist_kind != b->job.nlist_kind)

@@ -19,6 +19,9 @@ namespace dpd {
 
 constexpr int kMaxTypes = 8;
 constexpr int kWave = 64;
+// List-build tile: two Morton-consecutive 4x4x4 cell blocks (adjacent along
+// x), so a tile's cells have consecutive Morton ranks.
+constexpr int kTileX = 8, kTileY = 4, kTileZ = 4;
 
 // Kernel-side parameter block, passed by value.  Derived quantities are
 // computed once on the host (inverse cell sizes, sigma / sqrt(dt), ...).
@@ -36,6 +39,11 @@ struct KParams {
     int32_t nbits_b;
     int32_t n_blocks;
     int32_t small_dim[3]; // n_c < 4: a block's neighbourhood wraps onto itself
+    int32_t nt[3];        // tiles of kTileX x kTileY x kTileZ cells per side (list builder)
+    int32_t n_tiles;
+    int32_t tile_ok;      // every tile's neighbourhood is kTile + 2 distinct cells per side
+    float tile_lo32;      // FP32 pre-test of the tile builder (tile-frame positions):
+    float tile_hi32;      //   r^2 < lo is a neighbour, r^2 >= hi is not, else FP64 decides
     float list_lo32;      // FP32 pre-test: r^2 < lo is a neighbour for sure,
     float list_hi32;      // r^2 >= hi is not; in between the FP64 test decides
     double rl2;           // (r_c + skin)^2, neighbour test  r^2 < rl2
@@ -55,6 +63,7 @@ struct KParams {
     const int32_t* partner;     // device, by tag; nullptr = no bonds
     // position of this system inside a batch (all 0 for a single system)
     int32_t p_off, c_off, b_off, n_local;
+    int32_t t_off;
     // per type pair: a, gamma, sigma / sqrt(dt)
     double a[kMaxTypes * kMaxTypes];
     double g[kMaxTypes * kMaxTypes];
@@ -168,6 +177,7 @@ struct BatchView {
     const int32_t* p_off;
     const int32_t* c_off;
     const int32_t* b_off;
+    const int32_t* t_off;    // list-build tiles, numbered system by system
     const int32_t* ch_off;   // 64-row force chunks, numbered system by system
     const uint16_t* sys_of;
     int32_t n_sys;

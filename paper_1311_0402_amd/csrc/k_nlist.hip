@@ -32,6 +32,7 @@
 // stencil cells together; the distance test is the same FP32 pre-test with
 // the same exact FP64 band rule.
 #include <climits>
+#include <cmath>
 
 #include "dpd_launch.h"
 
@@ -414,6 +415,253 @@ void launch_nlist_pass(int waves, const KParams& kp, const BatchView& bv, int32_
                                       slab, slab_k, flag, s);
 }
 
+// ---- tile builder ----
+//
+// One workgroup per tile of kTileX x kTileY x kTileZ cells (consecutive
+// Morton ranks, so the tile's particles are one index range).  The union of
+// its cells' stencils, (kTileX+2) x (kTileY+2) x (kTileZ+2) cells, is staged
+// in LDS: each union cell's particles in index order, as FP32 positions in
+// one tile frame (in-cell offset plus the cell's whole-cell offset from the
+// frame origin) with the particle index.  Each tile cell's 27 stencil cells
+// are put in ascending rank once, by one lane, with the same sorting
+// network, and stored as LDS ranges.  Each lane then walks its particle's
+// ranges in that order, one candidate per step, so its row comes out
+// ascending; the walk is one flat loop over all of the particle's
+// candidates, so lanes whose k-th stencil cells differ in size do not wait
+// for each other cell by cell.  Candidates come from LDS, so the walk issues
+// no global loads besides the row stores.  Tiles whose neighbourhood
+// overflows the LDS, and systems too small for distinct tile
+// neighbourhoods, take the lane builder's walk over global memory.
+
+constexpr int kTUX = kTileX + 2, kTUY = kTileY + 2, kTUZ = kTileZ + 2;
+constexpr int kTU = kTUX * kTUY * kTUZ;          // union cells of a tile
+constexpr int kTC = kTileX * kTileY * kTileZ;     // cells of a tile
+constexpr int kTilePos = 1536;                    // staged particles per tile
+// union cell whose origin is the tile frame's origin (keeps |positions| small)
+constexpr int kTFX = kTileX / 2 + 1, kTFY = kTileY / 2 + 1, kTFZ = kTileZ / 2 + 1;
+// stencil entry: LDS start | LDS end << 12 | slab code << 24
+static_assert(kTilePos < 4096, "12-bit LDS offsets in the stencil entries");
+static_assert(kTC * 27 * 4 >= kTilePos * 2, "the staging map fits in the stencil table");
+
+// exclusive prefix of v over the workgroup (kW waves); total gets the sum
+template <int kW>
+__device__ __forceinline__ int32_t tile_excl_scan(int32_t v, int32_t* s_w, int32_t& total)
+{
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    int32_t incl = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int32_t t = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += t;
+    }
+    if (lane == kWave - 1) s_w[w] = incl;
+    __syncthreads();
+    int32_t base = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < kW; ++k) {
+        const int32_t sw = s_w[k];
+        base += k < w ? sw : 0;
+        tot += sw;
+    }
+    total = tot;
+    return base + incl - v;
+}
+
+template <bool kB, int kW>
+__global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchView bv, int32_t n_tiles, int32_t n,
+                                                            const double* __restrict__ x,
+                                                            const float* __restrict__ x32,
+                                                            const uint32_t* __restrict__ cell_xyz,
+                                                            const int32_t* __restrict__ cell_start,
+                                                            const int32_t* __restrict__ rank_tab,
+                                                            int32_t* __restrict__ offset,
+                                                            int32_t* __restrict__ slab, int32_t slab_k,
+                                                            int32_t* __restrict__ flag)
+{
+    constexpr int kThreads = kW * kWave;
+    static_assert(kThreads >= kTU && kThreads >= kTC, "one thread per union cell and per tile cell");
+    __shared__ int32_t s_rank[kTU];
+    __shared__ int32_t s_gstart[kTU];
+    __shared__ int32_t s_lstart[kTU + 1];
+    __shared__ float4 s_pos[kTilePos];
+    __shared__ uint32_t s_sten[kTC * 27];      // before the sort: union cell of every staged slot
+    __shared__ int32_t s_w[kW];
+    uint16_t* s_seg = reinterpret_cast<uint16_t*>(s_sten);
+
+    const int32_t tile = xcd_logical_id(blockIdx.x, gridDim.x);
+    if (tile >= n_tiles) return;
+    int32_t t_loc = tile;
+    const KParams* P = &kp;
+    if constexpr (kB) {
+        const int32_t sy = find_segment(bv.t_off, bv.n_sys, tile);
+        P = &bv.kps[sy];
+        t_loc = tile - bv.t_off[sy];
+    }
+    const int32_t nc0 = P->nc[0], nc1 = P->nc[1], nc2 = P->nc[2];
+    const int32_t tx = t_loc % P->nt[0], ty = (t_loc / P->nt[0]) % P->nt[1], tz = t_loc / (P->nt[0] * P->nt[1]);
+    const int32_t o0 = tx * kTileX, o1 = ty * kTileY, o2 = tz * kTileZ;
+    const int32_t v0 = min(kTileX, nc0 - o0), v1 = min(kTileY, nc1 - o1), v2 = min(kTileZ, nc2 - o2);
+    // the tile's origin cell has its smallest rank; its cells are the next v0 v1 v2 ranks
+    const int32_t r0 = rank_tab[lin_cell(*P, o0, o1, o2)];
+    const int32_t i_lo = cell_start[r0], i_hi = cell_start[r0 + v0 * v1 * v2];
+    if (i_lo == i_hi) return;
+    const int tid = threadIdx.x;
+    const bool fits = P->tile_ok != 0;
+
+    // ---- union cells: thread u owns union cell u ----
+    int32_t cnt = 0;
+    if (fits && tid < kTU) {
+        const int32_t ux = tid % kTUX, uy = (tid / kTUX) % kTUY, uz = tid / (kTUX * kTUY);
+        int32_t rank = INT_MAX, gs = 0;
+        if (ux < v0 + 2 && uy < v1 + 2 && uz < v2 + 2) {
+            rank = rank_tab[lin_cell(*P, wrap_cell(o0 + ux - 1, nc0), wrap_cell(o1 + uy - 1, nc1),
+                                     wrap_cell(o2 + uz - 1, nc2))];
+            gs = cell_start[rank];
+            cnt = cell_start[rank + 1] - gs;
+        }
+        s_rank[tid] = rank;
+        s_gstart[tid] = gs;
+    }
+    int32_t total;
+    const int32_t ls = tile_excl_scan<kW>(cnt, s_w, total);
+    if (!fits || total > kTilePos) {
+        // lane builder's global walk for this tile's particles
+        for (int32_t i = i_lo + tid; i < i_hi; i += kThreads)
+            nlist_lane<false>(*P, i, n, x, x32, cell_xyz, cell_start, rank_tab, offset, nullptr, slab, slab_k,
+                              flag);
+        return;
+    }
+    if (tid < kTU) {
+        s_lstart[tid] = ls;
+        for (int32_t k = 0; k < cnt; ++k) s_seg[ls + k] = (uint16_t)tid;
+    }
+    if (tid == 0) s_lstart[kTU] = total;
+    __syncthreads();
+
+    // ---- staging: every union particle in the tile frame ----
+    const float4* __restrict__ xw = reinterpret_cast<const float4*>(x32);
+    const float cl0 = P->cell_len32[0], cl1 = P->cell_len32[1], cl2 = P->cell_len32[2];
+    for (int32_t p = tid; p < total; p += kThreads) {
+        const int32_t u = s_seg[p];
+        const int32_t j = s_gstart[u] + (p - s_lstart[u]);
+        const float4 w = xw[j];
+        const int32_t ux = u % kTUX, uy = (u / kTUX) % kTUY, uz = u / (kTUX * kTUY);
+        s_pos[p] = make_float4(w.x + (float)(ux - kTFX) * cl0, w.y + (float)(uy - kTFY) * cl1,
+                               w.z + (float)(uz - kTFZ) * cl2, __int_as_float(j));
+    }
+    __syncthreads();
+
+    // ---- each tile cell's stencil in ascending rank, as LDS ranges ----
+    if (tid < kTC) {
+        const int32_t lx = tid % kTileX, ly = (tid / kTileX) % kTileY, lz = tid / (kTileX * kTileY);
+        if (lx < v0 && ly < v1 && lz < v2) {
+            uint32_t key[27];
+#pragma unroll
+            for (int c = 0; c < 27; ++c) {
+                const int32_t u = (lx + c % 3) + kTUX * ((ly + (c / 3) % 3) + kTUY * (lz + c / 9));
+                key[c] = ((uint32_t)s_rank[u] << 5) | (uint32_t)c;
+            }
+#pragma unroll
+            for (int c = 0; c < kNet27.count; ++c) {
+                const uint32_t a = key[kNet27.a[c]], b = key[kNet27.b[c]];
+                key[kNet27.a[c]] = a < b ? a : b;
+                key[kNet27.b[c]] = a < b ? b : a;
+            }
+#pragma unroll
+            for (int q = 0; q < 27; ++q) {
+                const int32_t c = (int32_t)(key[q] & 31u);
+                const int32_t ex = c % 3, ey = (c / 3) % 3, ez = c / 9;
+                const int32_t u = (lx + ex) + kTUX * ((ly + ey) + kTUY * (lz + ez));
+                const uint32_t code = (uint32_t)ex | ((uint32_t)ey << 2) | ((uint32_t)ez << 4);
+                s_sten[tid * 27 + q] = (uint32_t)s_lstart[u] | ((uint32_t)s_lstart[u + 1] << 12) | (code << 24);
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- the walk: one lane per particle of the tile ----
+    const float lo = P->tile_lo32, hi = P->tile_hi32;
+    const bool coded = n <= kSlabJMask;
+    const int64_t N = n;
+    for (int32_t i = i_lo + tid; i < i_hi; i += kThreads) {
+        const uint32_t me = cell_xyz[i];
+        const int32_t lx = (int32_t)(me & 1023u) - o0, ly = (int32_t)((me >> 10) & 1023u) - o1,
+                      lz = (int32_t)(me >> 20) - o2;
+        const int32_t ui = (lx + 1) + kTUX * ((ly + 1) + kTUY * (lz + 1));
+        const float4 wi = s_pos[s_lstart[ui] + (i - s_gstart[ui])];
+        const uint32_t* st = s_sten + (lx + kTileX * (ly + kTileY * lz)) * 27;
+        int32_t* __restrict__ out = slab + (int64_t)i * slab_k;
+        int32_t row = 0, q = 0;
+        uint32_t ent = st[0];
+        int32_t k = (int32_t)(ent & 0xFFFu), e = (int32_t)((ent >> 12) & 0xFFFu);
+        uint32_t cs = coded ? (ent >> 24) << kSlabCodeShift : 0u;
+        for (;;) {
+            while (k >= e && q < 26) {                     // next non-empty stencil cell
+                ent = st[++q];
+                k = (int32_t)(ent & 0xFFFu);
+                e = (int32_t)((ent >> 12) & 0xFFFu);
+                cs = coded ? (ent >> 24) << kSlabCodeShift : 0u;
+            }
+            if (k >= e) break;
+            const float4 w = s_pos[k];
+            const float dx = wi.x - w.x, dy = wi.y - w.y, dz = wi.z - w.z;
+            const float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
+            const int32_t j = __float_as_int(w.w);
+            bool hit = j != i && r2 < lo;
+            if (j != i && !hit && r2 < hi) hit = exact_hit(*P, x, N, i, j);
+            if (hit) {
+                if (row < slab_k) out[row] = (int32_t)((uint32_t)j | cs);
+                ++row;
+            }
+            ++k;
+        }
+        offset[i] = row;
+        if (row > slab_k) atomicOr(flag, 1);
+    }
+}
+
+template <bool kB, int kW>
+void launch_nlist_tiles_t(const KParams& kp, const BatchView& bv, int32_t n_tiles, int32_t n, const double* x,
+                          const float* x32, const uint32_t* cell_xyz, const int32_t* cell_start,
+                          const int32_t* rank_tab, int32_t* offset, int32_t* slab, int32_t slab_k, int32_t* flag,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL((k_nlist_tiles<kB, kW>), dim3(n_tiles), dim3(kW * kWave), 0, s, kp, bv, n_tiles, n, x, x32,
+                       cell_xyz, cell_start, rank_tab, offset, slab, slab_k, flag);
+}
+
+template <bool kB>
+void launch_nlist_tiles(int waves, const KParams& kp, const BatchView& bv, int32_t n_tiles, int32_t n,
+                        const double* x, const float* x32, const uint32_t* cell_xyz, const int32_t* cell_start,
+                        const int32_t* rank_tab, int32_t* offset, int32_t* slab, int32_t slab_k, int32_t* flag,
+                        hipStream_t s)
+{
+#define DPD_TILE_CASE(W)                                                                                         \
+    launch_nlist_tiles_t<kB, W>(kp, bv, n_tiles, n, x, x32, cell_xyz, cell_start, rank_tab, offset, slab, slab_k, \
+                                flag, s)
+    if (waves <= 6) DPD_TILE_CASE(6);
+    else if (waves <= 7) DPD_TILE_CASE(7);
+    else if (waves <= 8) DPD_TILE_CASE(8);
+    else if (waves <= 10) DPD_TILE_CASE(10);
+    else if (waves <= 12) DPD_TILE_CASE(12);
+    else DPD_TILE_CASE(16);
+#undef DPD_TILE_CASE
+}
+
+}  // namespace
+
+// Waves per tile workgroup: the mean particle count of a tile plus three
+// standard deviations, so a second pass over a tile's particles is rare.
+int nlist_tile_waves(int32_t n, int32_t n_cells)
+{
+    const double mean = (double)kTC * (double)n / (double)(n_cells > 0 ? n_cells : 1);
+    const double need = mean + 3.0 * std::sqrt(mean);
+    int w = (int)std::ceil(need / kWave);
+    return w < 6 ? 6 : (w > 16 ? 16 : w);
+}
+
+namespace {
+
 // CSR list from the slab: one wave per 64 consecutive rows writes their
 // entries [offset[i0], offset[i0 + 64]) in order, one entry per lane.
 __global__ __launch_bounds__(kBlock) void k_nlist_compact(int32_t n, const int32_t* __restrict__ offset,
@@ -466,24 +714,39 @@ int32_t nlist_slab_width(double density, double rl2)
     return (k + 15) / 16 * 16;
 }
 
-bool nlist_slab_coded(int kind, const uint32_t* cell_xyz, int32_t n_cells, int32_t n)
+// The tile and lane builders pack a rank and a 5-bit stencil code into 32
+// bits; beyond 2^27 cells the block builder takes over.
+static bool ranks_fit(const uint32_t* cell_xyz, int32_t n_cells)
 {
-    return kind == 0 && cell_xyz && n_cells < (1 << 27) && n <= kSlabJMask;
+    return cell_xyz && n_cells < (1 << 27);
 }
 
-hipError_t launch_nlist(const KParams& kp, const BatchView& bv, int32_t n_cells, int32_t n_blocks, int32_t n,
-                        const double* x, const float* x32, const uint32_t* cell_xyz, const int32_t* cell_start,
-                        const int32_t* rank_tab, int32_t* offset, int32_t* index, int64_t capacity, int32_t* slab,
-                        int32_t slab_k, int32_t* flag, int32_t* status, int32_t* scan_part, int waves,
-                        int kind, bool compact, hipStream_t s)
+bool nlist_slab_coded(int kind, const uint32_t* cell_xyz, int32_t n_cells, int32_t n)
+{
+    return (kind == 0 || kind == 2) && ranks_fit(cell_xyz, n_cells) && n <= kSlabJMask;
+}
+
+hipError_t launch_nlist(const KParams& kp, const BatchView& bv, int32_t n_cells, int32_t n_blocks, int32_t n_tiles,
+                        int32_t n, const double* x, const float* x32, const uint32_t* cell_xyz,
+                        const int32_t* cell_start, const int32_t* rank_tab, int32_t* offset, int32_t* index,
+                        int64_t capacity, int32_t* slab, int32_t slab_k, int32_t* flag, int32_t* status,
+                        int32_t* scan_part, int waves, int kind, bool compact, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipError_t e;
-    // the lane builder packs a rank and a 5-bit stencil code into 32 bits
-    const bool lanes = kind == 0 && cell_xyz && n_cells < (1 << 27);
+    const bool tiles = kind == 0 && ranks_fit(cell_xyz, n_cells);
+    const bool lanes = tiles || (kind == 2 && ranks_fit(cell_xyz, n_cells));
     if ((e = launch_fill_i32(offset + n, 1, 0, s)) != hipSuccess) return e;
     if ((e = launch_fill_i32(flag, 1, 0, s)) != hipSuccess) return e;
-    if (lanes)
+    if (tiles) {
+        const int tw = nlist_tile_waves(n, n_cells);
+        if (bv.kps)
+            launch_nlist_tiles<true>(tw, kp, bv, n_tiles, n, x, x32, cell_xyz, cell_start, rank_tab, offset, slab,
+                                     slab_k, flag, s);
+        else
+            launch_nlist_tiles<false>(tw, kp, bv, n_tiles, n, x, x32, cell_xyz, cell_start, rank_tab, offset, slab,
+                                      slab_k, flag, s);
+    } else if (lanes)
         launch_nlist_lanes<false>(waves, kp, bv, n, x, x32, cell_xyz, cell_start, rank_tab, offset, index, capacity,
                                   slab, slab_k, flag, s);
     else
@@ -497,6 +760,8 @@ hipError_t launch_nlist(const KParams& kp, const BatchView& bv, int32_t n_cells,
         hipLaunchKernelGGL(k_nlist_compact, dim3(ceil_div(ceil_div(n, kWave), kWavesPerBlock)), dim3(kBlock), 0,
                            s, n, (const int32_t*)offset, capacity, (const int32_t*)slab, slab_k,
                            (const int32_t*)flag, index);
+    // rows that overflowed the slab: the lane builder's walk writes the CSR
+    // rows directly (the same rows the tile builder would give)
     if (lanes)
         launch_nlist_lanes<true>(waves, kp, bv, n, x, x32, cell_xyz, cell_start, rank_tab, offset, index, capacity,
                                  slab, slab_k, flag, s);

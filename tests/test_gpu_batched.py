@@ -147,12 +147,13 @@ def test_graph_replay_equals_eager_and_is_resumable():
 
 
 def test_tiles_do_not_change_results():
-    """Launch shapes and both list builders give bitwise the same lists and
-    trajectories."""
+    """Launch shapes and all three list builders give bitwise the same lists
+    and trajectories."""
     systems = _systems(_spec(n_sys=5, seed=44))
     ref = None
     for tiles in [P.Tiles(), P.Tiles(force_grid=64, nlist_waves=1), P.Tiles(force_grid=4096, nlist_waves=2),
-                  P.Tiles(force_grid=700, nlist_waves=4, nlist_kind=1), P.Tiles(nlist_waves=1, nlist_kind=1)]:
+                  P.Tiles(force_grid=700, nlist_waves=4, nlist_kind=1), P.Tiles(nlist_waves=1, nlist_kind=1),
+                  P.Tiles(nlist_waves=2, nlist_kind=2)]:
         b = _batch(systems, P.MIXED)
         b.set_tiles(tiles)
         b.rebuild()
@@ -186,7 +187,7 @@ def test_batch_argument_errors():
     with pytest.raises(P.DPDError):
         b.set_tiles(P.Tiles(nlist_waves=3))
     with pytest.raises(P.DPDError):
-        b.set_tiles(P.Tiles(nlist_kind=2))
+        b.set_tiles(P.Tiles(nlist_kind=3))
     assert b.get_tiles() == P.Tiles(0, 4, 0)
 
 

@@ -54,6 +54,13 @@ def _systems():
         "amphiphile": di.amphiphile(n=6000, seed=4),
         "poiseuille": di.poiseuille(seed=9, box=(6.0, 12.0, 5.0), rho=4.0),
         "clustered": di.clustered_fluid(),
+        # boxes of at least 10 x 6 x 6 cells go through the tile list builder:
+        # partial tiles at the high faces, the planted cases, and a cluster
+        # whose tile neighbourhood overflows the LDS staging
+        "ragged_tiles": di.uniform_fluid(5000, (13.7, 9.1, 11.3), 11),
+        "edge_tiles": di.edge_case_fluid(seed=12, box=(12.0, 7.5, 6.5), n=600),
+        "clustered_tiles": di.clustered_fluid(seed=13, box=(12.0, 7.0, 7.0), n_cluster=700, n_rest=600,
+                                              size=1.5),
     }
 
 
