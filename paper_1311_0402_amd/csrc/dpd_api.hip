@@ -249,6 +249,7 @@ WsLayout ws_layout(const Job& job, int32_t n, bool aos = false)
     // per-particle potential energy and pair counts (per-system statistics of a batch)
     w.pe_part = take(N * sizeof(double));
     w.np_part = take(N * sizeof(int32_t));
+    w.tile_rest = take(((size_t)(job.n_tiles > 0 ? job.n_tiles : 0) + 1) * sizeof(int32_t));
     w.x64 = aos ? take(N * 4 * sizeof(double)) : 0;
     w.v64 = aos ? take(N * 4 * sizeof(double)) : 0;
     w.total = o;
@@ -294,7 +295,8 @@ int enqueue_nlist(const Job& job, const WsLayout& L, void* ws, const dpd_state* 
 {
     DPD_TRY(launch_nlist(job.kp, job.bv, job.n_cells, job.n_blocks, job.n_tiles, st->n, st->x, x32, cells->cell_xyz,
                          cells->cell_start, carve<int32_t>(ws, L.rank_tab), nl->offset, nl->index, nl->capacity,
-                         carve<int32_t>(ws, L.slab), L.slab_k, carve<int32_t>(ws, L.slab_flag), d_status,
+                         carve<int32_t>(ws, L.slab), L.slab_k, carve<int32_t>(ws, L.slab_flag),
+                         carve<int32_t>(ws, L.tile_rest), d_status,
                          carve<int32_t>(ws, L.scan_part), job.nlist_waves, job.nlist_kind, compact, s),
             "neighbour list");
     return DPD_OK;

@@ -36,6 +36,7 @@ struct WsLayout {
     size_t pe_part;                    // per-particle potential energy (batch statistics)
     size_t x64, v64;                   // packed FP64 copies for the FP64 step (0 when not laid out)
     size_t np_part;                    // per-particle pair count (batch statistics)
+    size_t tile_rest;                  // tiles left by the tile list builder: count, then tile ids
     size_t total;
 };
 
@@ -78,12 +79,13 @@ constexpr int32_t kSlabJMask = (1 << kSlabCodeShift) - 1;
 // the 2x2x2 cell blocks of all systems, n_tiles their list-build tiles.
 // kind 0: tile builder, 1: block builder, 2: lane builder (0 and 2 need
 // cell_xyz and fewer than 2^27 cells, else the block builder runs); waves
-// sizes the workgroups of builders 1 and 2.
+// sizes the workgroups of builders 1 and 2; tile_rest (n_tiles + 1 ints)
+// lists the tiles the tile builder leaves to the lane builder.
 hipError_t launch_nlist(const KParams& kp, const BatchView& bv, int32_t n_cells, int32_t n_blocks, int32_t n_tiles,
                         int32_t n, const double* x, const float* x32, const uint32_t* cell_xyz,
                         const int32_t* cell_start, const int32_t* rank_tab, int32_t* offset, int32_t* index,
-                        int64_t capacity, int32_t* slab, int32_t slab_k, int32_t* flag, int32_t* status,
-                        int32_t* scan_part, int waves, int kind, bool compact, hipStream_t s);
+                        int64_t capacity, int32_t* slab, int32_t slab_k, int32_t* flag, int32_t* tile_rest,
+                        int32_t* status, int32_t* scan_part, int waves, int kind, bool compact, hipStream_t s);
 // whether that build leaves coded slab entries (tile and lane builders, n < 2^26)
 bool nlist_slab_coded(int kind, const uint32_t* cell_xyz, int32_t n_cells, int32_t n);
 // waves per workgroup of the tile builder for n particles in n_cells cells

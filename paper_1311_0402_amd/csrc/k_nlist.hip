@@ -467,6 +467,38 @@ __device__ __forceinline__ int32_t tile_excl_scan(int32_t v, int32_t* s_w, int32
     return base + incl - v;
 }
 
+// The tile's system and cells: tile origin o (cells), its extent v (clipped
+// at the high faces) and its particle range [i_lo, i_hi).
+struct TileGeom {
+    const KParams* P;
+    int32_t o0, o1, o2, v0, v1, v2;
+    int32_t i_lo, i_hi;
+};
+
+template <bool kB>
+__device__ __forceinline__ TileGeom tile_geom(const KParams& kp, const BatchView& bv, int32_t tile,
+                                              const int32_t* __restrict__ cell_start,
+                                              const int32_t* __restrict__ rank_tab)
+{
+    TileGeom g;
+    int32_t t_loc = tile;
+    g.P = &kp;
+    if constexpr (kB) {
+        const int32_t sy = find_segment(bv.t_off, bv.n_sys, tile);
+        g.P = &bv.kps[sy];
+        t_loc = tile - bv.t_off[sy];
+    }
+    const KParams& P = *g.P;
+    const int32_t tx = t_loc % P.nt[0], ty = (t_loc / P.nt[0]) % P.nt[1], tz = t_loc / (P.nt[0] * P.nt[1]);
+    g.o0 = tx * kTileX; g.o1 = ty * kTileY; g.o2 = tz * kTileZ;
+    g.v0 = min(kTileX, P.nc[0] - g.o0); g.v1 = min(kTileY, P.nc[1] - g.o1); g.v2 = min(kTileZ, P.nc[2] - g.o2);
+    // the origin cell has the tile's smallest rank; its cells are the next v0 v1 v2 ranks
+    const int32_t r0 = rank_tab[lin_cell(P, g.o0, g.o1, g.o2)];
+    g.i_lo = cell_start[r0];
+    g.i_hi = cell_start[r0 + g.v0 * g.v1 * g.v2];
+    return g;
+}
+
 template <bool kB, int kW>
 __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchView bv, int32_t n_tiles, int32_t n,
                                                             const double* __restrict__ x,
@@ -476,7 +508,8 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
                                                             const int32_t* __restrict__ rank_tab,
                                                             int32_t* __restrict__ offset,
                                                             int32_t* __restrict__ slab, int32_t slab_k,
-                                                            int32_t* __restrict__ flag)
+                                                            int32_t* __restrict__ flag,
+                                                            int32_t* __restrict__ rest)
 {
     constexpr int kThreads = kW * kWave;
     static_assert(kThreads >= kTU && kThreads >= kTC, "one thread per union cell and per tile cell");
@@ -485,37 +518,26 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
     __shared__ int32_t s_lstart[kTU + 1];
     __shared__ float4 s_pos[kTilePos];
     __shared__ uint32_t s_sten[kTC * 27];      // before the sort: union cell of every staged slot
+    __shared__ uint8_t s_nne[kTC];
     __shared__ int32_t s_w[kW];
     uint16_t* s_seg = reinterpret_cast<uint16_t*>(s_sten);
 
     const int32_t tile = xcd_logical_id(blockIdx.x, gridDim.x);
     if (tile >= n_tiles) return;
-    int32_t t_loc = tile;
-    const KParams* P = &kp;
-    if constexpr (kB) {
-        const int32_t sy = find_segment(bv.t_off, bv.n_sys, tile);
-        P = &bv.kps[sy];
-        t_loc = tile - bv.t_off[sy];
-    }
-    const int32_t nc0 = P->nc[0], nc1 = P->nc[1], nc2 = P->nc[2];
-    const int32_t tx = t_loc % P->nt[0], ty = (t_loc / P->nt[0]) % P->nt[1], tz = t_loc / (P->nt[0] * P->nt[1]);
-    const int32_t o0 = tx * kTileX, o1 = ty * kTileY, o2 = tz * kTileZ;
-    const int32_t v0 = min(kTileX, nc0 - o0), v1 = min(kTileY, nc1 - o1), v2 = min(kTileZ, nc2 - o2);
-    // the tile's origin cell has its smallest rank; its cells are the next v0 v1 v2 ranks
-    const int32_t r0 = rank_tab[lin_cell(*P, o0, o1, o2)];
-    const int32_t i_lo = cell_start[r0], i_hi = cell_start[r0 + v0 * v1 * v2];
-    if (i_lo == i_hi) return;
+    const TileGeom g = tile_geom<kB>(kp, bv, tile, cell_start, rank_tab);
+    if (g.i_lo == g.i_hi) return;
+    const KParams& P = *g.P;
     const int tid = threadIdx.x;
-    const bool fits = P->tile_ok != 0;
+    const bool fits = P.tile_ok != 0;
 
     // ---- union cells: thread u owns union cell u ----
     int32_t cnt = 0;
     if (fits && tid < kTU) {
         const int32_t ux = tid % kTUX, uy = (tid / kTUX) % kTUY, uz = tid / (kTUX * kTUY);
         int32_t rank = INT_MAX, gs = 0;
-        if (ux < v0 + 2 && uy < v1 + 2 && uz < v2 + 2) {
-            rank = rank_tab[lin_cell(*P, wrap_cell(o0 + ux - 1, nc0), wrap_cell(o1 + uy - 1, nc1),
-                                     wrap_cell(o2 + uz - 1, nc2))];
+        if (ux < g.v0 + 2 && uy < g.v1 + 2 && uz < g.v2 + 2) {
+            rank = rank_tab[lin_cell(P, wrap_cell(g.o0 + ux - 1, P.nc[0]), wrap_cell(g.o1 + uy - 1, P.nc[1]),
+                                     wrap_cell(g.o2 + uz - 1, P.nc[2]))];
             gs = cell_start[rank];
             cnt = cell_start[rank + 1] - gs;
         }
@@ -525,10 +547,8 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
     int32_t total;
     const int32_t ls = tile_excl_scan<kW>(cnt, s_w, total);
     if (!fits || total > kTilePos) {
-        // lane builder's global walk for this tile's particles
-        for (int32_t i = i_lo + tid; i < i_hi; i += kThreads)
-            nlist_lane<false>(*P, i, n, x, x32, cell_xyz, cell_start, rank_tab, offset, nullptr, slab, slab_k,
-                              flag);
+        // left to the lane builder's walk over global memory (k_nlist_tile_rest)
+        if (tid == 0) rest[1 + atomicAdd(rest, 1)] = tile;
         return;
     }
     if (tid < kTU) {
@@ -540,7 +560,7 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
 
     // ---- staging: every union particle in the tile frame ----
     const float4* __restrict__ xw = reinterpret_cast<const float4*>(x32);
-    const float cl0 = P->cell_len32[0], cl1 = P->cell_len32[1], cl2 = P->cell_len32[2];
+    const float cl0 = P.cell_len32[0], cl1 = P.cell_len32[1], cl2 = P.cell_len32[2];
     for (int32_t p = tid; p < total; p += kThreads) {
         const int32_t u = s_seg[p];
         const int32_t j = s_gstart[u] + (p - s_lstart[u]);
@@ -551,10 +571,10 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
     }
     __syncthreads();
 
-    // ---- each tile cell's stencil in ascending rank, as LDS ranges ----
+    // ---- each tile cell's non-empty stencil cells in ascending rank ----
     if (tid < kTC) {
         const int32_t lx = tid % kTileX, ly = (tid / kTileX) % kTileY, lz = tid / (kTileX * kTileY);
-        if (lx < v0 && ly < v1 && lz < v2) {
+        if (lx < g.v0 && ly < g.v1 && lz < g.v2) {
             uint32_t key[27];
 #pragma unroll
             for (int c = 0; c < 27; ++c) {
@@ -567,56 +587,94 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
                 key[kNet27.a[c]] = a < b ? a : b;
                 key[kNet27.b[c]] = a < b ? b : a;
             }
+            uint32_t* st = s_sten + tid * 27;
+            int32_t m = 0;
 #pragma unroll
             for (int q = 0; q < 27; ++q) {
                 const int32_t c = (int32_t)(key[q] & 31u);
                 const int32_t ex = c % 3, ey = (c / 3) % 3, ez = c / 9;
                 const int32_t u = (lx + ex) + kTUX * ((ly + ey) + kTUY * (lz + ez));
                 const uint32_t code = (uint32_t)ex | ((uint32_t)ey << 2) | ((uint32_t)ez << 4);
-                s_sten[tid * 27 + q] = (uint32_t)s_lstart[u] | ((uint32_t)s_lstart[u + 1] << 12) | (code << 24);
+                const int32_t a = s_lstart[u], b = s_lstart[u + 1];
+                if (a < b) st[m++] = (uint32_t)a | ((uint32_t)b << 12) | (code << 24);
             }
+            s_nne[tid] = (uint8_t)m;
         }
     }
     __syncthreads();
 
     // ---- the walk: one lane per particle of the tile ----
-    const float lo = P->tile_lo32, hi = P->tile_hi32;
+    // The next candidate (and, on a cell change, the stencil entry after the
+    // next) is requested from LDS before the current one is tested.
+    const float lo = P.tile_lo32, hi = P.tile_hi32;
     const bool coded = n <= kSlabJMask;
     const int64_t N = n;
-    for (int32_t i = i_lo + tid; i < i_hi; i += kThreads) {
+    for (int32_t i = g.i_lo + tid; i < g.i_hi; i += kThreads) {
         const uint32_t me = cell_xyz[i];
-        const int32_t lx = (int32_t)(me & 1023u) - o0, ly = (int32_t)((me >> 10) & 1023u) - o1,
-                      lz = (int32_t)(me >> 20) - o2;
+        const int32_t lx = (int32_t)(me & 1023u) - g.o0, ly = (int32_t)((me >> 10) & 1023u) - g.o1,
+                      lz = (int32_t)(me >> 20) - g.o2;
         const int32_t ui = (lx + 1) + kTUX * ((ly + 1) + kTUY * (lz + 1));
         const float4 wi = s_pos[s_lstart[ui] + (i - s_gstart[ui])];
-        const uint32_t* st = s_sten + (lx + kTileX * (ly + kTileY * lz)) * 27;
+        const int32_t ci = lx + kTileX * (ly + kTileY * lz);
+        const uint32_t* st = s_sten + ci * 27;
+        const int32_t nne = s_nne[ci];                   // >= 1: i's own cell is in its stencil
         int32_t* __restrict__ out = slab + (int64_t)i * slab_k;
         int32_t row = 0, q = 0;
         uint32_t ent = st[0];
+        uint32_t ent_n = st[nne > 1 ? 1 : 0];
         int32_t k = (int32_t)(ent & 0xFFFu), e = (int32_t)((ent >> 12) & 0xFFFu);
         uint32_t cs = coded ? (ent >> 24) << kSlabCodeShift : 0u;
+        float4 w = s_pos[k];
         for (;;) {
-            while (k >= e && q < 26) {                     // next non-empty stencil cell
-                ent = st[++q];
-                k = (int32_t)(ent & 0xFFFu);
-                e = (int32_t)((ent >> 12) & 0xFFFu);
-                cs = coded ? (ent >> 24) << kSlabCodeShift : 0u;
+            int32_t k2 = k + 1, e2 = e, q2 = q;
+            uint32_t cs2 = cs;
+            if (k2 >= e) {
+                q2 = q + 1;
+                k2 = (int32_t)(ent_n & 0xFFFu);
+                e2 = (int32_t)((ent_n >> 12) & 0xFFFu);
+                cs2 = coded ? (ent_n >> 24) << kSlabCodeShift : 0u;
             }
-            if (k >= e) break;
-            const float4 w = s_pos[k];
+            const bool more = q2 < nne;
+            const float4 w2 = s_pos[more ? k2 : k];
             const float dx = wi.x - w.x, dy = wi.y - w.y, dz = wi.z - w.z;
             const float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
             const int32_t j = __float_as_int(w.w);
             bool hit = j != i && r2 < lo;
-            if (j != i && !hit && r2 < hi) hit = exact_hit(*P, x, N, i, j);
+            if (j != i && !hit && r2 < hi) hit = exact_hit(P, x, N, i, j);
             if (hit) {
                 if (row < slab_k) out[row] = (int32_t)((uint32_t)j | cs);
                 ++row;
             }
-            ++k;
+            if (!more) break;
+            if (q2 != q) ent_n = st[q2 + 1 < nne ? q2 + 1 : q2];
+            k = k2; e = e2; q = q2; cs = cs2; w = w2;
         }
         offset[i] = row;
         if (row > slab_k) atomicOr(flag, 1);
+    }
+}
+
+// Tiles the tile builder left (neighbourhood over the LDS capacity, or a
+// system too small for distinct tile neighbourhoods): rest[0] tiles listed
+// in rest[1..], their particles walked by the lane builder.
+template <bool kB>
+__global__ __launch_bounds__(kBlock) void k_nlist_tile_rest(KParams kp, BatchView bv, int32_t n,
+                                                            const double* __restrict__ x,
+                                                            const float* __restrict__ x32,
+                                                            const uint32_t* __restrict__ cell_xyz,
+                                                            const int32_t* __restrict__ cell_start,
+                                                            const int32_t* __restrict__ rank_tab,
+                                                            int32_t* __restrict__ offset,
+                                                            int32_t* __restrict__ slab, int32_t slab_k,
+                                                            int32_t* __restrict__ flag,
+                                                            const int32_t* __restrict__ rest)
+{
+    const int32_t count = rest[0];
+    for (int32_t t = blockIdx.x; t < count; t += gridDim.x) {
+        const TileGeom g = tile_geom<kB>(kp, bv, rest[1 + t], cell_start, rank_tab);
+        for (int32_t i = g.i_lo + (int32_t)threadIdx.x; i < g.i_hi; i += kBlock)
+            nlist_lane<false>(*g.P, i, n, x, x32, cell_xyz, cell_start, rank_tab, offset, nullptr, slab, slab_k,
+                              flag);
     }
 }
 
@@ -624,21 +682,22 @@ template <bool kB, int kW>
 void launch_nlist_tiles_t(const KParams& kp, const BatchView& bv, int32_t n_tiles, int32_t n, const double* x,
                           const float* x32, const uint32_t* cell_xyz, const int32_t* cell_start,
                           const int32_t* rank_tab, int32_t* offset, int32_t* slab, int32_t slab_k, int32_t* flag,
-                          hipStream_t s)
+                          int32_t* rest, hipStream_t s)
 {
     hipLaunchKernelGGL((k_nlist_tiles<kB, kW>), dim3(n_tiles), dim3(kW * kWave), 0, s, kp, bv, n_tiles, n, x, x32,
-                       cell_xyz, cell_start, rank_tab, offset, slab, slab_k, flag);
+                       cell_xyz, cell_start, rank_tab, offset, slab, slab_k, flag, rest);
 }
 
+// tile pass, then the pass over the tiles it left; rest[0] must be 0
 template <bool kB>
 void launch_nlist_tiles(int waves, const KParams& kp, const BatchView& bv, int32_t n_tiles, int32_t n,
                         const double* x, const float* x32, const uint32_t* cell_xyz, const int32_t* cell_start,
                         const int32_t* rank_tab, int32_t* offset, int32_t* slab, int32_t slab_k, int32_t* flag,
-                        hipStream_t s)
+                        int32_t* rest, hipStream_t s)
 {
 #define DPD_TILE_CASE(W)                                                                                         \
     launch_nlist_tiles_t<kB, W>(kp, bv, n_tiles, n, x, x32, cell_xyz, cell_start, rank_tab, offset, slab, slab_k, \
-                                flag, s)
+                                flag, rest, s)
     if (waves <= 6) DPD_TILE_CASE(6);
     else if (waves <= 7) DPD_TILE_CASE(7);
     else if (waves <= 8) DPD_TILE_CASE(8);
@@ -646,6 +705,9 @@ void launch_nlist_tiles(int waves, const KParams& kp, const BatchView& bv, int32
     else if (waves <= 12) DPD_TILE_CASE(12);
     else DPD_TILE_CASE(16);
 #undef DPD_TILE_CASE
+    const int grid = n_tiles < 1024 ? n_tiles : 1024;
+    hipLaunchKernelGGL((k_nlist_tile_rest<kB>), dim3(grid), dim3(kBlock), 0, s, kp, bv, n, x, x32, cell_xyz,
+                       cell_start, rank_tab, offset, slab, slab_k, flag, (const int32_t*)rest);
 }
 
 }  // namespace
@@ -729,8 +791,8 @@ bool nlist_slab_coded(int kind, const uint32_t* cell_xyz, int32_t n_cells, int32
 hipError_t launch_nlist(const KParams& kp, const BatchView& bv, int32_t n_cells, int32_t n_blocks, int32_t n_tiles,
                         int32_t n, const double* x, const float* x32, const uint32_t* cell_xyz,
                         const int32_t* cell_start, const int32_t* rank_tab, int32_t* offset, int32_t* index,
-                        int64_t capacity, int32_t* slab, int32_t slab_k, int32_t* flag, int32_t* status,
-                        int32_t* scan_part, int waves, int kind, bool compact, hipStream_t s)
+                        int64_t capacity, int32_t* slab, int32_t slab_k, int32_t* flag, int32_t* tile_rest,
+                        int32_t* status, int32_t* scan_part, int waves, int kind, bool compact, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipError_t e;
@@ -739,13 +801,14 @@ hipError_t launch_nlist(const KParams& kp, const BatchView& bv, int32_t n_cells,
     if ((e = launch_fill_i32(offset + n, 1, 0, s)) != hipSuccess) return e;
     if ((e = launch_fill_i32(flag, 1, 0, s)) != hipSuccess) return e;
     if (tiles) {
+        if ((e = launch_fill_i32(tile_rest, 1, 0, s)) != hipSuccess) return e;
         const int tw = nlist_tile_waves(n, n_cells);
         if (bv.kps)
             launch_nlist_tiles<true>(tw, kp, bv, n_tiles, n, x, x32, cell_xyz, cell_start, rank_tab, offset, slab,
-                                     slab_k, flag, s);
+                                     slab_k, flag, tile_rest, s);
         else
             launch_nlist_tiles<false>(tw, kp, bv, n_tiles, n, x, x32, cell_xyz, cell_start, rank_tab, offset, slab,
-                                      slab_k, flag, s);
+                                      slab_k, flag, tile_rest, s);
     } else if (lanes)
         launch_nlist_lanes<false>(waves, kp, bv, n, x, x32, cell_xyz, cell_start, rank_tab, offset, index, capacity,
                                   slab, slab_k, flag, s);
