@@ -516,7 +516,7 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
     __shared__ int32_t s_rank[kTU];
     __shared__ int32_t s_gstart[kTU];
     __shared__ int32_t s_lstart[kTU + 1];
-    __shared__ float4 s_pos[kTilePos];
+    __shared__ float4 s_pos[kTilePos + 1];     // + 1: the walk's paired reads may touch one past the end
     __shared__ uint32_t s_sten[kTC * 27];      // before the sort: union cell of every staged slot
     __shared__ uint8_t s_nne[kTC];
     __shared__ int32_t s_w[kW];
@@ -604,8 +604,12 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
     __syncthreads();
 
     // ---- the walk: one lane per particle of the tile ----
-    // The next candidate (and, on a cell change, the stencil entry after the
-    // next) is requested from LDS before the current one is tested.
+    // Two candidates of a cell per step (slots k and k + 1; the second idles
+    // on a cell's odd last candidate; its read may then be the spare slot
+    // past the staged range, never used).  The next step's pair (and, on a cell
+    // change, the stencil entry after the next) is requested from LDS
+    // before the current pair is tested; two steps per loop turn alternate
+    // the buffers.
     const float lo = P.tile_lo32, hi = P.tile_hi32;
     const bool coded = n <= kSlabJMask;
     const int64_t N = n;
@@ -624,18 +628,7 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
         uint32_t ent_n = st[nne > 1 ? 1 : 0];
         int32_t k = (int32_t)(ent & 0xFFFu), e = (int32_t)((ent >> 12) & 0xFFFu);
         uint32_t cs = coded ? (ent >> 24) << kSlabCodeShift : 0u;
-        float4 w = s_pos[k];
-        for (;;) {
-            int32_t k2 = k + 1, e2 = e, q2 = q;
-            uint32_t cs2 = cs;
-            if (k2 >= e) {
-                q2 = q + 1;
-                k2 = (int32_t)(ent_n & 0xFFFu);
-                e2 = (int32_t)((ent_n >> 12) & 0xFFFu);
-                cs2 = coded ? (ent_n >> 24) << kSlabCodeShift : 0u;
-            }
-            const bool more = q2 < nne;
-            const float4 w2 = s_pos[more ? k2 : k];
+        auto test = [&](const float4& w) {
             const float dx = wi.x - w.x, dy = wi.y - w.y, dz = wi.z - w.z;
             const float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
             const int32_t j = __float_as_int(w.w);
@@ -645,9 +638,34 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
                 if (row < slab_k) out[row] = (int32_t)((uint32_t)j | cs);
                 ++row;
             }
-            if (!more) break;
+        };
+        // one step on the pair (wa, wb) at slot k, requesting the next pair
+        // into (na, nb); false when the walk has ended
+        auto step = [&](const float4& wa, const float4& wb, float4& na, float4& nb) {
+            int32_t k2 = k + 2, e2 = e, q2 = q;
+            uint32_t cs2 = cs;
+            if (k2 >= e) {
+                q2 = q + 1;
+                k2 = (int32_t)(ent_n & 0xFFFu);
+                e2 = (int32_t)((ent_n >> 12) & 0xFFFu);
+                cs2 = coded ? (ent_n >> 24) << kSlabCodeShift : 0u;
+            }
+            const bool more = q2 < nne;
+            const float4* pn = s_pos + (more ? k2 : k);
+            na = pn[0];
+            nb = pn[1];
+            const bool two = k + 1 < e;
+            test(wa);
+            if (two) test(wb);
+            if (!more) return false;
             if (q2 != q) ent_n = st[q2 + 1 < nne ? q2 + 1 : q2];
-            k = k2; e = e2; q = q2; cs = cs2; w = w2;
+            k = k2; e = e2; q = q2; cs = cs2;
+            return true;
+        };
+        float4 a0 = s_pos[k], b0 = s_pos[k + 1], a1, b1;
+        for (;;) {
+            if (!step(a0, b0, a1, b1)) break;
+            if (!step(a1, b1, a0, b0)) break;
         }
         offset[i] = row;
         if (row > slab_k) atomicOr(flag, 1);
