@@ -34,11 +34,12 @@ __device__ __forceinline__ double weight_r(double wc, int wmode, double s)
     }
 }
 
-// FP32 weight: hardware sqrt, or 2^(s log2 w_C) for a general exponent
+// FP32 weight: hardware square root (v_sqrt_f32, within an ulp), or
+// 2^(s log2 w_C) for a general exponent
 __device__ __forceinline__ float weight_r32(float wc, int wmode, float s)
 {
     switch (wmode) {
-    case 0: return sqrtf(wc);
+    case 0: return __builtin_amdgcn_sqrtf(wc);
     case 1: return wc;
     case 2: return wc * wc;
     default: return wc > 0.f ? exp2f(s * __log2f(wc)) : 0.f;
@@ -467,6 +468,13 @@ __device__ __forceinline__ PairIn load_pair(const ForceArgs& a, const float4* __
     return in;
 }
 
+// one batch's row position, pair and operands in the mixed pipeline
+struct Stage {
+    RowPos rp;
+    int32_t i, j, code;
+    PairIn in;
+};
+
 template <int kWMode, typename Tab>
 __device__ __forceinline__ bool pair32(const KParams& P, const Tab* A, const Tab* G, const Tab* S,
                                        const ForceArgs& a, const PairIn& in, int64_t N, int32_t i, int32_t j,
@@ -514,7 +522,7 @@ __device__ __forceinline__ bool pair32(const KParams& P, const Tab* A, const Tab
     float wc = 1.0f - rr * (float)P.inv_rc;
     wc = wc > 0.f ? wc : 0.f;
     const float wr = weight_r32(wc, kWMode, (float)P.s);
-    const float wd = wr * wr;
+    const float wd = kWMode == 0 ? wc : wr * wr;     // s = 1/2: w_D = w_R^2 = w_C exactly
     const float ev = ex * (qi.x - qj.x) + ey * (qi.y - qj.y) + ez * (qi.z - qj.z);
     const int tp = in.ti * P.n_types + in.tj;
     const float xi_ij = gauss32(pair_words(__float_as_uint(pi.w), __float_as_uint(pj.w), step, P.seed_lo, P.seed_hi));
@@ -549,33 +557,32 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
     const float4* __restrict__ vw = reinterpret_cast<const float4*>(a.v32);
     const int32_t* __restrict__ slab = usable_slab(a);
     const bool coded = slab && a.slab_coded;
-    double pe_tot = 0.0, np_tot = 0.0;
+    double pe_tot = 0.0;
+    int32_t np_tot = 0;                        // pairs inside r_c seen by this lane
     for (int32_t c = cw.first; c < cw.end; c += cw.stride) {
         const PairJob jb = chunk_job<kB>(bv, a, c, ok, lane);
         float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, pe_row = 0.f, np_row = 0.f;
         // software pipeline: the list entry two batches ahead and the pair
-        // operands one batch ahead are requested before a batch is evaluated
-        RowPos rp = row_pos(jb, jb.e0, lane);
+        // operands one batch ahead are requested before a batch is evaluated;
+        // two stages alternate (the loop is unrolled by two) so no operand is
+        // copied from one to the other
+        Stage A, B;
+        A.rp = row_pos(jb, jb.e0, lane);
+        A.i = jb.i0 + A.rp.r;
+        const int32_t raw0 = jb.e0 + lane < jb.e1 ? entry_at(slab, a.slab_k, a, jb, A.rp, jb.e0 + lane) : A.i;
+        A.j = entry_j(raw0, coded);
+        A.code = entry_code(raw0, coded);
+        A.in = load_pair(a, xw, vw, A.i, A.j);
         RowPos rp_nxt = row_pos(jb, jb.e0 + kWave, lane);
-        int32_t i_cur = jb.i0 + rp.r;
-        const int32_t raw0 = jb.e0 + lane < jb.e1 ? entry_at(slab, a.slab_k, a, jb, rp, jb.e0 + lane) : i_cur;
-        int32_t j_cur = entry_j(raw0, coded), code_cur = entry_code(raw0, coded);
-        int32_t raw_nxt = jb.e0 + kWave + lane < jb.e1
-                              ? entry_at(slab, a.slab_k, a, jb, rp_nxt, jb.e0 + kWave + lane) : 0;
         bool has_nxt = jb.e0 + kWave + lane < jb.e1;
-        PairIn in = load_pair(a, xw, vw, i_cur, j_cur);
-        for (int32_t eb = jb.e0; eb < jb.e1; eb += kWave) {
-            const int32_t e = eb + lane;
-            const bool valid = e < jb.e1;
-            const int32_t i = i_cur, j = j_cur, code = code_cur;
-            const PairIn cur = in;
-            // requests for the next batches
-            if (eb + kWave < jb.e1) {
-                rp = rp_nxt;
-                i_cur = jb.i0 + rp.r;
-                j_cur = has_nxt ? entry_j(raw_nxt, coded) : i_cur;
-                code_cur = entry_code(raw_nxt, coded);
-                in = load_pair(a, xw, vw, i_cur, j_cur);
+        int32_t raw_nxt = has_nxt ? entry_at(slab, a.slab_k, a, jb, rp_nxt, jb.e0 + kWave + lane) : 0;
+        auto batch = [&](const Stage& cur, Stage& nxt, int32_t eb) {
+            if (eb + kWave < jb.e1) {                   // requests for the next batches
+                nxt.rp = rp_nxt;
+                nxt.i = jb.i0 + nxt.rp.r;
+                nxt.j = has_nxt ? entry_j(raw_nxt, coded) : nxt.i;
+                nxt.code = entry_code(raw_nxt, coded);
+                nxt.in = load_pair(a, xw, vw, nxt.i, nxt.j);
                 const int32_t e2 = eb + 2 * kWave + lane;
                 has_nxt = e2 < jb.e1;
                 if (eb + 2 * kWave < jb.e1) {
@@ -583,17 +590,20 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
                     raw_nxt = has_nxt ? entry_at(slab, a.slab_k, a, jb, rp_nxt, e2) : 0;
                 }
             }
+            const bool valid = eb + lane < jb.e1;
             float px = 0.f, py = 0.f, pz = 0.f, pp = 0.f, pn = 0.f;
             if (valid) {
                 bool hit;
                 if constexpr (kB) {
-                    const KParams& P = bv.kps[bv.sys_of[i]];
-                    hit = pair32<kWMode>(P, P.a, P.g, P.srdt, a, cur, N, i, j, code, coded, step, px, py, pz, pp);
+                    const KParams& P = bv.kps[bv.sys_of[cur.i]];
+                    hit = pair32<kWMode>(P, P.a, P.g, P.srdt, a, cur.in, N, cur.i, cur.j, cur.code, coded, step,
+                                         px, py, pz, pp);
                 } else {
-                    hit = pair32<kWMode>(kp, s_a, s_g, s_s, a, cur, N, i, j, code, coded, step, px, py, pz, pp);
+                    hit = pair32<kWMode>(kp, s_a, s_g, s_s, a, cur.in, N, cur.i, cur.j, cur.code, coded, step,
+                                         px, py, pz, pp);
                 }
                 pn = hit ? 1.f : 0.f;
-                np_tot += pn;
+                np_tot += hit ? 1 : 0;
             }
             pe_tot += pp;
             // the FP32 prefix values stay within a few hundred, so a row's
@@ -615,6 +625,10 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
                 pe_row += tp2;
                 np_row += tn;
             }
+        };
+        for (int32_t eb = jb.e0; eb < jb.e1; eb += 2 * kWave) {
+            batch(A, B, eb);
+            if (eb + kWave < jb.e1) batch(B, A, eb + kWave);
         }
         if (lane < jb.ni) {
             const int32_t i = jb.i0 + lane;
@@ -636,7 +650,7 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
             if (want_np) a.npair[i] = (int32_t)np_row;
         }
     }
-    if (a.fred_part) block_partials2(pe_tot, 0.5 * np_tot, a.fred_part);
+    if (a.fred_part) block_partials2(pe_tot, 0.5 * (double)np_tot, a.fred_part);
 }
 
 }  // namespace
