@@ -439,7 +439,9 @@ constexpr int kTC = kTileX * kTileY * kTileZ;     // cells of a tile
 constexpr int kTilePos = 1536;                    // staged particles per tile
 // union cell whose origin is the tile frame's origin (keeps |positions| small)
 constexpr int kTFX = kTileX / 2 + 1, kTFY = kTileY / 2 + 1, kTFZ = kTileZ / 2 + 1;
-// stencil entry: LDS start | LDS end << 12 | slab code << 24
+// stencil entry: LDS start | LDS end << 12 | slab code << kSlabCodeShift
+// (the code is 0 when the slab is not coded), so an entry's code bits are
+// the ones a slab entry carries
 static_assert(kTilePos < 4096, "12-bit LDS offsets in the stencil entries");
 static_assert(kTC * 27 * 4 >= kTilePos * 2, "the staging map fits in the stencil table");
 
@@ -588,15 +590,16 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
                 key[kNet27.b[c]] = a < b ? b : a;
             }
             uint32_t* st = s_sten + tid * 27;
+            const uint32_t cmask = n <= kSlabJMask ? ~0u : 0u;     // uncoded slab: no code bits
             int32_t m = 0;
 #pragma unroll
             for (int q = 0; q < 27; ++q) {
                 const int32_t c = (int32_t)(key[q] & 31u);
                 const int32_t ex = c % 3, ey = (c / 3) % 3, ez = c / 9;
                 const int32_t u = (lx + ex) + kTUX * ((ly + ey) + kTUY * (lz + ez));
-                const uint32_t code = (uint32_t)ex | ((uint32_t)ey << 2) | ((uint32_t)ez << 4);
+                const uint32_t code = ((uint32_t)ex | ((uint32_t)ey << 2) | ((uint32_t)ez << 4)) & cmask;
                 const int32_t a = s_lstart[u], b = s_lstart[u + 1];
-                if (a < b) st[m++] = (uint32_t)a | ((uint32_t)b << 12) | (code << 24);
+                if (a < b) st[m++] = (uint32_t)a | ((uint32_t)b << 12) | (code << kSlabCodeShift);
             }
             s_nne[tid] = (uint8_t)m;
         }
@@ -611,8 +614,8 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
     // before the current pair is tested; two steps per loop turn alternate
     // the buffers.
     const float lo = P.tile_lo32, hi = P.tile_hi32;
-    const bool coded = n <= kSlabJMask;
     const int64_t N = n;
+    constexpr uint32_t kCodeBits = ~0u << kSlabCodeShift;
     for (int32_t i = g.i_lo + tid; i < g.i_hi; i += kThreads) {
         const uint32_t me = cell_xyz[i];
         const int32_t lx = (int32_t)(me & 1023u) - g.o0, ly = (int32_t)((me >> 10) & 1023u) - g.o1,
@@ -622,12 +625,17 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
         const int32_t ci = lx + kTileX * (ly + kTileY * lz);
         const uint32_t* st = s_sten + ci * 27;
         const int32_t nne = s_nne[ci];                   // >= 1: i's own cell is in its stencil
-        int32_t* __restrict__ out = slab + (int64_t)i * slab_k;
-        int32_t row = 0, q = 0;
+        // hits go to *optr while it is below the row's end (a longer row only
+        // counts; its overflow sends the build through the direct pass)
+        int32_t* const out = slab + (int64_t)i * slab_k;
+        int32_t* const out_end = out + slab_k;
+        int32_t* optr = out;
+        int32_t over = 0;
+        int32_t q = 0;
         uint32_t ent = st[0];
         uint32_t ent_n = st[nne > 1 ? 1 : 0];
         int32_t k = (int32_t)(ent & 0xFFFu), e = (int32_t)((ent >> 12) & 0xFFFu);
-        uint32_t cs = coded ? (ent >> 24) << kSlabCodeShift : 0u;
+        uint32_t cs = ent & kCodeBits;
         auto test = [&](const float4& w) {
             const float dx = wi.x - w.x, dy = wi.y - w.y, dz = wi.z - w.z;
             const float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
@@ -635,8 +643,8 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
             bool hit = j != i && r2 < lo;
             if (j != i && !hit && r2 < hi) hit = exact_hit(P, x, N, i, j);
             if (hit) {
-                if (row < slab_k) out[row] = (int32_t)((uint32_t)j | cs);
-                ++row;
+                if (optr < out_end) *optr++ = (int32_t)((uint32_t)j | cs);
+                else ++over;
             }
         };
         // one step on the pair (wa, wb) at slot k, requesting the next pair
@@ -648,7 +656,7 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
                 q2 = q + 1;
                 k2 = (int32_t)(ent_n & 0xFFFu);
                 e2 = (int32_t)((ent_n >> 12) & 0xFFFu);
-                cs2 = coded ? (ent_n >> 24) << kSlabCodeShift : 0u;
+                cs2 = ent_n & kCodeBits;
             }
             const bool more = q2 < nne;
             const float4* pn = s_pos + (more ? k2 : k);
@@ -667,6 +675,7 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
             if (!step(a0, b0, a1, b1)) break;
             if (!step(a1, b1, a0, b0)) break;
         }
+        const int32_t row = (int32_t)(optr - out) + over;
         offset[i] = row;
         if (row > slab_k) atomicOr(flag, 1);
     }
