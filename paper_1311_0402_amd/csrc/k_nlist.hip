@@ -530,7 +530,8 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
     if (g.i_lo == g.i_hi) return;
     const KParams& P = *g.P;
     const int tid = threadIdx.x;
-    const bool fits = P.tile_ok != 0;
+    // (the tile's slab rows are addressed with 32-bit byte offsets)
+    const bool fits = P.tile_ok != 0 && (int64_t)(g.i_hi - g.i_lo) * slab_k * 4 + 4 * kTilePos < INT32_MAX;
 
     // ---- union cells: thread u owns union cell u ----
     int32_t cnt = 0;
@@ -616,6 +617,13 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
     const float lo = P.tile_lo32, hi = P.tile_hi32;
     const int64_t N = n;
     constexpr uint32_t kCodeBits = ~0u << kSlabCodeShift;
+    // The tile's slab rows through a buffer resource: a row longer than the
+    // slab width runs on into the next rows of the tile (stores past the
+    // tile's last row are dropped by the range check); such a row sets the
+    // flag, and the whole slab is then discarded for the direct pass.
+    const int32_t n_here = g.i_hi - g.i_lo;
+    const auto rows = __builtin_amdgcn_make_buffer_rsrc(slab + (int64_t)g.i_lo * slab_k, (short)0,
+                                                        n_here * slab_k * (int32_t)sizeof(int32_t), 0x00020000);
     for (int32_t i = g.i_lo + tid; i < g.i_hi; i += kThreads) {
         const uint32_t me = cell_xyz[i];
         const int32_t lx = (int32_t)(me & 1023u) - g.o0, ly = (int32_t)((me >> 10) & 1023u) - g.o1,
@@ -625,13 +633,8 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
         const int32_t ci = lx + kTileX * (ly + kTileY * lz);
         const uint32_t* st = s_sten + ci * 27;
         const int32_t nne = s_nne[ci];                   // >= 1: i's own cell is in its stencil
-        // hits go to *optr while it is below the row's end (a longer row only
-        // counts; its overflow sends the build through the direct pass)
-        int32_t* const out = slab + (int64_t)i * slab_k;
-        int32_t* const out_end = out + slab_k;
-        int32_t* optr = out;
-        int32_t over = 0;
-        int32_t q = 0;
+        const int32_t row0 = (i - g.i_lo) * slab_k * (int32_t)sizeof(int32_t);
+        int32_t row = 0, q = 0;
         uint32_t ent = st[0];
         uint32_t ent_n = st[nne > 1 ? 1 : 0];
         int32_t k = (int32_t)(ent & 0xFFFu), e = (int32_t)((ent >> 12) & 0xFFFu);
@@ -643,30 +646,31 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
             bool hit = j != i && r2 < lo;
             if (j != i && !hit && r2 < hi) hit = exact_hit(P, x, N, i, j);
             if (hit) {
-                if (optr < out_end) *optr++ = (int32_t)((uint32_t)j | cs);
-                else ++over;
+                __builtin_amdgcn_raw_buffer_store_b32((int32_t)((uint32_t)j | cs), rows,
+                                                      row0 + row * (int32_t)sizeof(int32_t), 0, 0);
+                ++row;
             }
         };
         // one step on the pair (wa, wb) at slot k, requesting the next pair
-        // into (na, nb); false when the walk has ended
+        // into (na, nb) and the stencil entry after the next; false when the
+        // walk has ended
         auto step = [&](const float4& wa, const float4& wb, float4& na, float4& nb) {
-            int32_t k2 = k + 2, e2 = e, q2 = q;
-            uint32_t cs2 = cs;
-            if (k2 >= e) {
-                q2 = q + 1;
-                k2 = (int32_t)(ent_n & 0xFFFu);
-                e2 = (int32_t)((ent_n >> 12) & 0xFFFu);
-                cs2 = ent_n & kCodeBits;
-            }
+            const bool adv = k + 2 >= e;
+            const int32_t k2 = adv ? (int32_t)(ent_n & 0xFFFu) : k + 2;
+            const int32_t e2 = adv ? (int32_t)((ent_n >> 12) & 0xFFFu) : e;
+            const uint32_t cs2 = adv ? (ent_n & kCodeBits) : cs;
+            const int32_t q2 = q + (adv ? 1 : 0);
             const bool more = q2 < nne;
             const float4* pn = s_pos + (more ? k2 : k);
             na = pn[0];
             nb = pn[1];
+            const int32_t qn = q2 + 1 < nne ? q2 + 1 : nne - 1;
+            const uint32_t ent_nn = st[qn];
             const bool two = k + 1 < e;
             test(wa);
             if (two) test(wb);
             if (!more) return false;
-            if (q2 != q) ent_n = st[q2 + 1 < nne ? q2 + 1 : q2];
+            ent_n = adv ? ent_nn : ent_n;
             k = k2; e = e2; q = q2; cs = cs2;
             return true;
         };
@@ -675,7 +679,6 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
             if (!step(a0, b0, a1, b1)) break;
             if (!step(a1, b1, a0, b0)) break;
         }
-        const int32_t row = (int32_t)(optr - out) + over;
         offset[i] = row;
         if (row > slab_k) atomicOr(flag, 1);
     }

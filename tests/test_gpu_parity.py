@@ -61,6 +61,9 @@ def _systems():
         "edge_tiles": di.edge_case_fluid(seed=12, box=(12.0, 7.5, 6.5), n=600),
         "clustered_tiles": di.clustered_fluid(seed=13, box=(12.0, 7.0, 7.0), n_cluster=700, n_rest=600,
                                               size=1.5),
+        # a blob whose rows outgrow the slab width inside a tile the tile
+        # builder walks (the build then falls back to the direct pass)
+        "blob_tiles": di.clustered_fluid(seed=14, box=(12.0, 7.0, 7.0), n_cluster=300, n_rest=1200, size=2.0),
     }
 
 
