@@ -742,14 +742,16 @@ void launch_nlist_tiles(int waves, const KParams& kp, const BatchView& bv, int32
 
 }  // namespace
 
-// Waves per tile workgroup: the mean particle count of a tile plus three
-// standard deviations, so a second pass over a tile's particles is rare.
+// Waves per tile workgroup: the mean particle count of a tile plus 1.5
+// standard deviations (a tile with more particles walks the rest in a
+// second round), at least enough threads for one per union cell.
 int nlist_tile_waves(int32_t n, int32_t n_cells)
 {
     const double mean = (double)kTC * (double)n / (double)(n_cells > 0 ? n_cells : 1);
-    const double need = mean + 3.0 * std::sqrt(mean);
+    const double need = mean + 1.5 * std::sqrt(mean);
     int w = (int)std::ceil(need / kWave);
-    return w < 6 ? 6 : (w > 16 ? 16 : w);
+    constexpr int kMinW = (kTU + kWave - 1) / kWave;
+    return w < kMinW ? kMinW : (w > 16 ? 16 : w);
 }
 
 namespace {

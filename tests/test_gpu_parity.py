@@ -57,13 +57,13 @@ def _systems():
         # boxes of at least 10 x 6 x 6 cells go through the tile list builder:
         # partial tiles at the high faces, the planted cases, and a cluster
         # whose tile neighbourhood overflows the LDS staging
-        "ragged_tiles": di.uniform_fluid(5000, (13.7, 9.1, 11.3), 11),
-        "edge_tiles": di.edge_case_fluid(seed=12, box=(12.0, 7.5, 6.5), n=600),
-        "clustered_tiles": di.clustered_fluid(seed=13, box=(12.0, 7.0, 7.0), n_cluster=700, n_rest=600,
+        "ragged_tiles": di.uniform_fluid(5000, (13.7, 11.1, 9.3), 11),
+        "edge_tiles": di.edge_case_fluid(seed=12, box=(12.0, 10.5, 6.5), n=800),
+        "clustered_tiles": di.clustered_fluid(seed=13, box=(12.0, 10.5, 7.0), n_cluster=1600, n_rest=800,
                                               size=1.5),
         # a blob whose rows outgrow the slab width inside a tile the tile
         # builder walks (the build then falls back to the direct pass)
-        "blob_tiles": di.clustered_fluid(seed=14, box=(12.0, 7.0, 7.0), n_cluster=300, n_rest=1200, size=2.0),
+        "blob_tiles": di.clustered_fluid(seed=14, box=(12.0, 10.5, 7.0), n_cluster=300, n_rest=1500, size=2.0),
     }
 
 
