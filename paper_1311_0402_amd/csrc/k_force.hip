@@ -242,29 +242,49 @@ __device__ __forceinline__ PairJob chunk_job(const BatchView& bv, const ForceArg
     return j;
 }
 
-// Row of this lane's entry e = eb + lane, and the lane where that row's part
-// of the batch starts.  Rows are the chunk's lanes 0..ni-1 with contiguous,
-// ascending entry ranges; the rows overlapping the batch are ra..rb-1
-// (uniform, from two ballots) and the wave steps through their ends with
-// readlane, so no lane waits on a shuffle chain.
+// Row of this lane's entry e = eb + lane (the number of the chunk's rows
+// that end at or before e), the lane where that row's part of the batch
+// starts and the row's first entry.  Rows finished before the batch are
+// counted with a ballot; each non-empty row starting inside the batch marks
+// the lane of its first entry in a per-wave LDS row (LDS operations of one
+// wave take effect in program order), and an inclusive prefix maximum over
+// the lanes carries each mark to the row's later entries.
 struct RowPos {
     int32_t r, ss;
     int32_t start;       // first entry of the row (absolute)
 };
 
-__device__ __forceinline__ RowPos row_pos(const PairJob& jb, int32_t eb, int lane)
+__device__ __forceinline__ int32_t wave_max_prefix(int32_t v)
+{
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, kDppRowShr | 1, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, kDppRowShr | 2, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, kDppRowShr | 4, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, kDppRowShr | 8, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, kDppBcast15, 0xA, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, kDppBcast31, 0xC, 0xF, false));
+    return v;
+}
+
+__device__ __forceinline__ RowPos row_pos(const PairJob& jb, int32_t eb, int lane, int32_t* __restrict__ s_mark)
 {
     const bool own = lane < jb.ni;
     const int32_t ra = (int32_t)__popcll(__ballot(own && jb.rend <= eb));
-    const int32_t rb = (int32_t)__popcll(__ballot(own && jb.rstart < eb + kWave));
-    const int32_t e = eb + lane;
-    RowPos p{ra, 0, __builtin_amdgcn_readlane(jb.rstart, ra < kWave ? ra : kWave - 1)};
-    for (int32_t q = ra; q < rb; ++q) {
-        const int32_t t = __builtin_amdgcn_readlane(jb.rend, q);
-        if (e >= t) { p.r = q + 1; p.ss = t - eb; p.start = t; }
-    }
-    p.r = p.r < jb.ni ? p.r : jb.ni - 1;       // lanes past the last entry
-    return p;
+    const int32_t p = jb.rstart - eb;
+    // compiler memory barriers: the previous call's reads stay before these
+    // writes, and the read below comes from LDS (other lanes' marks), never
+    // from this lane's own store
+    __asm__ __volatile__("" ::: "memory");
+    s_mark[lane] = 0;
+    if (own && jb.rend > jb.rstart && p >= 0 && p < kWave) s_mark[p] = lane + 1;
+    __asm__ __volatile__("" ::: "memory");
+    const int32_t v = wave_max_prefix(s_mark[lane]);
+    int32_t r = (v > ra + 1 ? v : ra + 1) - 1;
+    r = r < jb.ni ? r : jb.ni - 1;             // lanes past the last entry
+    RowPos rp;
+    rp.r = r;
+    rp.start = __shfl(jb.rstart, r, kWave);
+    rp.ss = rp.start - eb > 0 ? rp.start - eb : 0;
+    return rp;
 }
 
 // Entry e of the chunk's rows: from the builder's fixed-width slab while it
@@ -362,6 +382,7 @@ template <int kWMode, bool kB>
 __global__ __launch_bounds__(kBlock) void k_force_fp64(KParams kp, BatchView bv, ForceArgs a, int32_t n_chunks)
 {
     __shared__ double s_a[kTab], s_g[kTab], s_s[kTab];
+    __shared__ int32_t s_rowm[kBlock];                 // per-wave row marks (row_pos)
     if (!kB) {
         const int nt2 = kp.n_types * kp.n_types;
         for (int t = threadIdx.x; t < nt2; t += kBlock) {
@@ -370,6 +391,7 @@ __global__ __launch_bounds__(kBlock) void k_force_fp64(KParams kp, BatchView bv,
         __syncthreads();
     }
     const int lane = threadIdx.x & (kWave - 1);
+    int32_t* const s_mark = s_rowm + (threadIdx.x - lane);
     const ChunkWalk cw = chunk_walk(n_chunks);
     const int64_t N = a.n;
     const uint64_t step = (a.d_step ? *a.d_step : 0ull) + a.step_add;
@@ -385,7 +407,7 @@ __global__ __launch_bounds__(kBlock) void k_force_fp64(KParams kp, BatchView bv,
         for (int32_t eb = jb.e0; eb < jb.e1; eb += kWave) {
             const int32_t e = eb + lane;
             const bool valid = e < jb.e1;
-            const RowPos rp = row_pos(jb, eb, lane);
+            const RowPos rp = row_pos(jb, eb, lane, s_mark);
             const int32_t r = rp.r;
             const int32_t i = jb.i0 + r;
             const int32_t j = valid ? entry_j(entry_at(slab, a.slab_k, a, jb, rp, e), coded) : i;
@@ -539,6 +561,7 @@ template <int kWMode, bool kB>
 __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv, ForceArgs a, int32_t n_chunks)
 {
     __shared__ float s_a[kTab], s_g[kTab], s_s[kTab];
+    __shared__ int32_t s_rowm[kBlock];                 // per-wave row marks (row_pos)
     if (!kB) {
         const int nt2 = kp.n_types * kp.n_types;
         for (int t = threadIdx.x; t < nt2; t += kBlock) {
@@ -547,6 +570,7 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
         __syncthreads();
     }
     const int lane = threadIdx.x & (kWave - 1);
+    int32_t* const s_mark = s_rowm + (threadIdx.x - lane);
     const ChunkWalk cw = chunk_walk(n_chunks);
     const int64_t N = a.n;
     const uint64_t step = (a.d_step ? *a.d_step : 0ull) + a.step_add;
@@ -567,13 +591,13 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
         // two stages alternate (the loop is unrolled by two) so no operand is
         // copied from one to the other
         Stage A, B;
-        A.rp = row_pos(jb, jb.e0, lane);
+        A.rp = row_pos(jb, jb.e0, lane, s_mark);
         A.i = jb.i0 + A.rp.r;
         const int32_t raw0 = jb.e0 + lane < jb.e1 ? entry_at(slab, a.slab_k, a, jb, A.rp, jb.e0 + lane) : A.i;
         A.j = entry_j(raw0, coded);
         A.code = entry_code(raw0, coded);
         A.in = load_pair(a, xw, vw, A.i, A.j);
-        RowPos rp_nxt = row_pos(jb, jb.e0 + kWave, lane);
+        RowPos rp_nxt = row_pos(jb, jb.e0 + kWave, lane, s_mark);
         bool has_nxt = jb.e0 + kWave + lane < jb.e1;
         int32_t raw_nxt = has_nxt ? entry_at(slab, a.slab_k, a, jb, rp_nxt, jb.e0 + kWave + lane) : 0;
         auto batch = [&](const Stage& cur, Stage& nxt, int32_t eb) {
@@ -586,7 +610,7 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
                 const int32_t e2 = eb + 2 * kWave + lane;
                 has_nxt = e2 < jb.e1;
                 if (eb + 2 * kWave < jb.e1) {
-                    rp_nxt = row_pos(jb, eb + 2 * kWave, lane);
+                    rp_nxt = row_pos(jb, eb + 2 * kWave, lane, s_mark);
                     raw_nxt = has_nxt ? entry_at(slab, a.slab_k, a, jb, rp_nxt, e2) : 0;
                 }
             }
