@@ -163,8 +163,8 @@ size_t dpd_workspace_bytes(const dpd_params* p, int32_t n, int32_t precision);
  * packed FP32 copies, one float4 per sorted particle ([n][4], 16-byte
  * aligned): x32[i] = ((float)(x_k - c_k L_k / n_c,k) for k = x, y, z -- the
  * offset inside the particle's cell --, tag bits) and v32[i] = ((float)v,
- * cell_xyz bits).  The neighbour list needs x32; the mixed-precision force
- * needs both. */
+ * type as uint32 bits).  The neighbour list needs x32; the mixed-precision
+ * force needs both. */
 int dpd_bin_reorder(const dpd_params* p, const dpd_state* in, dpd_state* out,
                     dpd_cells* cells, float* x32, float* v32,
                     void* ws, size_t ws_bytes, void* stream);

@@ -472,21 +472,23 @@ __device__ __forceinline__ int cell_delta(int32_t ci, int32_t cj, int32_t n)
     return d < -1 ? d + n : d;
 }
 
-// One pair in the mixed form.  xw[i] = (x, y, z offsets inside the cell,
-// tag bits), vw[i] = (predicted velocity, cell bits), both float4.
-// The operands of one mixed-form pair, loaded a batch ahead of their use.
+// The operands of one mixed-form pair, loaded a batch ahead of their use:
+// xw[i] = (x, y, z offsets inside the cell, tag bits), vw[i] = (predicted
+// velocity, type), both float4; the packed cells are read only for list
+// entries without a stencil code.
 struct PairIn {
     float4 pi, qi, pj, qj;
-    int32_t ti, tj;
+    uint32_t ci, cj;
 };
 
 __device__ __forceinline__ PairIn load_pair(const ForceArgs& a, const float4* __restrict__ xw,
-                                            const float4* __restrict__ vw, int32_t i, int32_t j)
+                                            const float4* __restrict__ vw, int32_t i, int32_t j, bool coded)
 {
     PairIn in;
     in.pi = xw[i]; in.qi = vw[i];
     in.pj = xw[j]; in.qj = vw[j];
-    in.ti = a.type[i]; in.tj = a.type[j];
+    in.ci = 0u; in.cj = 0u;
+    if (!coded) { in.ci = a.cell_xyz[i]; in.cj = a.cell_xyz[j]; }
     return in;
 }
 
@@ -513,7 +515,7 @@ __device__ __forceinline__ bool pair32(const KParams& P, const Tab* A, const Tab
         oy = (float)(1 - ((code >> 2) & 3)) * P.cell_len32[1];
         oz = (float)(1 - (code >> 4)) * P.cell_len32[2];
     } else {
-        const uint32_t ci = __float_as_uint(qi.w), cj = __float_as_uint(qj.w);
+        const uint32_t ci = in.ci, cj = in.cj;
         ox = (float)cell_delta((int32_t)(ci & 1023u), (int32_t)(cj & 1023u), P.nc[0]) * P.cell_len32[0];
         oy = (float)cell_delta((int32_t)((ci >> 10) & 1023u), (int32_t)((cj >> 10) & 1023u), P.nc[1]) * P.cell_len32[1];
         oz = (float)cell_delta((int32_t)(ci >> 20), (int32_t)(cj >> 20), P.nc[2]) * P.cell_len32[2];
@@ -546,7 +548,7 @@ __device__ __forceinline__ bool pair32(const KParams& P, const Tab* A, const Tab
     const float wr = weight_r32(wc, kWMode, (float)P.s);
     const float wd = kWMode == 0 ? wc : wr * wr;     // s = 1/2: w_D = w_R^2 = w_C exactly
     const float ev = ex * (qi.x - qj.x) + ey * (qi.y - qj.y) + ez * (qi.z - qj.z);
-    const int tp = in.ti * P.n_types + in.tj;
+    const int tp = (int)__float_as_uint(qi.w) * P.n_types + (int)__float_as_uint(qj.w);
     const float xi_ij = gauss32(pair_words(__float_as_uint(pi.w), __float_as_uint(pj.w), step, P.seed_lo, P.seed_hi));
     const float at = (float)A[tp], gt = (float)G[tp], st = (float)S[tp];
     const float phi = at * wc - gt * wd * ev + st * wr * xi_ij;
@@ -596,7 +598,7 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
         const int32_t raw0 = jb.e0 + lane < jb.e1 ? entry_at(slab, a.slab_k, a, jb, A.rp, jb.e0 + lane) : A.i;
         A.j = entry_j(raw0, coded);
         A.code = entry_code(raw0, coded);
-        A.in = load_pair(a, xw, vw, A.i, A.j);
+        A.in = load_pair(a, xw, vw, A.i, A.j, coded);
         RowPos rp_nxt = row_pos(jb, jb.e0 + kWave, lane, s_mark);
         bool has_nxt = jb.e0 + kWave + lane < jb.e1;
         int32_t raw_nxt = has_nxt ? entry_at(slab, a.slab_k, a, jb, rp_nxt, jb.e0 + kWave + lane) : 0;
@@ -606,7 +608,7 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
                 nxt.i = jb.i0 + nxt.rp.r;
                 nxt.j = has_nxt ? entry_j(raw_nxt, coded) : nxt.i;
                 nxt.code = entry_code(raw_nxt, coded);
-                nxt.in = load_pair(a, xw, vw, nxt.i, nxt.j);
+                nxt.in = load_pair(a, xw, vw, nxt.i, nxt.j, coded);
                 const int32_t e2 = eb + 2 * kWave + lane;
                 has_nxt = e2 < jb.e1;
                 if (eb + 2 * kWave < jb.e1) {

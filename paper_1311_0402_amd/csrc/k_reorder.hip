@@ -323,7 +323,7 @@ __device__ __forceinline__ void finalize_one(const KParams& P, int32_t n, int32_
         w.x = (float)vv[0];
         w.y = (float)vv[1];
         w.z = (float)vv[2];
-        w.w = __uint_as_float(packed);
+        w.w = __uint_as_float((uint32_t)ty);
         reinterpret_cast<float4*>(g.v32)[dst] = w;
     }
 }

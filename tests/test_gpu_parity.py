@@ -93,7 +93,7 @@ def test_bin_reorder_bitexact(name):
     np.testing.assert_array_equal(dst.type.cpu().numpy(), s.type[perm_ref])
     iot = cells.idx_of_tag.cpu().numpy()
     np.testing.assert_array_equal(iot[s.tag[perm_ref]], np.arange(s.n))
-    # packed FP32 copies: (offset inside the cell, tag bits), (velocity, cell bits)
+    # packed FP32 copies: (offset inside the cell, tag bits), (velocity, type)
     cxyz = cells.cell_xyz.cpu().numpy().view(np.uint32)
     cc = np.stack([cxyz & 1023, (cxyz >> 10) & 1023, cxyz >> 20]).astype(np.float64)
     np.testing.assert_array_equal(cc, np.minimum(np.array(nc)[:, None] - 1,
@@ -105,7 +105,7 @@ def test_bin_reorder_bitexact(name):
     np.testing.assert_array_equal(xw[:, :3].T, (xs - cc * ell[:, None]).astype(np.float32))
     np.testing.assert_array_equal(xw[:, 3].view(np.uint32), s.tag[perm_ref])
     np.testing.assert_array_equal(vw[:, :3].T, s.v[:, perm_ref].astype(np.float32))
-    np.testing.assert_array_equal(vw[:, 3].view(np.uint32), cxyz)
+    np.testing.assert_array_equal(vw[:, 3].view(np.uint32), s.type[perm_ref].astype(np.uint32))
 
 
 def test_bin_reorder_is_deterministic_and_idempotent():
