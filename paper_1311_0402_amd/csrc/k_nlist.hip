@@ -439,6 +439,11 @@ constexpr int kTC = kTileX * kTileY * kTileZ;     // cells of a tile
 constexpr int kTilePos = 1536;                    // staged particles per tile
 // union cell whose origin is the tile frame's origin (keeps |positions| small)
 constexpr int kTFX = kTileX / 2 + 1, kTFY = kTileY / 2 + 1, kTFZ = kTileZ / 2 + 1;
+// candidates a lane tests per step of the walk, and their operands
+constexpr int kStepW = 2;
+struct StepW {
+    float4 w[kStepW];
+};
 // stencil entry: LDS start | LDS end << 12 | slab code << kSlabCodeShift
 // (the code is 0 when the slab is not coded), so an entry's code bits are
 // the ones a slab entry carries
@@ -518,7 +523,7 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
     __shared__ int32_t s_rank[kTU];
     __shared__ int32_t s_gstart[kTU];
     __shared__ int32_t s_lstart[kTU + 1];
-    __shared__ float4 s_pos[kTilePos + 1];     // + 1: the walk's paired reads may touch one past the end
+    __shared__ float4 s_pos[kTilePos + kStepW - 1];   // spare slots: a step's reads may run past the end
     __shared__ uint32_t s_sten[kTC * 27];      // before the sort: union cell of every staged slot
     __shared__ uint8_t s_nne[kTC];
     __shared__ int32_t s_w[kW];
@@ -608,11 +613,11 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
     __syncthreads();
 
     // ---- the walk: one lane per particle of the tile ----
-    // Two candidates of a cell per step (slots k and k + 1; the second idles
-    // on a cell's odd last candidate; its read may then be the spare slot
-    // past the staged range, never used).  The next step's pair (and, on a cell
-    // change, the stencil entry after the next) is requested from LDS
-    // before the current pair is tested; two steps per loop turn alternate
+    // kStepW candidates of a cell per step (slots k, k + 1, ...; slots past
+    // the cell's end idle, and their reads may be the spare slots past the
+    // staged range, never used).  The next step's candidates (and, on a cell
+    // change, the stencil entry after the next) are requested from LDS
+    // before the current ones are tested; two steps per loop turn alternate
     // the buffers.
     const float lo = P.tile_lo32, hi = P.tile_hi32;
     const int64_t N = n;
@@ -651,33 +656,36 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
                 ++row;
             }
         };
-        // one step on the pair (wa, wb) at slot k, requesting the next pair
-        // into (na, nb) and the stencil entry after the next; false when the
-        // walk has ended
-        auto step = [&](const float4& wa, const float4& wb, float4& na, float4& nb) {
-            const bool adv = k + 2 >= e;
-            const int32_t k2 = adv ? (int32_t)(ent_n & 0xFFFu) : k + 2;
+        // one step on the candidates at slots k .. k + kStepW - 1 (those below
+        // the cell's end), requesting the next step's into nxt and the
+        // stencil entry after the next; false when the walk has ended
+        auto step = [&](const StepW& cur, StepW& nxt) {
+            const bool adv = k + kStepW >= e;
+            const int32_t k2 = adv ? (int32_t)(ent_n & 0xFFFu) : k + kStepW;
             const int32_t e2 = adv ? (int32_t)((ent_n >> 12) & 0xFFFu) : e;
             const uint32_t cs2 = adv ? (ent_n & kCodeBits) : cs;
             const int32_t q2 = q + (adv ? 1 : 0);
             const bool more = q2 < nne;
             const float4* pn = s_pos + (more ? k2 : k);
-            na = pn[0];
-            nb = pn[1];
+#pragma unroll
+            for (int m = 0; m < kStepW; ++m) nxt.w[m] = pn[m];
             const int32_t qn = q2 + 1 < nne ? q2 + 1 : nne - 1;
             const uint32_t ent_nn = st[qn];
-            const bool two = k + 1 < e;
-            test(wa);
-            if (two) test(wb);
+            test(cur.w[0]);
+#pragma unroll
+            for (int m = 1; m < kStepW; ++m)
+                if (k + m < e) test(cur.w[m]);
             if (!more) return false;
             ent_n = adv ? ent_nn : ent_n;
             k = k2; e = e2; q = q2; cs = cs2;
             return true;
         };
-        float4 a0 = s_pos[k], b0 = s_pos[k + 1], a1, b1;
+        StepW s0, s1;
+#pragma unroll
+        for (int m = 0; m < kStepW; ++m) s0.w[m] = s_pos[k + m];
         for (;;) {
-            if (!step(a0, b0, a1, b1)) break;
-            if (!step(a1, b1, a0, b0)) break;
+            if (!step(s0, s1)) break;
+            if (!step(s1, s0)) break;
         }
         offset[i] = row;
         if (row > slab_k) atomicOr(flag, 1);
