@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <utility>
 #include <memory>
 #include <string>
 #include <vector>
@@ -250,6 +251,10 @@ WsLayout ws_layout(const Job& job, int32_t n, bool aos = false)
     w.pe_part = take(N * sizeof(double));
     w.np_part = take(N * sizeof(int32_t));
     w.tile_rest = take(((size_t)(job.n_tiles > 0 ? job.n_tiles : 0) + 1) * sizeof(int32_t));
+    const bool bonds = job.kp.partner != nullptr;
+    w.pidx_a = bonds ? take(2 * N * sizeof(int32_t)) : 0;
+    w.pidx_b = bonds ? take(2 * N * sizeof(int32_t)) : 0;
+    w.inv = bonds ? take(N * sizeof(int32_t)) : 0;
     w.x64 = aos ? take(N * 4 * sizeof(double)) : 0;
     w.v64 = aos ? take(N * 4 * sizeof(double)) : 0;
     w.total = o;
@@ -263,7 +268,8 @@ namespace {
 // binning + reordering from `in` into `out` (shared by dpd_bin_reorder and dpd_step)
 int enqueue_reorder(const Job& job, const WsLayout& L, void* ws, const dpd_state* in,
                     const double* vt_in, dpd_state* out, double* vt_out, dpd_cells* cells,
-                    float* x32, float* v32, hipStream_t s, bool aos = false)
+                    float* x32, float* v32, hipStream_t s, bool aos = false, int32_t* inv = nullptr,
+                    bool write_iot = true)
 {
     const int32_t n = in->n;
     int32_t* key = carve<int32_t>(ws, L.key);
@@ -281,7 +287,8 @@ int enqueue_reorder(const Job& job, const WsLayout& L, void* ws, const dpd_state
     GatherArgs g;
     g.x_in = in->x; g.v_in = in->v; g.vt_in = vt_in; g.type_in = in->type; g.cxyz_in = cxyz;
     g.x_out = out->x; g.v_out = out->v; g.vt_out = vt_out; g.tag_out = out->tag; g.type_out = out->type;
-    g.cell_xyz = cells->cell_xyz; g.perm = cells->perm; g.idx_of_tag = cells->idx_of_tag;
+    g.cell_xyz = cells->cell_xyz; g.perm = cells->perm; g.idx_of_tag = write_iot ? cells->idx_of_tag : nullptr;
+    g.inv = inv;
     g.x32 = x32; g.v32 = v32;
     g.x64 = aos ? carve<double>(ws, L.x64) : nullptr;
     g.v64 = aos ? carve<double>(ws, L.v64) : nullptr;
@@ -616,6 +623,14 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
     double* fsum_part = carve<double>(ws, L.fsum_part);
     const bool mixed = precision == DPD_MIXED;
 
+    // Bonds: the first reorder of the call writes the tag -> index map and
+    // the partners' sorted indices are looked up from it once; later steps
+    // carry them from reorder to reorder (coherent gathers instead of a
+    // scatter by tag), and the map is written again at the last step.
+    int32_t* pidx_cur = bonds ? carve<int32_t>(ws, L.pidx_a) : nullptr;
+    int32_t* pidx_nxt = bonds ? carve<int32_t>(ws, L.pidx_b) : nullptr;
+    int32_t* inv = bonds ? carve<int32_t>(ws, L.inv) : nullptr;
+
     auto mark = [&](int32_t k, int phase) -> hipError_t {
         if (!phase_events) return hipSuccess;
         return hipEventRecord(reinterpret_cast<hipEvent_t>(phase_events[6 * (int64_t)k + phase]), s);
@@ -624,8 +639,18 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
         DPD_TRY(mark(k, 0), "event");
         DPD_TRY(launch_vv1(kp, job.bv, n, st->x, st->v, st->f, st->tag, st->type, b.x, b.v, bvt, b.tag, b.type, s), "vv1");
         DPD_TRY(mark(k, 1), "event");
-        rc = enqueue_reorder(job, L, ws, &b, bvt, st, vt_sorted, cells, x32, mixed ? v32 : nullptr, s, aos);
+        rc = enqueue_reorder(job, L, ws, &b, bvt, st, vt_sorted, cells, x32, mixed ? v32 : nullptr, s, aos,
+                             k > 0 ? inv : nullptr, !bonds || k == 0 || k == n_steps - 1);
         if (rc) return rc;
+        if (bonds) {
+            if (k == 0) {
+                DPD_TRY(launch_pidx_init(kp, n, st->tag, cells->idx_of_tag, pidx_cur, s), "bond partners");
+            } else {
+                DPD_TRY(launch_pidx_update(n, cells->perm, inv, pidx_cur, pidx_nxt, s), "bond partners");
+                std::swap(pidx_cur, pidx_nxt);
+            }
+            a.pidx = pidx_cur;
+        }
         DPD_TRY(mark(k, 2), "event");
         // inside a call the force pass reads the builder's slab; the CSR list
         // is written for the last step, which the caller sees

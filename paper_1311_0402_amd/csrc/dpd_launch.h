@@ -37,6 +37,8 @@ struct WsLayout {
     size_t x64, v64;                   // packed FP64 copies for the FP64 step (0 when not laid out)
     size_t np_part;                    // per-particle pair count (batch statistics)
     size_t tile_rest;                  // tiles left by the tile list builder: count, then tile ids
+    size_t pidx_a, pidx_b, inv;        // bonds inside a step loop: partner indices (2 per particle,
+                                       // two generations) and the old -> new index map
     size_t total;
 };
 
@@ -58,10 +60,19 @@ struct GatherArgs {
     const double* x_in; const double* v_in; const double* vt_in; const uint8_t* type_in;
     const uint32_t* cxyz_in;
     double* x_out; double* v_out; double* vt_out; uint32_t* tag_out; uint8_t* type_out;
-    uint32_t* cell_xyz; int32_t* perm; int32_t* idx_of_tag;
+    uint32_t* cell_xyz; int32_t* perm; int32_t* idx_of_tag;   // idx_of_tag nullable
+    int32_t* inv = nullptr;         // nullable: inv[source index] = sorted index
     float* x32; float* v32;
     double* x64; double* v64;       // nullable: packed FP64 copies, double4 per particle
 };
+// bond partners of the sorted particles as sorted indices: pidx[2 i + b] =
+// idx_of_tag[partner[2 tag[i] + b]], -1 without a partner, -2 when the
+// partner tag has no particle
+hipError_t launch_pidx_init(const KParams& kp, int32_t n, const uint32_t* tag, const int32_t* idx_of_tag,
+                            int32_t* pidx, hipStream_t s);
+// after a reorder: pidx_new[2 d + b] = inv[pidx_old[2 perm[d] + b]] (negative values kept)
+hipError_t launch_pidx_update(int32_t n, const int32_t* perm, const int32_t* inv, const int32_t* pidx_old,
+                              int32_t* pidx_new, hipStream_t s);
 hipError_t launch_finalize(const KParams& kp, const BatchView& bv, int32_t n, const int32_t* tmp_key,
                            const int32_t* cell_start, const uint32_t* tmp_tag, const int32_t* tmp_src,
                            const GatherArgs& g, hipStream_t s);
@@ -100,6 +111,8 @@ struct ForceArgs {
     const uint32_t* cell_xyz; const float* x32; const float* v32;
     const int32_t* offset; const int32_t* index; int64_t capacity;
     const int32_t* idx_of_tag;
+    const int32_t* pidx = nullptr;                // nullable: bond partners' sorted indices, 2 per particle
+                                                  //   (-1 none, -2 missing); else partner + idx_of_tag
     const uint64_t* d_step; uint64_t step_add;   // step = (d_step ? *d_step : 0) + step_add
     double* f; double* pe;                        // pe nullable
     int32_t* npair;                               // nullable: pairs inside r_c per particle

@@ -72,13 +72,19 @@ __device__ __forceinline__ void add_bonds_body(const KParams& kp, const ForceArg
                                                double& fz, double& pe)
 {
     const int64_t N = a.n;
-    if (kp.partner && a.tag[i] < (uint32_t)a.n) {
-        const uint32_t t = a.tag[i];
+    if (kp.partner && (a.pidx || a.tag[i] < (uint32_t)a.n)) {
+        const uint32_t t = a.pidx ? 0u : a.tag[i];
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-            const int32_t pt = kp.partner[2 * (int64_t)t + b];
-            if (pt < 0) continue;
-            const int32_t j = (pt < a.n) ? a.idx_of_tag[pt] : -1;
+            int32_t j;
+            if (a.pidx) {
+                j = a.pidx[2 * (int64_t)i + b];
+                if (j == -1) continue;
+            } else {
+                const int32_t pt = kp.partner[2 * (int64_t)t + b];
+                if (pt < 0) continue;
+                j = (pt < a.n) ? a.idx_of_tag[pt] : -1;
+            }
             if (j < 0 || j >= a.n) {
                 if (a.status) atomicOr(a.status, 4 /* DPD_STATUS_BAD_BOND */);
                 continue;

@@ -281,6 +281,7 @@ __device__ __forceinline__ void finalize_one(const KParams& P, int32_t n, int32_
     for (int32_t q = lo; q < hi; ++q) below += (tmp_tag[q] < t) ? 1 : 0;
     const int32_t dst = lo + below;
     g.perm[dst] = src;
+    if (g.inv) g.inv[src] = dst;
     g.tag_out[dst] = t;
     g.type_out[dst] = ty;
     g.cell_xyz[dst] = packed;
@@ -340,6 +341,66 @@ __global__ __launch_bounds__(kBlock) void k_finalize(KParams kp, BatchView bv, i
     // a particle never leaves its system, so position p and its source share it
     if constexpr (kB) finalize_one(bv.kps[bv.sys_of[p]], n, p, tmp_key, cell_start, tmp_tag, tmp_src, g);
     else finalize_one(kp, n, p, tmp_key, cell_start, tmp_tag, tmp_src, g);
+}
+
+namespace {
+
+__global__ __launch_bounds__(kBlock) void k_pidx_init(int32_t n, const uint32_t* __restrict__ tag,
+                                                      const int32_t* __restrict__ partner, int32_t n_tags,
+                                                      const int32_t* __restrict__ idx_of_tag,
+                                                      int32_t* __restrict__ pidx)
+{
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t t = tag[i];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        int32_t j = -1;
+        if (t < (uint32_t)n_tags) {
+            const int32_t pt = partner[2 * (int64_t)t + b];
+            if (pt >= 0) {
+                j = pt < n_tags ? idx_of_tag[pt] : -2;
+                j = (j >= 0 && j < n) ? j : -2;
+            }
+        }
+        pidx[2 * (int64_t)i + b] = j;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pidx_update(int32_t n, const int32_t* __restrict__ perm,
+                                                        const int32_t* __restrict__ inv,
+                                                        const int32_t* __restrict__ pidx_old,
+                                                        int32_t* __restrict__ pidx_new)
+{
+    const int32_t d = blockIdx.x * kBlock + threadIdx.x;
+    if (d >= n) return;
+    const int32_t src = perm[d];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int32_t po = pidx_old[2 * (int64_t)src + b];
+        pidx_new[2 * (int64_t)d + b] = po < 0 ? po : inv[po];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_pidx_init(const KParams& kp, int32_t n, const uint32_t* tag, const int32_t* idx_of_tag,
+                            int32_t* pidx, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    // tags of a single system run 0 .. n - 1
+    hipLaunchKernelGGL(k_pidx_init, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, n, tag, kp.partner, n,
+                       idx_of_tag, pidx);
+    return hipGetLastError();
+}
+
+hipError_t launch_pidx_update(int32_t n, const int32_t* perm, const int32_t* inv, const int32_t* pidx_old,
+                              int32_t* pidx_new, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pidx_update, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, n, perm, inv, pidx_old,
+                       pidx_new);
+    return hipGetLastError();
 }
 
 hipError_t launch_finalize(const KParams& kp, const BatchView& bv, int32_t n, const int32_t* tmp_key,
