@@ -223,7 +223,9 @@ int dpd_forces(const dpd_params* p, int32_t precision, const dpd_state* sorted,
  * graph can be replayed.  On exit st holds the reordered state and
  * cells / nl describe it (within a call the force pass reads each step's
  * rows from the workspace; nl's CSR index is written for the last step
- * only, and its capacity is checked every step).  d_reductions (nullable, device double[n_steps][8])
+ * only, and its capacity is checked every step; with bonds, the force pass
+ * finds partners through sorted partner indices kept in the workspace and
+ * cells->idx_of_tag is written at the first and the last step).  d_reductions (nullable, device double[n_steps][8])
  * receives per step: P_x, P_y, P_z, sum |v|^2, potential energy, unique
  * pairs, sum |v - v_mean|^2 / (3 (n - 1)) (k_B T), 0.
  * phase_events (nullable): hipEvent_t[6 * n_steps], created by the caller;
