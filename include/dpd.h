@@ -232,7 +232,10 @@ int dpd_forces(const dpd_params* p, int32_t precision, const dpd_state* sorted,
  * for step k, events 6k .. 6k+5 are recorded on `stream` before the first
  * integration phase, after it, after reordering, after the neighbour list,
  * after the forces and after the second phase and statistics, so the
- * caller can time each phase of every step. */
+ * caller can time each phase of every step.  (The second phase of a step
+ * and the first phase of the next run as one pass over the state and are
+ * timed with the next step's first phase; the last step's second phase
+ * runs alone.) */
 int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_steps,
              uint64_t* d_step, double* d_reductions, dpd_cells* cells, dpd_nlist* nl,
              float* x32, float* v32, int32_t* d_status, void* const* phase_events,

@@ -635,9 +635,22 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
         if (!phase_events) return hipSuccess;
         return hipEventRecord(reinterpret_cast<hipEvent_t>(phase_events[6 * (int64_t)k + phase]), s);
     };
+    // Phase 2 of step k and phase 1 of step k + 1 run as one pass over the
+    // state (v after phase 2 is only needed for the statistics and by the
+    // next phase 1); the last step's phase 2 runs alone.
+    DriftArgs drift{st->x, st->tag, st->type, b.x, b.v, bvt, b.tag, b.type};
     for (int32_t k = 0; k < n_steps; ++k) {
         DPD_TRY(mark(k, 0), "event");
-        DPD_TRY(launch_vv1(kp, job.bv, n, st->x, st->v, st->f, st->tag, st->type, b.x, b.v, bvt, b.tag, b.type, s), "vv1");
+        if (k == 0) {
+            DPD_TRY(launch_vv1(kp, job.bv, n, st->x, st->v, st->f, st->tag, st->type, b.x, b.v, bvt, b.tag, b.type, s),
+                    "vv1");
+        } else {
+            DPD_TRY(launch_vv2(kp, n, st->v, st->f, red_part, a.fred_part, force_grid(a), fsum_part, s, &drift),
+                    "vv2 + vv1");
+            DPD_TRY(launch_reduce_final(n, red_part, kRedBlocks, fsum_part, kRedBlocks,
+                                        d_reductions ? d_reductions + 8 * (int64_t)(k - 1) : nullptr, nullptr,
+                                        d_step, d_status, s), "reduce");
+        }
         DPD_TRY(mark(k, 1), "event");
         rc = enqueue_reorder(job, L, ws, &b, bvt, st, vt_sorted, cells, x32, mixed ? v32 : nullptr, s, aos,
                              k > 0 ? inv : nullptr, !bonds || k == 0 || k == n_steps - 1);
@@ -659,10 +672,12 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
         DPD_TRY(mark(k, 3), "event");
         DPD_TRY(launch_forces(kp, job.bv, precision, a, s), "forces");
         DPD_TRY(mark(k, 4), "event");
-        DPD_TRY(launch_vv2(kp, n, st->v, st->f, red_part, a.fred_part, force_grid(a), fsum_part, s), "vv2");
-        DPD_TRY(launch_reduce_final(n, red_part, kRedBlocks, fsum_part, kRedBlocks,
-                                    d_reductions ? d_reductions + 8 * (int64_t)k : nullptr, nullptr, d_step,
-                                    d_status, s), "reduce");
+        if (k == n_steps - 1) {
+            DPD_TRY(launch_vv2(kp, n, st->v, st->f, red_part, a.fred_part, force_grid(a), fsum_part, s), "vv2");
+            DPD_TRY(launch_reduce_final(n, red_part, kRedBlocks, fsum_part, kRedBlocks,
+                                        d_reductions ? d_reductions + 8 * (int64_t)k : nullptr, nullptr, d_step,
+                                        d_status, s), "reduce");
+        }
         DPD_TRY(mark(k, 5), "event");
     }
     return DPD_OK;

@@ -148,10 +148,19 @@ hipError_t launch_sys_reduce(const BatchView& bat, int32_t n, const double* v, c
 hipError_t launch_counter(uint64_t* dst, const uint64_t* src, hipStream_t s);
 // particle -> system map of a batch
 hipError_t launch_sys_map(const BatchView& bat, int32_t n, uint16_t* sys_of, hipStream_t s);
-// phase 2 + momentum / |v|^2 partials; also folds the force partials
-// (fred_part, n_fred blocks) into fsum_part[kRedBlocks][2]
+// the next step's phase 1 fused after phase 2: bx, bv (, bvt) from x and
+// the phase-2 velocity, and btag / btype copied (the outputs of launch_vv1)
+struct DriftArgs {
+    const double* x; const uint32_t* tag; const uint8_t* type;
+    double* bx; double* bv; double* bvt; uint32_t* btag; uint8_t* btype;
+};
+// phase 2 + momentum / |v|^2 partials (f == nullptr: the partials of v as it
+// is); also folds the force partials (fred_part, n_fred blocks) into
+// fsum_part[kRedBlocks][2]; drift (nullable) adds the next step's phase 1,
+// and then v itself is left as it was (the reorder writes v_h into the state)
 hipError_t launch_vv2(const KParams& kp, int32_t n, double* v, const double* f, double* red_part,
-                      const double* fred_part, int32_t n_fred, double* fsum_part, hipStream_t s);
+                      const double* fred_part, int32_t n_fred, double* fsum_part, hipStream_t s,
+                      const DriftArgs* drift = nullptr);
 // sums the partials in a fixed order; red (nullable) gets the 8 step totals;
 // stats (nullable) gets (PE, pairs); increments *d_step when non-null
 hipError_t launch_reduce_final(int32_t n, const double* red_part, int n_red, const double* fred_part,

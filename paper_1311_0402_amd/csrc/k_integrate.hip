@@ -6,7 +6,9 @@
 //                   into [0, L) (add L if negative, then subtract L if >= L);
 //                   v~ = fma(lambda dt, F, v) unless lambda = 1/2 (v~ = v_h).
 // Phase 2 (k_vv2):  v = fma(dt/2, F_new, v_h), plus per-block partial sums
-//                   of momentum and |v|^2 over a fixed grid.
+//                   of momentum and |v|^2 over a fixed grid; optionally
+//                   followed by the next step's phase 1 on the same data
+//                   (then v itself is not stored: the reorder takes v_h).
 // k_reduce_final adds all partials in one fixed order (deterministic) and
 // advances the device step counter.
 #include "dpd_launch.h"
@@ -109,15 +111,32 @@ __global__ __launch_bounds__(kBlock) void k_sys_map(BatchView bat, int32_t n, ui
 __global__ __launch_bounds__(kBlock) void k_vv2(KParams kp, int32_t n, double* __restrict__ v,
                                                 const double* __restrict__ f, double* __restrict__ part,
                                                 const double* __restrict__ fred, int32_t n_fred,
-                                                double* __restrict__ fsum)
+                                                double* __restrict__ fsum, DriftArgs dr)
 {
     __shared__ double s_p[kBlock / kWave], s_q[kBlock / kWave];
     const int k = blockIdx.y;
     const int64_t base = (int64_t)k * n;
+    const double L = kp.L[k];
     double p = 0.0, q = 0.0;
     for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += kRedBlocks * kBlock) {
-        const double vn = __fma_rn(kp.half_dt, f[base + i], v[base + i]);
-        v[base + i] = vn;
+        double vn = v[base + i];
+        if (f) vn = __fma_rn(kp.half_dt, f[base + i], vn);
+        if (dr.bx) {
+            // the next step's phase 1, as k_vv1 computes it from v = vn
+            const double vh = __fma_rn(kp.half_dt, f[base + i], vn);
+            double xn = __fma_rn(kp.dt, vh, dr.x[base + i]);
+            if (xn < 0.0) xn = xn + L;
+            if (xn >= L) xn = xn - L;
+            dr.bx[base + i] = xn;
+            dr.bv[base + i] = vh;
+            if (dr.bvt) dr.bvt[base + i] = __fma_rn(kp.lam_dt, f[base + i], vn);
+            if (k == 0) {
+                dr.btag[i] = dr.tag[i];
+                dr.btype[i] = dr.type[i];
+            }
+        } else if (f) {
+            v[base + i] = vn;
+        }
         p += vn;
         q += vn * vn;
     }
@@ -250,10 +269,13 @@ hipError_t launch_sys_map(const BatchView& bat, int32_t n, uint16_t* sys_of, hip
 }
 
 hipError_t launch_vv2(const KParams& kp, int32_t n, double* v, const double* f, double* red_part,
-                      const double* fred_part, int32_t n_fred, double* fsum_part, hipStream_t s)
+                      const double* fred_part, int32_t n_fred, double* fsum_part, hipStream_t s,
+                      const DriftArgs* drift)
 {
+    DriftArgs dr{};
+    if (drift) dr = *drift;
     hipLaunchKernelGGL(k_vv2, dim3(kRedBlocks, 3), dim3(kBlock), 0, s, kp, n, v, f, red_part, fred_part, n_fred,
-                       fsum_part);
+                       fsum_part, dr);
     return hipGetLastError();
 }
 
