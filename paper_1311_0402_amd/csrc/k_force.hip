@@ -357,7 +357,17 @@ __device__ __forceinline__ Op64 load_op64(const ForceArgs& a, int64_t N, int32_t
     return o;
 }
 
-template <int kWMode>
+// A wave-uniform seed is passed through an empty asm statement before each
+// pair's hash: the compiler then forms the ten round keys with scalar adds
+// at the point of use instead of keeping twenty of them live across the
+// loop (which overflows the scalar registers into lane spills).
+template <bool kUniform>
+__device__ __forceinline__ void opaque_keys(uint32_t& s0, uint32_t& s1)
+{
+    if constexpr (kUniform) __asm__ volatile("" : "+s"(s0), "+s"(s1));
+}
+
+template <int kWMode, bool kUniform>
 __device__ __forceinline__ bool pair64(const KParams& P, const double* A, const double* G, const double* S,
                                        const Op64& oi, const Op64& oj, uint64_t step,
                                        double& px, double& py, double& pz, double& pp)
@@ -377,7 +387,9 @@ __device__ __forceinline__ bool pair64(const KParams& P, const double* A, const 
     const double wd = wr * wr;
     const double ev = ex * (oi.vx - oj.vx) + ey * (oi.vy - oj.vy) + ez * (oi.vz - oj.vz);
     const int tp = oi.type * P.n_types + oj.type;
-    const double xi_ij = gauss64(pair_words(oi.tag, oj.tag, step, P.seed_lo, P.seed_hi));
+    uint32_t s0 = P.seed_lo, s1 = P.seed_hi;
+    opaque_keys<kUniform>(s0, s1);
+    const double xi_ij = gauss64(pair_words(oi.tag, oj.tag, step, s0, s1));
     const double phi = A[tp] * wc - G[tp] * wd * ev + S[tp] * wr * xi_ij;
     px = phi * ex; py = phi * ey; pz = phi * ez;
     pp = 0.25 * A[tp] * P.r_c * wc * wc;
@@ -422,10 +434,10 @@ __global__ __launch_bounds__(kBlock) void k_force_fp64(KParams kp, BatchView bv,
                 bool hit;
                 if constexpr (kB) {
                     const KParams& P = bv.kps[bv.sys_of[i]];
-                    hit = pair64<kWMode>(P, P.a, P.g, P.srdt, load_op64(a, N, i), load_op64(a, N, j), step,
+                    hit = pair64<kWMode, false>(P, P.a, P.g, P.srdt, load_op64(a, N, i), load_op64(a, N, j), step,
                                          px, py, pz, pp);
                 } else {
-                    hit = pair64<kWMode>(kp, s_a, s_g, s_s, load_op64(a, N, i), load_op64(a, N, j), step,
+                    hit = pair64<kWMode, true>(kp, s_a, s_g, s_s, load_op64(a, N, i), load_op64(a, N, j), step,
                                          px, py, pz, pp);
                 }
                 pn = hit ? 1.0 : 0.0;
@@ -505,7 +517,7 @@ struct Stage {
     PairIn in;
 };
 
-template <int kWMode, typename Tab>
+template <int kWMode, bool kUniform, typename Tab>
 __device__ __forceinline__ bool pair32(const KParams& P, const Tab* A, const Tab* G, const Tab* S,
                                        const ForceArgs& a, const PairIn& in, int64_t N, int32_t i, int32_t j,
                                        int32_t code, bool coded, uint64_t step, float& px, float& py, float& pz,
@@ -555,7 +567,9 @@ __device__ __forceinline__ bool pair32(const KParams& P, const Tab* A, const Tab
     const float wd = kWMode == 0 ? wc : wr * wr;     // s = 1/2: w_D = w_R^2 = w_C exactly
     const float ev = ex * (qi.x - qj.x) + ey * (qi.y - qj.y) + ez * (qi.z - qj.z);
     const int tp = (int)__float_as_uint(qi.w) * P.n_types + (int)__float_as_uint(qj.w);
-    const float xi_ij = gauss32(pair_words(__float_as_uint(pi.w), __float_as_uint(pj.w), step, P.seed_lo, P.seed_hi));
+    uint32_t s0 = P.seed_lo, s1 = P.seed_hi;
+    opaque_keys<kUniform>(s0, s1);
+    const float xi_ij = gauss32(pair_words(__float_as_uint(pi.w), __float_as_uint(pj.w), step, s0, s1));
     const float at = (float)A[tp], gt = (float)G[tp], st = (float)S[tp];
     const float phi = at * wc - gt * wd * ev + st * wr * xi_ij;
     px = phi * ex; py = phi * ey; pz = phi * ez;
@@ -628,10 +642,10 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
                 bool hit;
                 if constexpr (kB) {
                     const KParams& P = bv.kps[bv.sys_of[cur.i]];
-                    hit = pair32<kWMode>(P, P.a, P.g, P.srdt, a, cur.in, N, cur.i, cur.j, cur.code, coded, step,
+                    hit = pair32<kWMode, false>(P, P.a, P.g, P.srdt, a, cur.in, N, cur.i, cur.j, cur.code, coded, step,
                                          px, py, pz, pp);
                 } else {
-                    hit = pair32<kWMode>(kp, s_a, s_g, s_s, a, cur.in, N, cur.i, cur.j, cur.code, coded, step,
+                    hit = pair32<kWMode, true>(kp, s_a, s_g, s_s, a, cur.in, N, cur.i, cur.j, cur.code, coded, step,
                                          px, py, pz, pp);
                 }
                 pn = hit ? 1.f : 0.f;
