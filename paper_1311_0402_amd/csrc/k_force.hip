@@ -520,8 +520,8 @@ struct Stage {
 template <int kWMode, bool kUniform, typename Tab>
 __device__ __forceinline__ bool pair32(const KParams& P, const Tab* A, const Tab* G, const Tab* S,
                                        const ForceArgs& a, const PairIn& in, int64_t N, int32_t i, int32_t j,
-                                       int32_t code, bool coded, uint64_t step, float& px, float& py, float& pz,
-                                       float& pp)
+                                       int32_t code, bool coded, bool valid, uint64_t step, float& px,
+                                       float& py, float& pz, float& pp)
 {
     const float4 pi = in.pi, qi = in.qi;
     const float4 pj = in.pj, qj = in.qj;
@@ -543,23 +543,26 @@ __device__ __forceinline__ bool pair32(const KParams& P, const Tab* A, const Tab
     const float dz = (pi.z - pj.z) + oz;
     const float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
     // with no skin the FP64 list already decided the pair set; a skin needs
-    // the FP32 test (documented reading)
-    if (!(P.rl2 == P.rc2 || r2 < (float)P.rc2)) return false;
-    float rr, ex, ey, ez;
-    if (r2 >= kCloseR2) {
-        const float inv_r = __builtin_amdgcn_rsqf(r2);
-        rr = r2 * inv_r;
-        ex = dx * inv_r; ey = dy * inv_r; ez = dz * inv_r;
-    } else {
+    // the FP32 test (documented reading).  Lanes without a pair (past the
+    // batch's end) run the same arithmetic on their own particle and are
+    // zeroed at the end, so the common path has no branches.
+    bool hit = valid && (P.rl2 == P.rc2 || r2 < (float)P.rc2);
+    const float inv_r = __builtin_amdgcn_rsqf(r2);
+    float rr = r2 * inv_r;
+    float ex = dx * inv_r, ey = dy * inv_r, ez = dz * inv_r;
+    if (hit && r2 < kCloseR2) {
         // FP32 offsets cannot resolve the direction of a nearly coincident
         // pair: take its geometry from FP64 positions
         const double ddx = min_image(a.x[i] - a.x[j], P.L[0], P.halfL[0]);
         const double ddy = min_image(a.x[N + i] - a.x[N + j], P.L[1], P.halfL[1]);
         const double ddz = min_image(a.x[2 * N + i] - a.x[2 * N + j], P.L[2], P.halfL[2]);
         const double r64 = sqrt(dist2(ddx, ddy, ddz));
-        if (!(r64 > 0.0)) return false;              // coincident: no direction, no force
-        rr = (float)r64;
-        ex = (float)(ddx / r64); ey = (float)(ddy / r64); ez = (float)(ddz / r64);
+        if (r64 > 0.0) {
+            rr = (float)r64;
+            ex = (float)(ddx / r64); ey = (float)(ddy / r64); ez = (float)(ddz / r64);
+        } else {
+            hit = false;                               // coincident: no direction, no force
+        }
     }
     float wc = 1.0f - rr * (float)P.inv_rc;
     wc = wc > 0.f ? wc : 0.f;
@@ -572,9 +575,11 @@ __device__ __forceinline__ bool pair32(const KParams& P, const Tab* A, const Tab
     const float xi_ij = gauss32(pair_words(__float_as_uint(pi.w), __float_as_uint(pj.w), step, s0, s1));
     const float at = (float)A[tp], gt = (float)G[tp], st = (float)S[tp];
     const float phi = at * wc - gt * wd * ev + st * wr * xi_ij;
-    px = phi * ex; py = phi * ey; pz = phi * ez;
-    pp = 0.25f * (float)P.r_c * at * wc * wc;
-    return true;
+    px = hit ? phi * ex : 0.f;
+    py = hit ? phi * ey : 0.f;
+    pz = hit ? phi * ez : 0.f;
+    pp = hit ? 0.25f * (float)P.r_c * at * wc * wc : 0.f;
+    return hit;
 }
 
 // Mixed form.  Pair terms in FP32, the segmented scan in FP32, each row's
@@ -637,20 +642,18 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
                 }
             }
             const bool valid = eb + lane < jb.e1;
-            float px = 0.f, py = 0.f, pz = 0.f, pp = 0.f, pn = 0.f;
-            if (valid) {
-                bool hit;
-                if constexpr (kB) {
-                    const KParams& P = bv.kps[bv.sys_of[cur.i]];
-                    hit = pair32<kWMode, false>(P, P.a, P.g, P.srdt, a, cur.in, N, cur.i, cur.j, cur.code, coded, step,
-                                         px, py, pz, pp);
-                } else {
-                    hit = pair32<kWMode, true>(kp, s_a, s_g, s_s, a, cur.in, N, cur.i, cur.j, cur.code, coded, step,
-                                         px, py, pz, pp);
-                }
-                pn = hit ? 1.f : 0.f;
-                np_tot += hit ? 1 : 0;
+            float px, py, pz, pp;
+            bool hit;
+            if constexpr (kB) {
+                const KParams& P = bv.kps[bv.sys_of[cur.i]];
+                hit = pair32<kWMode, false>(P, P.a, P.g, P.srdt, a, cur.in, N, cur.i, cur.j, cur.code, coded, valid,
+                                            step, px, py, pz, pp);
+            } else {
+                hit = pair32<kWMode, true>(kp, s_a, s_g, s_s, a, cur.in, N, cur.i, cur.j, cur.code, coded, valid,
+                                           step, px, py, pz, pp);
             }
+            float pn = hit ? 1.f : 0.f;
+            np_tot += hit ? 1 : 0;
             pe_tot += pp;
             // the FP32 prefix values stay within a few hundred, so a row's
             // part, their difference, carries an error of a few ulp of that
