@@ -293,7 +293,7 @@ def cpu_baseline(sysd):
         x, v, f, red, _ = oracle.run(sub, x, v, f, sub.tag, sub.type, k, 1, use_cells=True)
         k += 1
         el = time.perf_counter() - t0
-        if el > 12.0 or k >= 10:
+        if el > 10.0 or k >= 60:
             break
     rate = n_sample * k / el
     return {"value": rate, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
