@@ -139,6 +139,22 @@ const char* dpd_last_error(void);
 /* Library version string. */
 const char* dpd_version(void);
 
+/* How the force pass walks the list (a process-wide host setting).  The
+ * pair terms of Eqs (2)-(5) are antisymmetric, f_ji = -f_ij, so a pair of
+ * two particles inside the same chunk of 64 consecutive sorted particles
+ * (chunks counted from each system's first particle) can be evaluated once,
+ * from the lower particle's row, with its negated force going to the upper
+ * particle; the list rows stay full either way.
+ *   mode 0: every list entry is evaluated (each pair from both rows);
+ *   mode 1: pairs inside a chunk once, in both precisions;
+ *   mode 2 (default): pairs inside a chunk once in the FP64 form, every
+ *           entry in the mixed form (the faster choice for each on MI355X).
+ * The modes differ only in the order of each particle's sums; each is
+ * deterministic.  It applies to launches enqueued afterwards (a batch's
+ * cached step graph is captured again).  Returns the previous mode, or
+ * DPD_EINVAL for another value. */
+int dpd_set_pair_evaluation(int32_t mode);
+
 /* Cells per side for these parameters (rule in the header comment).
  * Returns DPD_EINVAL when the box holds fewer than 3 or more than 1023 cells
  * per side. */

@@ -7,9 +7,10 @@ library was not built.
 """
 from .dpd import (FP64, MIXED, Batch, Cells, NList, Params, State, System, Tiles, alloc_workspace, cell_grid,
                   default_capacity, dpd_bin_reorder, dpd_build_neighbors, dpd_forces,
-                  dpd_forces_backward, dpd_step, dpd_step_backward, workspace_bytes)
+                  dpd_forces_backward, dpd_step, dpd_step_backward, set_pair_evaluation, workspace_bytes)
 from ._abi import DPDError
 
 __all__ = ["FP64", "MIXED", "Batch", "Cells", "NList", "Params", "State", "System", "Tiles", "alloc_workspace",
            "cell_grid", "default_capacity", "dpd_bin_reorder", "dpd_build_neighbors", "dpd_forces",
-           "dpd_forces_backward", "dpd_step", "dpd_step_backward", "workspace_bytes", "DPDError"]
+           "dpd_forces_backward", "dpd_step", "dpd_step_backward", "set_pair_evaluation", "workspace_bytes",
+           "DPDError"]

@@ -366,7 +366,7 @@ BatchTable batch_table(int32_t n_sys, int64_t n_total)
 // Arguments a captured step depends on; a change means capturing again.
 struct GraphKey {
     int32_t precision;
-    int32_t force_grid, nlist_waves, nlist_kind;
+    int32_t force_grid, nlist_waves, nlist_kind, pairs_once;
     dpd_state st;
     dpd_cells cells;
     dpd_nlist nl;
@@ -472,6 +472,12 @@ extern "C" {
 const char* dpd_last_error(void) { return g_error.c_str(); }
 
 const char* dpd_version(void) { return "libdpd 0.1 (gfx950)"; }
+
+int dpd_set_pair_evaluation(int32_t mode)
+{
+    if (mode < 0 || mode > 2) return fail(DPD_EINVAL, "pair evaluation mode must be 0, 1 or 2");
+    return set_pair_mode(mode);
+}
 
 int dpd_cell_grid(const dpd_params* p, int32_t nc[3])
 {
@@ -1021,6 +1027,7 @@ int dpd_batch_step(dpd_batch* b, int32_t precision, dpd_state* st, int32_t n_ste
     key.force_grid = b->job.force_grid;
     key.nlist_waves = b->job.nlist_waves;
     key.nlist_kind = b->job.nlist_kind;
+    key.pairs_once = pair_mode();
     key.st = *st; key.cells = *cells; key.nl = *nl;
     key.d_step = d_step; key.red = d_reductions; key.x32 = x32; key.v32 = v32; key.d_status = d_status;
     key.ws = ws; key.ws_bytes = ws_bytes;

@@ -125,10 +125,19 @@ struct ForceArgs {
     int32_t slab_coded;                           // slab entries carry the stencil offset (see below)
     const double* x64;                            // nullable: (x, y, z, tag bits) per sorted particle
     const double* v64;                            //   and (v~, type bits), double4 each (FP64 pass)
+    int32_t pairs_once = -1;                      // pairs of one 64-row chunk evaluated once
+                                                  //   (1), every entry (0), the pair mode's choice (-1)
 };
 hipError_t launch_forces(const KParams& kp, const BatchView& bv, int precision, const ForceArgs& a,
                          hipStream_t s);
 constexpr int kMaxForceGrid = 8192;
+// library default of ForceArgs::pairs_once for a precision (0 FP64, 1
+// mixed) under the process-wide pair mode (0 every entry, 1 pairs once,
+// 2 pairs once in the FP64 form; 2 unless changed); set returns the previous
+// mode
+bool pairs_once_default(int precision);
+int set_pair_mode(int mode);
+int pair_mode();
 // default persistent grid of the force pass (the workgroups resident at once)
 int force_blocks(int32_t n, int precision);
 // the grid a launch uses: ForceArgs.grid, set by the caller (> 0)

@@ -13,6 +13,8 @@
 // FP32 cell length, FP32 pair arithmetic with hardware rsqrt / sqrt / log /
 // cos, and per-particle compensated (two-sum) FP32 accumulation; the
 // result is stored as FP64.
+#include <atomic>
+
 #include "dpd_launch.h"
 
 namespace dpd {
@@ -157,6 +159,12 @@ __device__ __forceinline__ float dpp_move(float v)
 }
 
 template <int kCtrl, int kRowMask>
+__device__ __forceinline__ int32_t dpp_move(int32_t v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, kCtrl, kRowMask, 0xF, false);
+}
+
+template <int kCtrl, int kRowMask>
 __device__ __forceinline__ double dpp_move(double v)
 {
     const long long b = __double_as_longlong(v);
@@ -215,18 +223,50 @@ __device__ __forceinline__ float row_part(float prefix, int32_t first, int32_t l
     return last < 0 ? 0.f : (first > 0 ? hi - lo : hi);
 }
 
+// a slab entry's particle index and stencil code (-1: not coded)
+__device__ __forceinline__ int32_t entry_j(int32_t raw, bool coded)
+{
+    return coded ? (raw & kSlabJMask) : raw;
+}
+
+__device__ __forceinline__ int32_t entry_code(int32_t raw, bool coded)
+{
+    return coded ? (int32_t)((uint32_t)raw >> kSlabCodeShift) : -1;
+}
+
 struct PairJob {
     int32_t i0, ni;      // first particle of the chunk, particles in it
-    int32_t e0, e1;      // its CSR entries
-    int32_t rstart, rend;  // this lane's row (lane < ni)
+    int32_t e0, e1;      // the entries walked (CSR positions, or with pairs
+                         //   once the kept entries numbered from e0)
+    int32_t rstart, rend;  // this lane's row among them (lane < ni)
+    int32_t ni_once;     // pairs once: ni, or 0 when the chunk walks every entry
 };
+
+// Pairs once: per row of a wave's chunk (LDS, indexed by the wave's first
+// thread + row), the row's first CSR entry and (entries below the chunk) |
+// (mirror entries) << 16.
+struct RowSkip {
+    int32_t* raw;
+    int32_t* skip;
+};
+
+constexpr int kPrePass = 16;    // row entries counted with independent loads
 
 // chunk c: 64 rows from i0 (fewer at the end of the particle range).  In a
 // batch, chunks are numbered system by system from each system's first
 // particle, so every row is grouped, and its sum ordered, exactly as in the
 // system's own single-system run.
-template <bool kB>
-__device__ __forceinline__ PairJob chunk_job(const BatchView& bv, const ForceArgs& a, int32_t c, bool ok, int lane)
+//
+// Pairs once (kSym): a pair of two particles of the same chunk is evaluated
+// only from the lower row; its entry in the upper row (a "mirror") is left
+// out of the walk and the lower row's evaluation adds the negated force to
+// the upper particle through the wave's LDS accumulators.  Rows ascend, so a
+// row's mirrors (chunk particles below it) are one run of entries after
+// those below the chunk; the walk numbers the kept entries of the chunk's
+// rows consecutively from e0 and maps them back to list positions.
+template <bool kB, bool kSym>
+__device__ __forceinline__ PairJob chunk_job(const BatchView& bv, const ForceArgs& a, const int32_t* slab,
+                                             bool coded, const RowSkip& sk, int32_t c, bool ok, int lane)
 {
     PairJob j;
     int32_t end = a.n;
@@ -245,6 +285,47 @@ __device__ __forceinline__ PairJob chunk_job(const BatchView& bv, const ForceArg
     const int32_t prev = __shfl_up(j.rend, 1, kWave);
     j.rstart = lane == 0 ? j.e0 : prev;
     if (lane >= j.ni) { j.rstart = j.e1; j.rend = j.e1; }
+    j.ni_once = 0;
+    if constexpr (kSym) {
+        const int32_t i = j.i0 + lane;
+        const int32_t cnt = j.rend - j.rstart;
+        int32_t below = 0, mir = 0;
+        // count the row's entries below the chunk and below i: the first
+        // kPrePass entries with independent loads, the rest (rows whose
+        // mirrors reach further, rare) a group at a time; rows ascend
+        for (int32_t p = 0; p < cnt; p += kPrePass) {
+            int32_t jj[kPrePass];
+#pragma unroll
+            for (int q = 0; q < kPrePass; ++q) {
+                const int32_t raw = p + q < cnt
+                    ? (slab ? slab[(int64_t)i * a.slab_k + p + q] : a.index[j.rstart + p + q]) : 0x7fffffff;
+                jj[q] = p + q < cnt ? entry_j(raw, coded) : 0x7fffffff;
+            }
+#pragma unroll
+            for (int q = 0; q < kPrePass; ++q) {
+                below += jj[q] < j.i0 ? 1 : 0;
+                mir += (jj[q] >= j.i0 && jj[q] < i) ? 1 : 0;
+            }
+            if (jj[kPrePass - 1] > i) break;
+        }
+        // counts are packed in 16 bits: a chunk with a longer row walks
+        // every entry (the choice covers both rows of each of its pairs)
+        const bool once = !__any(cnt > 0xffff);
+        if (!once) { below = 0; mir = 0; }
+        j.ni_once = once ? j.ni : 0;
+        const int32_t kept = cnt - mir;
+        const int32_t incl = wave_prefix(kept);
+        const int32_t tot = __shfl(incl, kWave - 1, kWave);
+        // the previous chunk's reads of these slots come first (program
+        // order of one wave's LDS operations)
+        __asm__ __volatile__("" ::: "memory");
+        sk.raw[lane] = j.rstart;
+        sk.skip[lane] = below | (mir << 16);
+        __asm__ __volatile__("" ::: "memory");
+        j.rstart = j.e0 + incl - kept;
+        j.rend = j.e0 + incl;
+        j.e1 = j.e0 + tot;
+    }
     return j;
 }
 
@@ -294,22 +375,22 @@ __device__ __forceinline__ RowPos row_pos(const PairJob& jb, int32_t eb, int lan
 }
 
 // Entry e of the chunk's rows: from the builder's fixed-width slab while it
-// holds every row (row i at slab[i * K]), else from the CSR list.
+// holds every row (row i at slab[i * K]), else from the CSR list.  With
+// pairs once, e numbers the kept entries and skips the row's mirror run.
+template <bool kSym>
 __device__ __forceinline__ int32_t entry_at(const int32_t* __restrict__ slab, int32_t slab_k,
-                                            const ForceArgs& a, const PairJob& jb, const RowPos& rp, int32_t e)
+                                            const ForceArgs& a, const PairJob& jb, const RowPos& rp,
+                                            const RowSkip& sk, int32_t e)
 {
-    return slab ? slab[(int64_t)(jb.i0 + rp.r) * slab_k + (e - rp.start)] : a.index[e];
-}
-
-// a slab entry's particle index and stencil code (-1: not coded)
-__device__ __forceinline__ int32_t entry_j(int32_t raw, bool coded)
-{
-    return coded ? (raw & kSlabJMask) : raw;
-}
-
-__device__ __forceinline__ int32_t entry_code(int32_t raw, bool coded)
-{
-    return coded ? (int32_t)((uint32_t)raw >> kSlabCodeShift) : -1;
+    if constexpr (kSym) {
+        int32_t p = e - rp.start;
+        const int32_t skip = sk.skip[rp.r];
+        p += p >= (skip & 0xffff) ? (skip >> 16) : 0;
+        if (slab) return slab[(int64_t)(jb.i0 + rp.r) * slab_k + p];
+        return a.index[sk.raw[rp.r] + p];
+    } else {
+        return slab ? slab[(int64_t)(jb.i0 + rp.r) * slab_k + (e - rp.start)] : a.index[e];
+    }
 }
 
 // the slab when it is usable for this launch, else null
@@ -396,11 +477,16 @@ __device__ __forceinline__ bool pair64(const KParams& P, const double* A, const 
     return true;
 }
 
-template <int kWMode, bool kB>
-__global__ __launch_bounds__(kBlock) void k_force_fp64(KParams kp, BatchView bv, ForceArgs a, int32_t n_chunks)
+template <int kWMode, bool kB, bool kSym>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_force_fp64(KParams kp, BatchView bv, ForceArgs a, int32_t n_chunks)
 {
     __shared__ double s_a[kTab], s_g[kTab], s_s[kTab];
     __shared__ int32_t s_rowm[kBlock];                 // per-wave row marks (row_pos)
+    // pairs once: the mirrored contributions to the wave's 64 rows
+    __shared__ double s_jx[kSym ? kBlock : 1], s_jy[kSym ? kBlock : 1], s_jz[kSym ? kBlock : 1];
+    __shared__ double s_jp[kSym ? kBlock : 1];
+    __shared__ int32_t s_jn[kSym ? kBlock : 1];
+    __shared__ int32_t s_raw[kSym ? kBlock : 1], s_skip[kSym ? kBlock : 1];
     if (!kB) {
         const int nt2 = kp.n_types * kp.n_types;
         for (int t = threadIdx.x; t < nt2; t += kBlock) {
@@ -410,6 +496,13 @@ __global__ __launch_bounds__(kBlock) void k_force_fp64(KParams kp, BatchView bv,
     }
     const int lane = threadIdx.x & (kWave - 1);
     int32_t* const s_mark = s_rowm + (threadIdx.x - lane);
+    const int wbase = threadIdx.x - lane;
+    const int sb = kSym ? wbase : 0;
+    const RowSkip sk{s_raw + sb, s_skip + sb};
+    if constexpr (kSym) {
+        s_jx[threadIdx.x] = 0.0; s_jy[threadIdx.x] = 0.0; s_jz[threadIdx.x] = 0.0;
+        s_jp[threadIdx.x] = 0.0; s_jn[threadIdx.x] = 0;
+    }
     const ChunkWalk cw = chunk_walk(n_chunks);
     const int64_t N = a.n;
     const uint64_t step = (a.d_step ? *a.d_step : 0ull) + a.step_add;
@@ -420,7 +513,7 @@ __global__ __launch_bounds__(kBlock) void k_force_fp64(KParams kp, BatchView bv,
     const int32_t* __restrict__ slab = usable_slab(a);
     const bool coded = slab && a.slab_coded;
     for (int32_t c = cw.first; c < cw.end; c += cw.stride) {
-        const PairJob jb = chunk_job<kB>(bv, a, c, ok, lane);
+        const PairJob jb = chunk_job<kB, kSym>(bv, a, slab, coded, sk, c, ok, lane);
         double fx = 0.0, fy = 0.0, fz = 0.0, pe_row = 0.0, np_row = 0.0;
         for (int32_t eb = jb.e0; eb < jb.e1; eb += kWave) {
             const int32_t e = eb + lane;
@@ -428,7 +521,7 @@ __global__ __launch_bounds__(kBlock) void k_force_fp64(KParams kp, BatchView bv,
             const RowPos rp = row_pos(jb, eb, lane, s_mark);
             const int32_t r = rp.r;
             const int32_t i = jb.i0 + r;
-            const int32_t j = valid ? entry_j(entry_at(slab, a.slab_k, a, jb, rp, e), coded) : i;
+            const int32_t j = valid ? entry_j(entry_at<kSym>(slab, a.slab_k, a, jb, rp, sk, e), coded) : i;
             double px = 0.0, py = 0.0, pz = 0.0, pp = 0.0, pn = 0.0;
             if (valid) {
                 bool hit;
@@ -442,6 +535,19 @@ __global__ __launch_bounds__(kBlock) void k_force_fp64(KParams kp, BatchView bv,
                 }
                 pn = hit ? 1.0 : 0.0;
                 np_tot += pn;
+                if constexpr (kSym) {
+                    // a pair inside the chunk: the upper particle's share
+                    if (hit && (uint32_t)(j - jb.i0) < (uint32_t)jb.ni_once) {
+                        const int q = wbase + (j - jb.i0);
+                        atomicAdd(&s_jx[q], -px);
+                        atomicAdd(&s_jy[q], -py);
+                        atomicAdd(&s_jz[q], -pz);
+                        if (want_pe) atomicAdd(&s_jp[q], pp);
+                        if (want_np) atomicAdd(&s_jn[q], 1);
+                        np_tot += 1.0;
+                        pe_tot += pp;
+                    }
+                }
             }
             pe_tot += pp;
             const int ss = rp.ss;
@@ -458,6 +564,15 @@ __global__ __launch_bounds__(kBlock) void k_force_fp64(KParams kp, BatchView bv,
             const double tp2 = want_pe ? __shfl(pp, sl, kWave) : 0.0;
             const double tn = want_np ? __shfl(pn, sl, kWave) : 0.0;
             if (src >= 0) { fx += tx; fy += ty; fz += tz; pe_row += tp2; np_row += tn; }
+        }
+        if constexpr (kSym) {
+            // LDS operations of one wave take effect in program order
+            __asm__ __volatile__("" ::: "memory");
+            fx += s_jx[threadIdx.x]; fy += s_jy[threadIdx.x]; fz += s_jz[threadIdx.x];
+            pe_row += s_jp[threadIdx.x]; np_row += (double)s_jn[threadIdx.x];
+            s_jx[threadIdx.x] = 0.0; s_jy[threadIdx.x] = 0.0; s_jz[threadIdx.x] = 0.0;
+            s_jp[threadIdx.x] = 0.0; s_jn[threadIdx.x] = 0;
+            __asm__ __volatile__("" ::: "memory");
         }
         if (lane < jb.ni) {
             const int32_t i = jb.i0 + lane;
@@ -584,11 +699,16 @@ __device__ __forceinline__ bool pair32(const KParams& P, const Tab* A, const Tab
 
 // Mixed form.  Pair terms in FP32, the segmented scan in FP32, each row's
 // batches added with a two-sum, the result stored in FP64.
-template <int kWMode, bool kB>
-__global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv, ForceArgs a, int32_t n_chunks)
+template <int kWMode, bool kB, bool kSym>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_force_mixed(KParams kp, BatchView bv, ForceArgs a, int32_t n_chunks)
 {
     __shared__ float s_a[kTab], s_g[kTab], s_s[kTab];
     __shared__ int32_t s_rowm[kBlock];                 // per-wave row marks (row_pos)
+    // pairs once: the mirrored contributions to the wave's 64 rows
+    __shared__ float s_jx[kSym ? kBlock : 1], s_jy[kSym ? kBlock : 1], s_jz[kSym ? kBlock : 1];
+    __shared__ float s_jp[kSym ? kBlock : 1];
+    __shared__ int32_t s_jn[kSym ? kBlock : 1];
+    __shared__ int32_t s_raw[kSym ? kBlock : 1], s_skip[kSym ? kBlock : 1];
     if (!kB) {
         const int nt2 = kp.n_types * kp.n_types;
         for (int t = threadIdx.x; t < nt2; t += kBlock) {
@@ -598,6 +718,13 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
     }
     const int lane = threadIdx.x & (kWave - 1);
     int32_t* const s_mark = s_rowm + (threadIdx.x - lane);
+    const int wbase = threadIdx.x - lane;
+    const int sb = kSym ? wbase : 0;
+    const RowSkip sk{s_raw + sb, s_skip + sb};
+    if constexpr (kSym) {
+        s_jx[threadIdx.x] = 0.f; s_jy[threadIdx.x] = 0.f; s_jz[threadIdx.x] = 0.f;
+        s_jp[threadIdx.x] = 0.f; s_jn[threadIdx.x] = 0;
+    }
     const ChunkWalk cw = chunk_walk(n_chunks);
     const int64_t N = a.n;
     const uint64_t step = (a.d_step ? *a.d_step : 0ull) + a.step_add;
@@ -611,7 +738,7 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
     double pe_tot = 0.0;
     int32_t np_tot = 0;                        // pairs inside r_c seen by this lane
     for (int32_t c = cw.first; c < cw.end; c += cw.stride) {
-        const PairJob jb = chunk_job<kB>(bv, a, c, ok, lane);
+        const PairJob jb = chunk_job<kB, kSym>(bv, a, slab, coded, sk, c, ok, lane);
         float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, pe_row = 0.f, np_row = 0.f;
         // software pipeline: the list entry two batches ahead and the pair
         // operands one batch ahead are requested before a batch is evaluated;
@@ -620,13 +747,13 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
         Stage A, B;
         A.rp = row_pos(jb, jb.e0, lane, s_mark);
         A.i = jb.i0 + A.rp.r;
-        const int32_t raw0 = jb.e0 + lane < jb.e1 ? entry_at(slab, a.slab_k, a, jb, A.rp, jb.e0 + lane) : A.i;
+        const int32_t raw0 = jb.e0 + lane < jb.e1 ? entry_at<kSym>(slab, a.slab_k, a, jb, A.rp, sk, jb.e0 + lane) : A.i;
         A.j = entry_j(raw0, coded);
         A.code = entry_code(raw0, coded);
         A.in = load_pair(a, xw, vw, A.i, A.j, coded);
         RowPos rp_nxt = row_pos(jb, jb.e0 + kWave, lane, s_mark);
         bool has_nxt = jb.e0 + kWave + lane < jb.e1;
-        int32_t raw_nxt = has_nxt ? entry_at(slab, a.slab_k, a, jb, rp_nxt, jb.e0 + kWave + lane) : 0;
+        int32_t raw_nxt = has_nxt ? entry_at<kSym>(slab, a.slab_k, a, jb, rp_nxt, sk, jb.e0 + kWave + lane) : 0;
         auto batch = [&](const Stage& cur, Stage& nxt, int32_t eb) {
             if (eb + kWave < jb.e1) {                   // requests for the next batches
                 nxt.rp = rp_nxt;
@@ -638,7 +765,7 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
                 has_nxt = e2 < jb.e1;
                 if (eb + 2 * kWave < jb.e1) {
                     rp_nxt = row_pos(jb, eb + 2 * kWave, lane, s_mark);
-                    raw_nxt = has_nxt ? entry_at(slab, a.slab_k, a, jb, rp_nxt, e2) : 0;
+                    raw_nxt = has_nxt ? entry_at<kSym>(slab, a.slab_k, a, jb, rp_nxt, sk, e2) : 0;
                 }
             }
             const bool valid = eb + lane < jb.e1;
@@ -655,6 +782,19 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
             float pn = hit ? 1.f : 0.f;
             np_tot += hit ? 1 : 0;
             pe_tot += pp;
+            if constexpr (kSym) {
+                // a pair inside the chunk: the upper particle's share
+                if (hit && (uint32_t)(cur.j - jb.i0) < (uint32_t)jb.ni_once) {
+                    const int q = wbase + (cur.j - jb.i0);
+                    atomicAdd(&s_jx[q], -px);
+                    atomicAdd(&s_jy[q], -py);
+                    atomicAdd(&s_jz[q], -pz);
+                    if (want_pe) atomicAdd(&s_jp[q], pp);
+                    if (want_np) atomicAdd(&s_jn[q], 1);
+                    np_tot += 1;
+                    pe_tot += pp;
+                }
+            }
             // the FP32 prefix values stay within a few hundred, so a row's
             // part, their difference, carries an error of a few ulp of that
             px = wave_prefix(px);
@@ -679,9 +819,23 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
             batch(A, B, eb);
             if (eb + kWave < jb.e1) batch(B, A, eb + kWave);
         }
+        float jx = 0.f, jy = 0.f, jz = 0.f, jp = 0.f;
+        int32_t jn = 0;
+        if constexpr (kSym) {
+            // LDS operations of one wave take effect in program order: the
+            // reads see every atomic above; the slots are cleared for the
+            // next chunk
+            __asm__ __volatile__("" ::: "memory");
+            jx = s_jx[threadIdx.x]; jy = s_jy[threadIdx.x]; jz = s_jz[threadIdx.x];
+            jp = s_jp[threadIdx.x]; jn = s_jn[threadIdx.x];
+            s_jx[threadIdx.x] = 0.f; s_jy[threadIdx.x] = 0.f; s_jz[threadIdx.x] = 0.f;
+            s_jp[threadIdx.x] = 0.f; s_jn[threadIdx.x] = 0;
+            __asm__ __volatile__("" ::: "memory");
+        }
         if (lane < jb.ni) {
             const int32_t i = jb.i0 + lane;
             double fx = (double)sx + (double)cx, fy = (double)sy + (double)cy, fz = (double)sz + (double)cz;
+            if constexpr (kSym) { fx += (double)jx; fy += (double)jy; fz += (double)jz; }
             double pe_b = 0.0;
             if constexpr (kB) {
                 const KParams& P = bv.kps[bv.sys_of[i]];
@@ -695,14 +849,29 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(KParams kp, BatchView bv
             a.f[i] = fx;
             a.f[N + i] = fy;
             a.f[2 * N + i] = fz;
-            if (want_pe) a.pe[i] = (double)pe_row + pe_b;
-            if (want_np) a.npair[i] = (int32_t)np_row;
+            if (want_pe) a.pe[i] = (double)pe_row + (double)jp + pe_b;
+            if (want_np) a.npair[i] = (int32_t)np_row + jn;
         }
     }
     if (a.fred_part) block_partials2(pe_tot, 0.5 * (double)np_tot, a.fred_part);
 }
 
 }  // namespace
+
+namespace {
+std::atomic<int> g_pair_mode{2};
+}  // namespace
+
+// 0: every entry, 1: pairs once, 2: pairs once in the FP64 form only (its
+// pair arithmetic outweighs the shorter walk; the mixed walk over the kept
+// entries is measured slower than the full one)
+bool pairs_once_default(int precision)
+{
+    const int m = g_pair_mode.load(std::memory_order_relaxed);
+    return m == 2 ? precision == 0 : m == 1;
+}
+int set_pair_mode(int mode) { return g_pair_mode.exchange(mode); }
+int pair_mode() { return g_pair_mode.load(std::memory_order_relaxed); }
 
 // Persistent grid: twice the workgroups the chip holds at once (occupancy of
 // the kernel times the compute units, cached per device and precision),
@@ -717,8 +886,8 @@ int force_blocks(int32_t n, int precision)
     const int pr = precision ? 1 : 0;
     if (cache[dev][pr] == 0) {
         int per_cu = 0, cus = 0;
-        const void* f = pr ? reinterpret_cast<const void*>(&k_force_mixed<0, false>)
-                           : reinterpret_cast<const void*>(&k_force_fp64<0, false>);
+        const void* f = pr ? reinterpret_cast<const void*>(&k_force_mixed<0, false, false>)
+                           : reinterpret_cast<const void*>(&k_force_fp64<0, false, true>);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kBlock, 0) != hipSuccess || per_cu < 1)
             per_cu = 4;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
@@ -733,24 +902,24 @@ int force_blocks(int32_t n, int precision)
 
 namespace {
 
-template <bool kB>
+template <bool kB, bool kSym>
 void launch_forces_t(const KParams& kp, const BatchView& bv, int precision, const ForceArgs& a, hipStream_t s)
 {
     const dim3 grid(force_grid(a)), block(kBlock);
     const int32_t chunks = bv.kps ? bv.n_chunks : ceil_div(a.n, kChunk);
     if (precision == 0) {
         switch (kp.wmode) {
-        case 0: hipLaunchKernelGGL((k_force_fp64<0, kB>), grid, block, 0, s, kp, bv, a, chunks); break;
-        case 1: hipLaunchKernelGGL((k_force_fp64<1, kB>), grid, block, 0, s, kp, bv, a, chunks); break;
-        case 2: hipLaunchKernelGGL((k_force_fp64<2, kB>), grid, block, 0, s, kp, bv, a, chunks); break;
-        default: hipLaunchKernelGGL((k_force_fp64<3, kB>), grid, block, 0, s, kp, bv, a, chunks); break;
+        case 0: hipLaunchKernelGGL((k_force_fp64<0, kB, kSym>), grid, block, 0, s, kp, bv, a, chunks); break;
+        case 1: hipLaunchKernelGGL((k_force_fp64<1, kB, kSym>), grid, block, 0, s, kp, bv, a, chunks); break;
+        case 2: hipLaunchKernelGGL((k_force_fp64<2, kB, kSym>), grid, block, 0, s, kp, bv, a, chunks); break;
+        default: hipLaunchKernelGGL((k_force_fp64<3, kB, kSym>), grid, block, 0, s, kp, bv, a, chunks); break;
         }
     } else {
         switch (kp.wmode) {
-        case 0: hipLaunchKernelGGL((k_force_mixed<0, kB>), grid, block, 0, s, kp, bv, a, chunks); break;
-        case 1: hipLaunchKernelGGL((k_force_mixed<1, kB>), grid, block, 0, s, kp, bv, a, chunks); break;
-        case 2: hipLaunchKernelGGL((k_force_mixed<2, kB>), grid, block, 0, s, kp, bv, a, chunks); break;
-        default: hipLaunchKernelGGL((k_force_mixed<3, kB>), grid, block, 0, s, kp, bv, a, chunks); break;
+        case 0: hipLaunchKernelGGL((k_force_mixed<0, kB, kSym>), grid, block, 0, s, kp, bv, a, chunks); break;
+        case 1: hipLaunchKernelGGL((k_force_mixed<1, kB, kSym>), grid, block, 0, s, kp, bv, a, chunks); break;
+        case 2: hipLaunchKernelGGL((k_force_mixed<2, kB, kSym>), grid, block, 0, s, kp, bv, a, chunks); break;
+        default: hipLaunchKernelGGL((k_force_mixed<3, kB, kSym>), grid, block, 0, s, kp, bv, a, chunks); break;
         }
     }
 }
@@ -761,8 +930,14 @@ void launch_forces_t(const KParams& kp, const BatchView& bv, int precision, cons
 hipError_t launch_forces(const KParams& kp, const BatchView& bv, int precision, const ForceArgs& a, hipStream_t s)
 {
     if (a.n <= 0) return hipSuccess;
-    if (bv.kps) launch_forces_t<true>(kp, bv, precision, a, s);
-    else launch_forces_t<false>(kp, bv, precision, a, s);
+    const bool once = a.pairs_once < 0 ? pairs_once_default(precision) : a.pairs_once != 0;
+    if (bv.kps) {
+        if (once) launch_forces_t<true, true>(kp, bv, precision, a, s);
+        else launch_forces_t<true, false>(kp, bv, precision, a, s);
+    } else {
+        if (once) launch_forces_t<false, true>(kp, bv, precision, a, s);
+        else launch_forces_t<false, false>(kp, bv, precision, a, s);
+    }
     return hipGetLastError();
 }
 

@@ -176,6 +176,16 @@ def cell_grid(params: Params):
     return tuple(int(v) for v in nc)
 
 
+def set_pair_evaluation(mode: int) -> int:
+    """0: every list entry is evaluated; 1: a pair inside one 64-particle
+    chunk is evaluated once; 2 (default): once in the FP64 form, every entry
+    in the mixed form.  Returns the previous mode."""
+    rc = lib().dpd_set_pair_evaluation(int(mode))
+    if rc < 0:
+        check(rc, "dpd_set_pair_evaluation")
+    return int(rc)
+
+
 def workspace_bytes(params: Params, n: int, precision: int = FP64) -> int:
     nb = lib().dpd_workspace_bytes(C.byref(params.c()), int(n), int(precision))
     if nb == 0:
