@@ -214,6 +214,23 @@ __device__ __forceinline__ T wave_prefix(T v)
     return v;
 }
 
+// FP32 form: the two row-tail carries as single DPP adds (rows outside the
+// row mask keep their value, the same result as adding the zero a masked
+// move gives them).  The s_nops cover the wait a DPP read of a VGPR needs
+// after a VALU write of it (before each add, and after the last for DPP
+// reads the compiler places next, since it does not see into the asm).
+template <>
+__device__ __forceinline__ float wave_prefix<float>(float v)
+{
+    v += dpp_move<kDppRowShr | 1, 0xF>(v);
+    v += dpp_move<kDppRowShr | 2, 0xF>(v);
+    v += dpp_move<kDppRowShr | 4, 0xF>(v);
+    v += dpp_move<kDppRowShr | 8, 0xF>(v);
+    __asm__("s_nop 1\n\tv_add_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf" : "+v"(v));
+    __asm__("s_nop 1\n\tv_add_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n\ts_nop 1" : "+v"(v));
+    return v;
+}
+
 // this row's part of batch [eb, eb+64) from the prefix values: lanes
 // [first, last] (last = row_end_lane), zero when the row has no entry there
 __device__ __forceinline__ float row_part(float prefix, int32_t first, int32_t last)
@@ -341,15 +358,18 @@ struct RowPos {
     int32_t start;       // first entry of the row (absolute)
 };
 
+// (marks are >= 0: an unsigned maximum, whose identity 0 lets the compiler
+// fold each move into its DPP max)
 __device__ __forceinline__ int32_t wave_max_prefix(int32_t v)
 {
-    v = max(v, __builtin_amdgcn_update_dpp(0, v, kDppRowShr | 1, 0xF, 0xF, false));
-    v = max(v, __builtin_amdgcn_update_dpp(0, v, kDppRowShr | 2, 0xF, 0xF, false));
-    v = max(v, __builtin_amdgcn_update_dpp(0, v, kDppRowShr | 4, 0xF, 0xF, false));
-    v = max(v, __builtin_amdgcn_update_dpp(0, v, kDppRowShr | 8, 0xF, 0xF, false));
-    v = max(v, __builtin_amdgcn_update_dpp(0, v, kDppBcast15, 0xA, 0xF, false));
-    v = max(v, __builtin_amdgcn_update_dpp(0, v, kDppBcast31, 0xC, 0xF, false));
-    return v;
+    uint32_t u = (uint32_t)v;
+    u = max(u, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, kDppRowShr | 1, 0xF, 0xF, false));
+    u = max(u, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, kDppRowShr | 2, 0xF, 0xF, false));
+    u = max(u, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, kDppRowShr | 4, 0xF, 0xF, false));
+    u = max(u, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, kDppRowShr | 8, 0xF, 0xF, false));
+    u = max(u, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, kDppBcast15, 0xA, 0xF, false));
+    u = max(u, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)u, kDppBcast31, 0xC, 0xF, false));
+    return (int32_t)u;
 }
 
 __device__ __forceinline__ RowPos row_pos(const PairJob& jb, int32_t eb, int lane, int32_t* __restrict__ s_mark)

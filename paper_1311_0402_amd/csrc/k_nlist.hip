@@ -638,8 +638,9 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
         const int32_t ci = lx + kTileX * (ly + kTileY * lz);
         const uint32_t* st = s_sten + ci * 27;
         const int32_t nne = s_nne[ci];                   // >= 1: i's own cell is in its stencil
+        // byte offset of this lane's next entry in the tile's slab rows
         const int32_t row0 = (i - g.i_lo) * slab_k * (int32_t)sizeof(int32_t);
-        int32_t row = 0, q = 0;
+        int32_t rb = row0, q = 0;
         uint32_t ent = st[0];
         uint32_t ent_n = st[nne > 1 ? 1 : 0];
         int32_t k = (int32_t)(ent & 0xFFFu), e = (int32_t)((ent >> 12) & 0xFFFu);
@@ -651,9 +652,8 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
             bool hit = j != i && r2 < lo;
             if (j != i && !hit && r2 < hi) hit = exact_hit(P, x, N, i, j);
             if (hit) {
-                __builtin_amdgcn_raw_buffer_store_b32((int32_t)((uint32_t)j | cs), rows,
-                                                      row0 + row * (int32_t)sizeof(int32_t), 0, 0);
-                ++row;
+                __builtin_amdgcn_raw_buffer_store_b32((int32_t)((uint32_t)j | cs), rows, rb, 0, 0);
+                rb += (int32_t)sizeof(int32_t);
             }
         };
         // one step on the candidates at slots k .. k + kStepW - 1 (those below
@@ -687,6 +687,7 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
             if (!step(s0, s1)) break;
             if (!step(s1, s0)) break;
         }
+        const int32_t row = (rb - row0) / (int32_t)sizeof(int32_t);
         offset[i] = row;
         if (row > slab_k) atomicOr(flag, 1);
     }
