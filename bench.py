@@ -26,6 +26,17 @@ if ROOT not in sys.path:
 
 METRIC = "DPD pair-force evals/s & particle-steps/s at 16M, mixed vs FP64, 1 MI355X"
 HBM_PEAK_GBS = 8000.0
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz full-rate 32-bit
+# lane operations (non-packed) per second, in units of 1e12
+VALU_PEAK_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Algorithmic lane slots of one pair evaluation (full-rate operations count
+# 1; 32-bit integer products and transcendentals, a quarter of the rate,
+# count 4).  Philox4x32-10: 20 products (80) + 40 two-input xors; the
+# uniforms 4; Box-Muller log, sqrt, cos (12) + 2 products; geometry (minimum
+# image or cell offset, r^2, 1/r or sqrt and divide, unit vector) 20 / 23;
+# weights 5 / 6; the force (e.v, phi, components) 12; the row sum: three
+# compensated two-sums (18, mixed) or three adds (3, FP64).
+ALU_SLOTS_PER_PAIR = {"mixed": 193, "fp64": 182}
 PHASES = ["vv1", "reorder", "nlist", "forces", "vv2_stats"]
 
 
@@ -95,6 +106,14 @@ def phase_bytes(n, nnz, n_bond_ends, precision, n_cells):
             "vv2_stats": 72.0 * n}
 
 
+def alu_roofline(form, precision):
+    """The force pass against the VALU issue peak: algorithmic lane slots of
+    one evaluation per unique pair (Newton's third law) per second."""
+    ach = form["unique_pairs_per_step"] * ALU_SLOTS_PER_PAIR[precision] / (form["force_ms"] * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TSLOTS, "unit": "Tslot/s",
+            "frac": ach / VALU_PEAK_TSLOTS, "slots_per_unique_pair": ALU_SLOTS_PER_PAIR[precision]}
+
+
 def run_precision(P, torch, sysd, precision, steps, warmup):
     import paper_1311_0402_amd as PK
     prec = PK.FP64 if precision == "fp64" else PK.MIXED
@@ -150,6 +169,7 @@ def run_precision(P, torch, sysd, precision, steps, warmup):
         "kbt_last": float(r[-1, 6]),
         "momentum_max": float(np.abs(r[:, :3]).max()),
     }
+    out["force_alu_frac"] = alu_roofline(out, precision)["frac"]
     del sim
     torch.cuda.empty_cache()
     return out
@@ -358,7 +378,10 @@ def main():
     achieved = fb / (head["force_ms"] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": "forces", "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(head_name),
-                "algorithmic_bytes": fb, "dominant_phase": dom}
+                "algorithmic_bytes": fb, "dominant_phase": dom,
+                # the bound the counters show: VALU issue, against the
+                # algorithmic work of each unique pair evaluated once
+                "alu": alu_roofline(head, head_name)}
     line = {
         "metric": METRIC,
         "value": head["particle_steps_per_s"],
