@@ -101,11 +101,9 @@ int make_kparams(const dpd_params* p, KParams* k)
     k->n_blocks = (int32_t)nblk;
     const int32_t tdim[3] = {kTileX, kTileY, kTileZ};
     int64_t ntile = 1;
-    k->tile_ok = 1;
     for (int d = 0; d < 3; ++d) {
         k->nt[d] = (k->nc[d] + tdim[d] - 1) / tdim[d];
         ntile *= k->nt[d];
-        if (k->nc[d] < tdim[d] + 2) k->tile_ok = 0;
     }
     k->n_tiles = (int32_t)ntile;
     k->rl2 = r_list * r_list;

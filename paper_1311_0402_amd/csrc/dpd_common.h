@@ -41,7 +41,6 @@ struct KParams {
     int32_t small_dim[3]; // n_c < 4: a block's neighbourhood wraps onto itself
     int32_t nt[3];        // tiles of kTileX x kTileY x kTileZ cells per side (list builder)
     int32_t n_tiles;
-    int32_t tile_ok;      // every tile's neighbourhood is kTile + 2 distinct cells per side
     float tile_lo32;      // FP32 pre-test of the tile builder (tile-frame positions):
     float tile_hi32;      //   r^2 < lo is a neighbour, r^2 >= hi is not, else FP64 decides
     float list_lo32;      // FP32 pre-test: r^2 < lo is a neighbour for sure,

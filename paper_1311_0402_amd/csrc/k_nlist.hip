@@ -429,9 +429,13 @@ void launch_nlist_pass(int waves, const KParams& kp, const BatchView& bv, int32_
 // ascending; the walk is one flat loop over all of the particle's
 // candidates, so lanes whose k-th stencil cells differ in size do not wait
 // for each other cell by cell.  Candidates come from LDS, so the walk issues
-// no global loads besides the row stores.  Tiles whose neighbourhood
-// overflows the LDS, and systems too small for distinct tile
-// neighbourhoods, take the lane builder's walk over global memory.
+// no global loads besides the row stores.  In a grid narrower than the
+// union (fewer than 10 x 6 x 6 cells) a cell can appear in the union at two
+// places, as two periodic images, and is staged twice; every tile cell's
+// 27 stencil cells are still distinct cells (3 or more per side), each at
+// the image next to it, so no candidate is seen twice.  Tiles whose
+// neighbourhood overflows the LDS take the lane builder's walk over global
+// memory.
 
 constexpr int kTUX = kTileX + 2, kTUY = kTileY + 2, kTUZ = kTileZ + 2;
 constexpr int kTU = kTUX * kTUY * kTUZ;          // union cells of a tile
@@ -536,7 +540,7 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
     const KParams& P = *g.P;
     const int tid = threadIdx.x;
     // (the tile's slab rows are addressed with 32-bit byte offsets)
-    const bool fits = P.tile_ok != 0 && (int64_t)(g.i_hi - g.i_lo) * slab_k * 4 + 4 * kTilePos < INT32_MAX;
+    const bool fits = (int64_t)(g.i_hi - g.i_lo) * slab_k * 4 + 4 * kTilePos < INT32_MAX;
 
     // ---- union cells: thread u owns union cell u ----
     int32_t cnt = 0;
@@ -693,9 +697,9 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
     }
 }
 
-// Tiles the tile builder left (neighbourhood over the LDS capacity, or a
-// system too small for distinct tile neighbourhoods): rest[0] tiles listed
-// in rest[1..], their particles walked by the lane builder.
+// Tiles the tile builder left (neighbourhood over the LDS capacity):
+// rest[0] tiles listed in rest[1..], their particles walked by the lane
+// builder.
 template <bool kB>
 __global__ __launch_bounds__(kBlock) void k_nlist_tile_rest(KParams kp, BatchView bv, int32_t n,
                                                             const double* __restrict__ x,

@@ -54,9 +54,13 @@ def _systems():
         "amphiphile": di.amphiphile(n=6000, seed=4),
         "poiseuille": di.poiseuille(seed=9, box=(6.0, 12.0, 5.0), rho=4.0),
         "clustered": di.clustered_fluid(),
-        # boxes of at least 10 x 6 x 6 cells go through the tile list builder:
-        # partial tiles at the high faces, the planted cases, and a cluster
-        # whose tile neighbourhood overflows the LDS staging
+        # the tile list builder: partial tiles at the high faces, the planted
+        # cases, and a cluster whose tile neighbourhood overflows the LDS
+        # staging; grids narrower than a tile's 10 x 6 x 6-cell neighbourhood
+        # (cells staged once per periodic image), down to 3 cells a side
+        "tiny_tiles": di.uniform_fluid(110, (3.3, 3.4, 3.6), 21),
+        "thin_tiles": di.uniform_fluid(700, (3.1, 12.5, 5.4), 22),
+        "slab_tiles": di.uniform_fluid(1500, (14.2, 4.3, 7.7), 23),
         "ragged_tiles": di.uniform_fluid(5000, (13.7, 11.1, 9.3), 11),
         "edge_tiles": di.edge_case_fluid(seed=12, box=(12.0, 10.5, 6.5), n=800),
         "clustered_tiles": di.clustered_fluid(seed=13, box=(12.0, 10.5, 7.0), n_cluster=1600, n_rest=800,
