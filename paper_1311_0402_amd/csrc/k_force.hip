@@ -139,7 +139,10 @@ __device__ __forceinline__ ChunkWalk chunk_walk(int32_t n_chunks)
     const int64_t waves = (int64_t)groups * wpg;
     const int64_t w0 = (int64_t)g0 * wpg, wx = (int64_t)gx * wpg;
     ChunkWalk cw;
-    cw.first = (int32_t)(n_chunks * w0 / waves) + k * wpg + (int32_t)(threadIdx.x / kWave);
+    // the wave's index is uniform across its lanes: say so, so that the
+    // chunk, its particle range and (in a batch) its system are scalars
+    cw.first = __builtin_amdgcn_readfirstlane((int32_t)(n_chunks * w0 / waves) + k * wpg +
+                                              (int32_t)(threadIdx.x / kWave));
     cw.end = (int32_t)(n_chunks * (w0 + wx) / waves);
     cw.stride = (int32_t)wx;
     return cw;
@@ -257,7 +260,62 @@ struct PairJob {
                          //   once the kept entries numbered from e0)
     int32_t rstart, rend;  // this lane's row among them (lane < ni)
     int32_t ni_once;     // pairs once: ni, or 0 when the chunk walks every entry
+    int32_t sys;         // the chunk's system in a batch (one per chunk)
 };
+
+// The scalar parameters a pair reads, for a batch chunk's system: loaded
+// once per chunk and made wave-uniform (scalar registers), where the pairs
+// would otherwise read them from the batch table through vector loads.
+struct PairParams {
+    double L[3], halfL[3];
+    double rc2, rl2, inv_rc, s, r_c;
+    float cell_len32[3];
+    int32_t nc[3];
+    int32_t n_types;
+    uint32_t seed_lo, seed_hi;
+};
+
+__device__ __forceinline__ double rfl(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)b);
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ float rfl(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+__device__ __forceinline__ int32_t rfl(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint32_t rfl(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+
+__device__ __forceinline__ PairParams pair_params(const KParams& K)
+{
+    PairParams p;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        p.L[d] = rfl(K.L[d]); p.halfL[d] = rfl(K.halfL[d]);
+        p.cell_len32[d] = rfl(K.cell_len32[d]); p.nc[d] = rfl(K.nc[d]);
+    }
+    p.rc2 = rfl(K.rc2); p.rl2 = rfl(K.rl2); p.inv_rc = rfl(K.inv_rc); p.s = rfl(K.s); p.r_c = rfl(K.r_c);
+    p.n_types = rfl(K.n_types);
+    p.seed_lo = rfl(K.seed_lo); p.seed_hi = rfl(K.seed_hi);
+    return p;
+}
+
+// A batch chunk's type tables (a, gamma, sigma / sqrt(dt)) copied into the
+// wave's LDS rows: the chunk belongs to one system, so its pairs read the
+// tables from LDS and its scalar parameters through a wave-uniform index.
+template <typename Tab>
+__device__ __forceinline__ void stage_tables(const KParams& P, Tab* wa, Tab* wg, Tab* ws, int lane)
+{
+    const int nt2 = P.n_types * P.n_types;
+    // the previous chunk's reads come first (one wave's LDS operations take
+    // effect in program order)
+    __asm__ __volatile__("" ::: "memory");
+    for (int t = lane; t < nt2; t += kWave) {
+        wa[t] = (Tab)P.a[t]; wg[t] = (Tab)P.g[t]; ws[t] = (Tab)P.srdt[t];
+    }
+    __asm__ __volatile__("" ::: "memory");
+}
 
 // Pairs once: per row of a wave's chunk (LDS, indexed by the wave's first
 // thread + row), the row's first CSR entry and (entries below the chunk) |
@@ -287,8 +345,10 @@ __device__ __forceinline__ PairJob chunk_job(const BatchView& bv, const ForceArg
 {
     PairJob j;
     int32_t end = a.n;
+    j.sys = 0;
     if constexpr (kB) {
         const int32_t sy = find_segment(bv.ch_off, bv.n_sys, c);
+        j.sys = __builtin_amdgcn_readfirstlane(sy);
         j.i0 = bv.p_off[sy] + (c - bv.ch_off[sy]) * kChunk;
         end = bv.p_off[sy + 1];
     } else {
@@ -468,8 +528,8 @@ __device__ __forceinline__ void opaque_keys(uint32_t& s0, uint32_t& s1)
     if constexpr (kUniform) __asm__ volatile("" : "+s"(s0), "+s"(s1));
 }
 
-template <int kWMode, bool kUniform>
-__device__ __forceinline__ bool pair64(const KParams& P, const double* A, const double* G, const double* S,
+template <int kWMode, bool kUniform, typename PT>
+__device__ __forceinline__ bool pair64(const PT& P, const double* A, const double* G, const double* S,
                                        const Op64& oi, const Op64& oj, uint64_t step,
                                        double& px, double& py, double& pz, double& pp)
 {
@@ -507,6 +567,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     __shared__ double s_jp[kSym ? kBlock : 1];
     __shared__ int32_t s_jn[kSym ? kBlock : 1];
     __shared__ int32_t s_raw[kSym ? kBlock : 1], s_skip[kSym ? kBlock : 1];
+    // a batch: each wave's own copy of its chunk's tables
+    __shared__ double s_wt[kB ? 3 * (kBlock / kWave) * kTab : 1];
     if (!kB) {
         const int nt2 = kp.n_types * kp.n_types;
         for (int t = threadIdx.x; t < nt2; t += kBlock) {
@@ -514,6 +576,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         }
         __syncthreads();
     }
+    double* const wt = s_wt + (kB ? 3 * kTab * (int)(threadIdx.x / kWave) : 0);
     const int lane = threadIdx.x & (kWave - 1);
     int32_t* const s_mark = s_rowm + (threadIdx.x - lane);
     const int wbase = threadIdx.x - lane;
@@ -534,6 +597,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const bool coded = slab && a.slab_coded;
     for (int32_t c = cw.first; c < cw.end; c += cw.stride) {
         const PairJob jb = chunk_job<kB, kSym>(bv, a, slab, coded, sk, c, ok, lane);
+        PairParams pp_sys;
+        if constexpr (kB) {
+            stage_tables(bv.kps[jb.sys], wt, wt + kTab, wt + 2 * kTab, lane);
+            pp_sys = pair_params(bv.kps[jb.sys]);
+        }
         double fx = 0.0, fy = 0.0, fz = 0.0, pe_row = 0.0, np_row = 0.0;
         for (int32_t eb = jb.e0; eb < jb.e1; eb += kWave) {
             const int32_t e = eb + lane;
@@ -546,9 +614,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             if (valid) {
                 bool hit;
                 if constexpr (kB) {
-                    const KParams& P = bv.kps[bv.sys_of[i]];
-                    hit = pair64<kWMode, false>(P, P.a, P.g, P.srdt, load_op64(a, N, i), load_op64(a, N, j), step,
-                                         px, py, pz, pp);
+                    hit = pair64<kWMode, true>(pp_sys, wt, wt + kTab, wt + 2 * kTab, load_op64(a, N, i),
+                                               load_op64(a, N, j), step, px, py, pz, pp);
                 } else {
                     hit = pair64<kWMode, true>(kp, s_a, s_g, s_s, load_op64(a, N, i), load_op64(a, N, j), step,
                                          px, py, pz, pp);
@@ -597,7 +664,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         if (lane < jb.ni) {
             const int32_t i = jb.i0 + lane;
             double pe_b = 0.0;
-            if constexpr (kB) add_bonds_body(bv.kps[bv.sys_of[i]], a, i, a.x[i], a.x[N + i], a.x[2 * N + i], fx, fy, fz, pe_b);
+            if constexpr (kB) add_bonds_body(bv.kps[jb.sys], a, i, a.x[i], a.x[N + i], a.x[2 * N + i], fx, fy, fz, pe_b);
             else add_bonds_body(kp, a, i, a.x[i], a.x[N + i], a.x[2 * N + i], fx, fy, fz, pe_b);
             pe_tot += pe_b;
             a.f[i] = fx;
@@ -652,8 +719,8 @@ struct Stage {
     PairIn in;
 };
 
-template <int kWMode, bool kUniform, typename Tab>
-__device__ __forceinline__ bool pair32(const KParams& P, const Tab* A, const Tab* G, const Tab* S,
+template <int kWMode, bool kUniform, typename PT, typename Tab>
+__device__ __forceinline__ bool pair32(const PT& P, const Tab* A, const Tab* G, const Tab* S,
                                        const ForceArgs& a, const PairIn& in, int64_t N, int32_t i, int32_t j,
                                        int32_t code, bool coded, bool valid, uint64_t step, float& px,
                                        float& py, float& pz, float& pp)
@@ -729,6 +796,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     __shared__ float s_jp[kSym ? kBlock : 1];
     __shared__ int32_t s_jn[kSym ? kBlock : 1];
     __shared__ int32_t s_raw[kSym ? kBlock : 1], s_skip[kSym ? kBlock : 1];
+    // a batch: each wave's own copy of its chunk's tables
+    __shared__ float s_wt[kB ? 3 * (kBlock / kWave) * kTab : 1];
     if (!kB) {
         const int nt2 = kp.n_types * kp.n_types;
         for (int t = threadIdx.x; t < nt2; t += kBlock) {
@@ -736,6 +805,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         }
         __syncthreads();
     }
+    float* const wt = s_wt + (kB ? 3 * kTab * (int)(threadIdx.x / kWave) : 0);
     const int lane = threadIdx.x & (kWave - 1);
     int32_t* const s_mark = s_rowm + (threadIdx.x - lane);
     const int wbase = threadIdx.x - lane;
@@ -759,6 +829,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     int32_t np_tot = 0;                        // pairs inside r_c seen by this lane
     for (int32_t c = cw.first; c < cw.end; c += cw.stride) {
         const PairJob jb = chunk_job<kB, kSym>(bv, a, slab, coded, sk, c, ok, lane);
+        PairParams pp_sys;
+        if constexpr (kB) {
+            stage_tables(bv.kps[jb.sys], wt, wt + kTab, wt + 2 * kTab, lane);
+            pp_sys = pair_params(bv.kps[jb.sys]);
+        }
         float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, pe_row = 0.f, np_row = 0.f;
         // software pipeline: the list entry two batches ahead and the pair
         // operands one batch ahead are requested before a batch is evaluated;
@@ -792,9 +867,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             float px, py, pz, pp;
             bool hit;
             if constexpr (kB) {
-                const KParams& P = bv.kps[bv.sys_of[cur.i]];
-                hit = pair32<kWMode, false>(P, P.a, P.g, P.srdt, a, cur.in, N, cur.i, cur.j, cur.code, coded, valid,
-                                            step, px, py, pz, pp);
+                hit = pair32<kWMode, true>(pp_sys, wt, wt + kTab, wt + 2 * kTab, a, cur.in, N, cur.i, cur.j,
+                                           cur.code, coded, valid, step, px, py, pz, pp);
             } else {
                 hit = pair32<kWMode, true>(kp, s_a, s_g, s_s, a, cur.in, N, cur.i, cur.j, cur.code, coded, valid,
                                            step, px, py, pz, pp);
@@ -858,7 +932,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             if constexpr (kSym) { fx += (double)jx; fy += (double)jy; fz += (double)jz; }
             double pe_b = 0.0;
             if constexpr (kB) {
-                const KParams& P = bv.kps[bv.sys_of[i]];
+                const KParams& P = bv.kps[jb.sys];
                 if (P.partner || P.body_g != 0.0)
                     add_bonds_body(P, a, i, a.x[i], a.x[N + i], a.x[2 * N + i], fx, fy, fz, pe_b);
             } else {
