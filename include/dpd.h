@@ -392,7 +392,9 @@ int dpd_batch_forces(const dpd_batch* b, int32_t precision, const dpd_state* sor
  * with dpd_step's eight per-step totals for every system.  use_graph != 0:
  * one step is captured into a HIP graph held by the handle (captured again
  * when an argument or the tiles change) and the graph is launched n_steps
- * times on `stream`; the results equal those of use_graph = 0. */
+ * times on `stream`; the results equal those of use_graph = 0.  As in
+ * dpd_step, the steps' forces read each step's rows from the workspace and
+ * nl's CSR index is written once, for the last step. */
 int dpd_batch_step(dpd_batch* b, int32_t precision, dpd_state* st, int32_t n_steps, uint64_t* d_step,
                    double* d_reductions, dpd_cells* cells, dpd_nlist* nl, float* x32, float* v32,
                    int32_t* d_status, int32_t use_graph, void* ws, size_t ws_bytes, void* stream);

@@ -248,6 +248,7 @@ WsLayout ws_layout(const Job& job, int32_t n, bool aos = false)
     // per-particle potential energy and pair counts (per-system statistics of a batch)
     w.pe_part = take(N * sizeof(double));
     w.np_part = take(N * sizeof(int32_t));
+    w.sys_part = take((size_t)(job.bv.kps && job.bv.n_chunks > 0 ? job.bv.n_chunks : 1) * 6 * sizeof(double));
     w.tile_rest = take(((size_t)(job.n_tiles > 0 ? job.n_tiles : 0) + 1) * sizeof(int32_t));
     const bool bonds = job.kp.partner != nullptr;
     w.pidx_a = bonds ? take(2 * N * sizeof(int32_t)) : 0;
@@ -409,6 +410,8 @@ int check_batch_state(const dpd_batch* b, const dpd_state* st, const char* name,
 }
 
 // one batched step: integrate, reorder, list, forces, integrate, statistics
+// One batched step.  The force pass reads the builder's slab rows; the CSR
+// index is written by dpd_batch_step once, after its last step.
 int enqueue_batch_step(const dpd_batch* bt, const WsLayout& L, void* ws, int32_t precision, dpd_state* st,
                        uint64_t* d_step, double* red, dpd_cells* cells, dpd_nlist* nl, float* x32, float* v32,
                        int32_t* d_status, hipStream_t s)
@@ -450,11 +453,12 @@ int enqueue_batch_step(const dpd_batch* bt, const WsLayout& L, void* ws, int32_t
             "vv1");
     if ((rc = enqueue_reorder(job, L, ws, &b, bvt, st, vt_sorted, cells, x32, mixed ? v32 : nullptr, s, aos)))
         return rc;
-    if ((rc = enqueue_nlist(job, L, ws, st, cells, x32, nl, d_status, s))) return rc;
+    if ((rc = enqueue_nlist(job, L, ws, st, cells, x32, nl, d_status, s, false))) return rc;
     DPD_TRY(launch_forces(kp, job.bv, precision, a, s), "forces");
     DPD_TRY(launch_vv2(kp, n, st->v, st->f, carve<double>(ws, L.red_part), nullptr, 0,
                        carve<double>(ws, L.fsum_part), s), "vv2");
-    DPD_TRY(launch_sys_reduce(job.bv, n, st->v, a.pe, a.npair, red, d_step, bt->step_base, d_status, s),
+    DPD_TRY(launch_sys_reduce(job.bv, n, st->v, a.pe, a.npair, carve<double>(ws, L.sys_part), red, d_step,
+                              bt->step_base, d_status, s),
             "system statistics");
     DPD_TRY(launch_counter(d_step, nullptr, s), "step counter");
     return DPD_OK;
@@ -1012,12 +1016,19 @@ int dpd_batch_step(dpd_batch* b, int32_t precision, dpd_state* st, int32_t n_ste
     const hipStream_t s = as_stream(stream);
     if ((rc = enqueue_rank_table(b->job, L, ws, s))) return rc;
     DPD_TRY(launch_counter(b->step_base, d_step, s), "step base");
+    // the steps' forces read the builder's slab; the CSR index of the last
+    // step's list is written once, at the end
+    auto compact = [&]() -> int {
+        DPD_TRY(launch_nlist_compact(n, nl->offset, nl->capacity, carve<int32_t>(ws, L.slab), L.slab_k,
+                                     carve<int32_t>(ws, L.slab_flag), nl->index, s), "neighbour list");
+        return DPD_OK;
+    };
     if (!use_graph) {
         for (int32_t k = 0; k < n_steps; ++k)
             if ((rc = enqueue_batch_step(b, L, ws, precision, st, d_step, d_reductions, cells, nl, x32, v32,
                                          d_status, s)))
                 return rc;
-        return DPD_OK;
+        return compact();
     }
     GraphKey key;
     std::memset(&key, 0, sizeof(key));
@@ -1051,7 +1062,7 @@ int dpd_batch_step(dpd_batch* b, int32_t precision, dpd_state* st, int32_t n_ste
         b->have_key = true;
     }
     for (int32_t k = 0; k < n_steps; ++k) DPD_TRY(hipGraphLaunch(b->exec, s), "graph launch");
-    return DPD_OK;
+    return compact();
 }
 
 }  // extern "C"

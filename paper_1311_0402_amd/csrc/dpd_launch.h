@@ -36,6 +36,7 @@ struct WsLayout {
     size_t pe_part;                    // per-particle potential energy (batch statistics)
     size_t x64, v64;                   // packed FP64 copies for the FP64 step (0 when not laid out)
     size_t np_part;                    // per-particle pair count (batch statistics)
+    size_t sys_part;                   // per-chunk sums of a batch's statistics (6 per chunk)
     size_t tile_rest;                  // tiles left by the tile list builder: count, then tile ids
     size_t pidx_a, pidx_b, inv;        // bonds inside a step loop: partner indices (2 per particle,
                                        // two generations) and the old -> new index map
@@ -101,6 +102,10 @@ hipError_t launch_nlist(const KParams& kp, const BatchView& bv, int32_t n_cells,
 bool nlist_slab_coded(int kind, const uint32_t* cell_xyz, int32_t n_cells, int32_t n);
 // waves per workgroup of the tile builder for n particles in n_cells cells
 int nlist_tile_waves(int32_t n, int32_t n_cells);
+// the CSR index from the builder's slab rows (nothing while the slab flag
+// is set: the direct pass wrote the rows then)
+hipError_t launch_nlist_compact(int32_t n, const int32_t* offset, int64_t capacity, const int32_t* slab,
+                                int32_t slab_k, const int32_t* flag, int32_t* index, hipStream_t s);
 hipError_t launch_nlist_check(int32_t n, const int32_t* offset, int64_t capacity, int32_t* status,
                               hipStream_t s);
 
@@ -147,12 +152,13 @@ inline int force_grid(const ForceArgs& a) { return a.grid; }
 hipError_t launch_vv1(const KParams& kp, const BatchView& bat, int32_t n, const double* x, const double* v,
                       const double* f, const uint32_t* tag, const uint8_t* type, double* bx, double* bv,
                       double* bvt, uint32_t* btag, uint8_t* btype, hipStream_t s);
-// per-system statistics of a batch: one block per system sums v (momentum,
-// |v|^2), the per-particle PE and pair counts over its particle range and
-// writes them to row (*d_step - *base) of red[rows][n_sys][8] (red nullable)
+// per-system statistics of a batch: v (momentum, |v|^2), the per-particle
+// PE and pair counts summed per 64-particle chunk into part[n_chunks][6],
+// then per system over its chunks (fixed orders), written to row
+// (*d_step - *base) of red[rows][n_sys][8] (red nullable)
 hipError_t launch_sys_reduce(const BatchView& bat, int32_t n, const double* v, const double* pe,
-                             const int32_t* npair, double* red, const uint64_t* d_step, const uint64_t* base,
-                             int32_t* status, hipStream_t s);
+                             const int32_t* npair, double* part, double* red, const uint64_t* d_step,
+                             const uint64_t* base, int32_t* status, hipStream_t s);
 // *dst = *src, or *dst += 1 when src is null (device step counters)
 hipError_t launch_counter(uint64_t* dst, const uint64_t* src, hipStream_t s);
 // particle -> system map of a batch

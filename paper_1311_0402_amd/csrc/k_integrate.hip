@@ -54,27 +54,51 @@ __global__ __launch_bounds__(kBlock) void k_vv1(KParams kp, BatchView bat, int32
     else vv1_one(kp, n, i, k, x, v, f, tag, type, bx, bv, bvt, btag, btype);
 }
 
-// one block per system: momentum, |v|^2, potential energy and pairs over the
-// system's particle range (fixed order), then k_B T.  The totals go to row
-// (*d_step - *base) of red (row 0 when base is null).
-__global__ __launch_bounds__(kBlock) void k_sys_reduce(BatchView bat, int32_t n, const double* __restrict__ v,
+// Per-system statistics of a batch, in two fixed-order passes.  First one
+// wave per 64-particle chunk (chunks are numbered system by system) sums
+// momentum, |v|^2, potential energy and pairs over its particles into
+// part[c][0..5]; then one block per system adds its chunks' sums and forms
+// k_B T.  The totals go to row (*d_step - *base) of red (row 0 when base is
+// null).
+__global__ __launch_bounds__(kBlock) void k_sys_chunks(BatchView bat, int32_t n, const double* __restrict__ v,
                                                        const double* __restrict__ pe,
-                                                       const int32_t* __restrict__ npair, double* __restrict__ red,
-                                                       const uint64_t* d_step, const uint64_t* base,
-                                                       int32_t* status)
+                                                       const int32_t* __restrict__ npair,
+                                                       double* __restrict__ part)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int32_t c = blockIdx.x * (kBlock / kWave) + (int32_t)(threadIdx.x / kWave);
+    if (c >= bat.n_chunks) return;
+    const int32_t sy = find_segment(bat.ch_off, bat.n_sys, c);
+    const int32_t i = bat.p_off[sy] + (c - bat.ch_off[sy]) * kWave + lane;
+    const int64_t N = n;
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (i < bat.p_off[sy + 1]) {
+        const double vx = v[i], vy = v[N + i], vz = v[2 * N + i];
+        acc[0] = vx; acc[1] = vy; acc[2] = vz;
+        acc[3] = vx * vx + vy * vy + vz * vz;
+        acc[4] = pe[i];
+        acc[5] = (double)npair[i];
+    }
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) acc[q] += __shfl_down(acc[q], d, kWave);
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) part[6 * (int64_t)c + q] = acc[q];
+}
+
+__global__ __launch_bounds__(kBlock) void k_sys_reduce(BatchView bat, const double* __restrict__ part,
+                                                       double* __restrict__ red, const uint64_t* d_step,
+                                                       const uint64_t* base, int32_t* status)
 {
     __shared__ double s[6][kBlock];
     const int32_t sy = blockIdx.x;
     const int32_t lo = bat.p_off[sy], hi = bat.p_off[sy + 1];
-    const int64_t N = n;
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int32_t i = lo + threadIdx.x; i < hi; i += kBlock) {
-        const double vx = v[i], vy = v[N + i], vz = v[2 * N + i];
-        acc[0] += vx; acc[1] += vy; acc[2] += vz;
-        acc[3] += vx * vx + vy * vy + vz * vz;
-        acc[4] += pe[i];
-        acc[5] += (double)npair[i];
-    }
+    for (int32_t c = bat.ch_off[sy] + threadIdx.x; c < bat.ch_off[sy + 1]; c += kBlock)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) acc[q] += part[6 * (int64_t)c + q];
     for (int q = 0; q < 6; ++q) s[q][threadIdx.x] = acc[q];
     __syncthreads();
     for (int wdt = kBlock / 2; wdt > 0; wdt >>= 1) {
@@ -246,12 +270,14 @@ hipError_t launch_vv1(const KParams& kp, const BatchView& bat, int32_t n, const 
 }
 
 hipError_t launch_sys_reduce(const BatchView& bat, int32_t n, const double* v, const double* pe,
-                             const int32_t* npair, double* red, const uint64_t* d_step, const uint64_t* base,
-                             int32_t* status, hipStream_t s)
+                             const int32_t* npair, double* part, double* red, const uint64_t* d_step,
+                             const uint64_t* base, int32_t* status, hipStream_t s)
 {
-    if (bat.n_sys <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sys_reduce, dim3(bat.n_sys), dim3(kBlock), 0, s, bat, n, v, pe, npair, red, d_step, base,
-                       status);
+    if (bat.n_sys <= 0 || bat.n_chunks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sys_chunks, dim3(ceil_div(bat.n_chunks, kBlock / kWave)), dim3(kBlock), 0, s, bat, n, v,
+                       pe, npair, part);
+    hipLaunchKernelGGL(k_sys_reduce, dim3(bat.n_sys), dim3(kBlock), 0, s, bat, (const double*)part, red, d_step,
+                       base, status);
     return hipGetLastError();
 }
 

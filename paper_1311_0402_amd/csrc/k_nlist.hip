@@ -879,6 +879,15 @@ hipError_t launch_nlist(const KParams& kp, const BatchView& bv, int32_t n_cells,
     return hipGetLastError();
 }
 
+hipError_t launch_nlist_compact(int32_t n, const int32_t* offset, int64_t capacity, const int32_t* slab,
+                                int32_t slab_k, const int32_t* flag, int32_t* index, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_nlist_compact, dim3(ceil_div(ceil_div(n, kWave), kWavesPerBlock)), dim3(kBlock), 0, s, n,
+                       offset, capacity, slab, slab_k, flag, index);
+    return hipGetLastError();
+}
+
 hipError_t launch_nlist_check(int32_t n, const int32_t* offset, int64_t capacity, int32_t* status,
                               hipStream_t s)
 {
