@@ -375,11 +375,13 @@ __global__ __launch_bounds__(kBlock) void k_pidx_update(int32_t n, const int32_t
     const int32_t d = blockIdx.x * kBlock + threadIdx.x;
     if (d >= n) return;
     const int32_t src = perm[d];
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-        const int32_t po = pidx_old[2 * (int64_t)src + b];
-        pidx_new[2 * (int64_t)d + b] = po < 0 ? po : inv[po];
-    }
+    // a particle's two partners as one 8-byte access (the arrays are
+    // 8-byte aligned workspace)
+    const int2 po = reinterpret_cast<const int2*>(pidx_old)[src];
+    int2 pn;
+    pn.x = po.x < 0 ? po.x : inv[po.x];
+    pn.y = po.y < 0 ? po.y : inv[po.y];
+    reinterpret_cast<int2*>(pidx_new)[d] = pn;
 }
 
 }  // namespace
