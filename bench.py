@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import subprocess
 import os
 import sys
 import time
@@ -296,6 +297,41 @@ def run_counters(P, torch, sysd):
     print(json.dumps({"counters_run": True, "copy_bytes": COPY_BYTES}), flush=True)
 
 
+CPU_SAMPLE = r"""
+import json, os, sys, time
+sys.path.insert(0, sys.argv[1])
+import oracle
+import dpd_inputs as di
+n = int(sys.argv[2]); budget = float(sys.argv[3])
+sub = di.amphiphile(n=n, seed=31)
+f, _, _ = oracle.forces(sub, sub.x, sub.v, sub.tag, sub.type, 0, mode="cells")
+x, v, k = sub.x, sub.v, 0
+t0 = time.perf_counter()
+while True:
+    x, v, f, red, _ = oracle.run(sub, x, v, f, sub.tag, sub.type, k, 1, use_cells=True)
+    k += 1
+    el = time.perf_counter() - t0
+    if el > budget or k >= 60:
+        break
+print(json.dumps({"n": n, "steps": k, "seconds": el}))
+"""
+
+
+def cpu_single_thread():
+    """The oracle on one host thread (a child process with OMP_NUM_THREADS=1;
+    the oracle takes its thread count when it first runs), on a 100,000
+    particle box of the same density and chemistry, for about 8 s."""
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", CPU_SAMPLE, ROOT, "100000", "8.0"], env=env,
+                         capture_output=True, text=True, check=True).stdout
+    r = json.loads(out.strip().splitlines()[-1])
+    return {"value": r["n"] * r["steps"] / r["seconds"], "unit": "particle-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{r['steps']} full oracle steps (cell-list neighbour search, FP64) of a "
+                      f"{r['n']}-particle amphiphile box of the same density and chemistry on one thread, "
+                      f"{r['seconds']:.1f} s"}
+
+
 def cpu_baseline(sysd):
     """The CPU oracle on a bounded sample: whole oracle time steps (cell-list
     neighbour search, all host threads) on a slab of the same workload."""
@@ -319,14 +355,15 @@ def cpu_baseline(sysd):
     return {"value": rate, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{k} full oracle steps (cell-list neighbour search, FP64) of a "
                       f"{n_sample}-particle amphiphile box of the same density and chemistry, "
-                      f"{el:.1f} s"}
+                      f"{el:.1f} s",
+            "single_thread": cpu_single_thread()}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=16_000_000)
     ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")

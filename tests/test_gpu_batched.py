@@ -107,6 +107,9 @@ def test_batch_steps_equal_single_systems(precision):
     assert int(b.d_step.item()) == K
     red = red.cpu().numpy()
     bx, bv, bf = (t.cpu().numpy() for t in (b.state.x, b.state.v, b.state.f))
+    # the list the call leaves (written once, after the last step)
+    boff = b.nlist.offset.cpu().numpy().astype(np.int64)
+    bidx = b.nlist.index.cpu().numpy().astype(np.int64)
     for k, s in enumerate(systems):
         sim = _single(s, precision)
         r1 = torch.zeros((K, 8), dtype=torch.float64, device="cuda")
@@ -116,6 +119,10 @@ def test_batch_steps_equal_single_systems(precision):
         np.testing.assert_array_equal(bx[:, sl], x, err_msg=f"system {k}")
         np.testing.assert_array_equal(bv[:, sl], v, err_msg=f"system {k}")
         np.testing.assert_array_equal(bf[:, sl], f, err_msg=f"system {k}")
+        off, idx = sim.host_nlist()
+        o, i = _local_rows(boff, bidx, sl.start, sl.stop)
+        np.testing.assert_array_equal(o, off, err_msg=f"system {k} offsets")
+        np.testing.assert_array_equal(i, idx, err_msg=f"system {k} rows")
         r1 = r1.cpu().numpy()
         # momentum sums cancel: compare them on the scale of sum |v|
         vscale = np.abs(v).sum()
@@ -139,7 +146,9 @@ def test_graph_replay_equals_eager_and_is_resumable():
         red2 = torch.zeros((4, b.n_sys, 8), dtype=torch.float64, device="cuda")
         b.step(4, reductions=red2, use_graph=use_graph)
         torch.cuda.synchronize()
-        runs.append([t.cpu().numpy() for t in (b.state.x, b.state.v, b.state.f, red, red2)])
+        nnz = int(b.nlist.offset[b.n].item())
+        runs.append([t.cpu().numpy() for t in (b.state.x, b.state.v, b.state.f, red, red2, b.nlist.offset,
+                                                 b.nlist.index[:nnz])])
         assert int(b.d_step.item()) == 7
         b.close()
     for u, w in zip(*runs):
