@@ -440,7 +440,13 @@ void launch_nlist_pass(int waves, const KParams& kp, const BatchView& bv, int32_
 constexpr int kTUX = kTileX + 2, kTUY = kTileY + 2, kTUZ = kTileZ + 2;
 constexpr int kTU = kTUX * kTUY * kTUZ;          // union cells of a tile
 constexpr int kTC = kTileX * kTileY * kTileZ;     // cells of a tile
-constexpr int kTilePos = 1536;                    // staged particles per tile
+// staged particles per tile: the workgroup's lanes (sized to the tile
+// population's mean + 1.5 sigma) times 2.9, a little above the union's
+// 360 / 128 cells per tile cell.  At density 3 (7 waves, 1,312 slots) the
+// union's ~1,100 particles fluctuate by ~33, and the LDS use (39 KB) lets
+// four workgroups share a compute unit.
+template <int kW>
+constexpr int tile_pos() { return (kW * kWave * 29 / 10 + 15) / 16 * 16; }
 // union cell whose origin is the tile frame's origin (keeps |positions| small)
 constexpr int kTFX = kTileX / 2 + 1, kTFY = kTileY / 2 + 1, kTFZ = kTileZ / 2 + 1;
 // candidates a lane tests per step of the walk, and their operands
@@ -451,8 +457,8 @@ struct StepW {
 // stencil entry: LDS start | LDS end << 12 | slab code << kSlabCodeShift
 // (the code is 0 when the slab is not coded), so an entry's code bits are
 // the ones a slab entry carries
-static_assert(kTilePos < 4096, "12-bit LDS offsets in the stencil entries");
-static_assert(kTC * 27 * 4 >= kTilePos * 2, "the staging map fits in the stencil table");
+static_assert(tile_pos<16>() < 4096, "12-bit LDS offsets in the stencil entries");
+static_assert(kTC * 27 * 4 >= tile_pos<16>() * 2, "the staging map fits in the stencil table");
 
 // exclusive prefix of v over the workgroup (kW waves); total gets the sum
 template <int kW>
@@ -527,6 +533,7 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
     __shared__ int32_t s_rank[kTU];
     __shared__ int32_t s_gstart[kTU];
     __shared__ int32_t s_lstart[kTU + 1];
+    constexpr int kTilePos = tile_pos<kW>();
     __shared__ float4 s_pos[kTilePos + kStepW - 1];   // spare slots: a step's reads may run past the end
     __shared__ uint32_t s_sten[kTC * 27];      // before the sort: union cell of every staged slot
     __shared__ uint8_t s_nne[kTC];
