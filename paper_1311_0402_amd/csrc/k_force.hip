@@ -303,7 +303,7 @@ __device__ __forceinline__ PairParams pair_params(const KParams& K)
 
 // A batch chunk's type tables (a, gamma, sigma / sqrt(dt)) copied into the
 // wave's LDS rows: the chunk belongs to one system, so its pairs read the
-// tables from LDS and its scalar parameters through a wave-uniform index.
+// tables from LDS (and its scalar parameters from pair_params).
 template <typename Tab>
 __device__ __forceinline__ void stage_tables(const KParams& P, Tab* wa, Tab* wg, Tab* ws, int lane)
 {
