@@ -603,13 +603,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             pp_sys = pair_params(bv.kps[jb.sys]);
         }
         double fx = 0.0, fy = 0.0, fz = 0.0, pe_row = 0.0, np_row = 0.0;
+        // the list entries are requested a batch ahead of their use
+        RowPos rp_nxt = row_pos(jb, jb.e0, lane, s_mark);
+        int32_t raw_nxt = jb.e0 + lane < jb.e1 ? entry_at<kSym>(slab, a.slab_k, a, jb, rp_nxt, sk, jb.e0 + lane) : 0;
         for (int32_t eb = jb.e0; eb < jb.e1; eb += kWave) {
             const int32_t e = eb + lane;
             const bool valid = e < jb.e1;
-            const RowPos rp = row_pos(jb, eb, lane, s_mark);
+            const RowPos rp = rp_nxt;
+            const int32_t raw = raw_nxt;
+            if (eb + kWave < jb.e1) {
+                rp_nxt = row_pos(jb, eb + kWave, lane, s_mark);
+                raw_nxt = e + kWave < jb.e1 ? entry_at<kSym>(slab, a.slab_k, a, jb, rp_nxt, sk, e + kWave) : 0;
+            }
             const int32_t r = rp.r;
             const int32_t i = jb.i0 + r;
-            const int32_t j = valid ? entry_j(entry_at<kSym>(slab, a.slab_k, a, jb, rp, sk, e), coded) : i;
+            const int32_t j = valid ? entry_j(raw, coded) : i;
             double px = 0.0, py = 0.0, pz = 0.0, pp = 0.0, pn = 0.0;
             if (valid) {
                 bool hit;
