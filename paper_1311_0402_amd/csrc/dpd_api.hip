@@ -455,11 +455,11 @@ int enqueue_batch_step(const dpd_batch* bt, const WsLayout& L, void* ws, int32_t
         return rc;
     if ((rc = enqueue_nlist(job, L, ws, st, cells, x32, nl, d_status, s, false))) return rc;
     DPD_TRY(launch_forces(kp, job.bv, precision, a, s), "forces");
-    DPD_TRY(launch_vv2(kp, n, st->v, st->f, carve<double>(ws, L.red_part), nullptr, 0,
-                       carve<double>(ws, L.fsum_part), s), "vv2");
-    DPD_TRY(launch_sys_reduce(job.bv, n, st->v, a.pe, a.npair, carve<double>(ws, L.sys_part), red, d_step,
-                              bt->step_base, d_status, s),
-            "system statistics");
+    // the second half-kick (dt is shared by the systems) and the statistics
+    // in one pass per 64-particle chunk
+    DPD_TRY(launch_sys_reduce(job.bv, n, st->v, st->f, kp.half_dt, a.pe, a.npair, carve<double>(ws, L.sys_part),
+                              red, d_step, bt->step_base, d_status, s),
+            "vv2 + system statistics");
     DPD_TRY(launch_counter(d_step, nullptr, s), "step counter");
     return DPD_OK;
 }

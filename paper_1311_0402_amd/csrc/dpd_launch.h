@@ -155,10 +155,12 @@ hipError_t launch_vv1(const KParams& kp, const BatchView& bat, int32_t n, const 
 // per-system statistics of a batch: v (momentum, |v|^2), the per-particle
 // PE and pair counts summed per 64-particle chunk into part[n_chunks][6],
 // then per system over its chunks (fixed orders), written to row
-// (*d_step - *base) of red[rows][n_sys][8] (red nullable)
-hipError_t launch_sys_reduce(const BatchView& bat, int32_t n, const double* v, const double* pe,
-                             const int32_t* npair, double* part, double* red, const uint64_t* d_step,
-                             const uint64_t* base, int32_t* status, hipStream_t s);
+// (*d_step - *base) of red[rows][n_sys][8] (red nullable).  With f
+// (nullable), the chunk pass first applies the second half-kick
+// v = fma(half_dt, F, v) and stores v.
+hipError_t launch_sys_reduce(const BatchView& bat, int32_t n, double* v, const double* f, double half_dt,
+                             const double* pe, const int32_t* npair, double* part, double* red,
+                             const uint64_t* d_step, const uint64_t* base, int32_t* status, hipStream_t s);
 // *dst = *src, or *dst += 1 when src is null (device step counters)
 hipError_t launch_counter(uint64_t* dst, const uint64_t* src, hipStream_t s);
 // particle -> system map of a batch

@@ -60,7 +60,10 @@ __global__ __launch_bounds__(kBlock) void k_vv1(KParams kp, BatchView bat, int32
 // part[c][0..5]; then one block per system adds its chunks' sums and forms
 // k_B T.  The totals go to row (*d_step - *base) of red (row 0 when base is
 // null).
-__global__ __launch_bounds__(kBlock) void k_sys_chunks(BatchView bat, int32_t n, const double* __restrict__ v,
+// With f given, the chunk pass first applies the step's second half-kick
+// v = fma(dt/2, F, v) (the same arithmetic as k_vv2) and stores v.
+__global__ __launch_bounds__(kBlock) void k_sys_chunks(BatchView bat, int32_t n, double* __restrict__ v,
+                                                       const double* __restrict__ f, double half_dt,
                                                        const double* __restrict__ pe,
                                                        const int32_t* __restrict__ npair,
                                                        double* __restrict__ part)
@@ -73,7 +76,13 @@ __global__ __launch_bounds__(kBlock) void k_sys_chunks(BatchView bat, int32_t n,
     const int64_t N = n;
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (i < bat.p_off[sy + 1]) {
-        const double vx = v[i], vy = v[N + i], vz = v[2 * N + i];
+        double vx = v[i], vy = v[N + i], vz = v[2 * N + i];
+        if (f) {
+            vx = __fma_rn(half_dt, f[i], vx);
+            vy = __fma_rn(half_dt, f[N + i], vy);
+            vz = __fma_rn(half_dt, f[2 * N + i], vz);
+            v[i] = vx; v[N + i] = vy; v[2 * N + i] = vz;
+        }
         acc[0] = vx; acc[1] = vy; acc[2] = vz;
         acc[3] = vx * vx + vy * vy + vz * vz;
         acc[4] = pe[i];
@@ -269,13 +278,13 @@ hipError_t launch_vv1(const KParams& kp, const BatchView& bat, int32_t n, const 
     return hipGetLastError();
 }
 
-hipError_t launch_sys_reduce(const BatchView& bat, int32_t n, const double* v, const double* pe,
-                             const int32_t* npair, double* part, double* red, const uint64_t* d_step,
-                             const uint64_t* base, int32_t* status, hipStream_t s)
+hipError_t launch_sys_reduce(const BatchView& bat, int32_t n, double* v, const double* f, double half_dt,
+                             const double* pe, const int32_t* npair, double* part, double* red,
+                             const uint64_t* d_step, const uint64_t* base, int32_t* status, hipStream_t s)
 {
     if (bat.n_sys <= 0 || bat.n_chunks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_sys_chunks, dim3(ceil_div(bat.n_chunks, kBlock / kWave)), dim3(kBlock), 0, s, bat, n, v,
-                       pe, npair, part);
+                       f, half_dt, pe, npair, part);
     hipLaunchKernelGGL(k_sys_reduce, dim3(bat.n_sys), dim3(kBlock), 0, s, bat, (const double*)part, red, d_step,
                        base, status);
     return hipGetLastError();
