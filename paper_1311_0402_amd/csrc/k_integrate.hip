@@ -17,7 +17,9 @@ namespace dpd {
 
 namespace {
 
-__device__ __forceinline__ void vv1_one(const KParams& kp, int32_t n, int32_t i, int k,
+// kp supplies the step sizes (shared by a batch's systems), L the box edge
+// of particle i's system
+__device__ __forceinline__ void vv1_one(const KParams& kp, double L, int32_t n, int32_t i, int k,
                                         const double* __restrict__ x, const double* __restrict__ v,
                                         const double* __restrict__ f, const uint32_t* __restrict__ tag,
                                         const uint8_t* __restrict__ type, double* __restrict__ bx,
@@ -25,7 +27,6 @@ __device__ __forceinline__ void vv1_one(const KParams& kp, int32_t n, int32_t i,
                                         uint32_t* __restrict__ btag, uint8_t* __restrict__ btype)
 {
     const int64_t a = (int64_t)k * n + i;
-    const double L = kp.L[k];
     const double vh = __fma_rn(kp.half_dt, f[a], v[a]);
     double xn = __fma_rn(kp.dt, vh, x[a]);
     if (xn < 0.0) xn = xn + L;
@@ -50,8 +51,10 @@ __global__ __launch_bounds__(kBlock) void k_vv1(KParams kp, BatchView bat, int32
     const int32_t i = blockIdx.x * kBlock + threadIdx.x;
     const int k = blockIdx.y;                       // component
     if (i >= n) return;
-    if constexpr (kB) vv1_one(bat.kps[bat.sys_of[i]], n, i, k, x, v, f, tag, type, bx, bv, bvt, btag, btype);
-    else vv1_one(kp, n, i, k, x, v, f, tag, type, bx, bv, bvt, btag, btype);
+    if constexpr (kB)
+        vv1_one(kp, bat.kps[bat.sys_of[i]].L[k], n, i, k, x, v, f, tag, type, bx, bv, bvt, btag, btype);
+    else
+        vv1_one(kp, kp.L[k], n, i, k, x, v, f, tag, type, bx, bv, bvt, btag, btype);
 }
 
 // Per-system statistics of a batch, in two fixed-order passes.  First one
