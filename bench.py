@@ -38,7 +38,12 @@ VALU_PEAK_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12
 # weights 5 / 6; the force (e.v, phi, components) 12; the row sum: three
 # compensated two-sums (18, mixed) or three adds (3, FP64).
 ALU_SLOTS_PER_PAIR = {"mixed": 193, "fp64": 182}
-PHASES = ["vv1", "reorder", "nlist", "forces", "vv2_stats"]
+# Phases of a step as dpd_step's events bracket them.  "integrate" is the one
+# pass over the state that ends a step and starts the next (the second
+# half-kick of step k - 1 fused with the half-kick and drift of step k, plus
+# the statistics), timed between events 0 and 1 of step k; the last step's
+# lone second half-kick (events 4 to 5) is added to it.
+PHASES = ["integrate", "reorder", "nlist", "forces"]
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_traffic_amphiphile16M.json")
@@ -86,25 +91,26 @@ def force_bytes(n, nnz, n_bond_ends, precision):
     return n * per + 4 * nnz + 8 * n + 28 * n_bond_ends
 
 
-def phase_bytes(n, nnz, n_bond_ends, precision, n_cells):
+def phase_bytes(n, nnz, n_bond_ends, precision, n_cells, steps):
     """Algorithmic HBM bytes of each phase of one step (each datum once).
 
-    vv1: R x, v, F (72), tag, type (5); W drifted x, v (48), tag, type (5).
+    integrate: R x, v, F (72), tag, type (5); W drifted x, v (48), tag, type
+    (5) every step, plus the last step's lone second half-kick (R v, F 48, W
+    v 24) spread over the steps.
     reorder: bin R x 24, W key, slot, cell 12; scan ~8 per cell; place R key,
     slot, tag 12, W tag, source 8; finalize R source, key 8, cell bounds 8,
     in-cell tags 12, x, v 48, type, cell 5, W x, v 48, tag, type, cell,
     perm, idx_of_tag 17, float4 copies 16 (+16 mixed).
     nlist: R x32 16, cell 4, cell table and ranks 8 per cell; W row count 4,
     4 per entry; scan 8.
-    forces: see force_bytes.  vv2: R v, F 48, W v 24.
+    forces: see force_bytes.
     """
     mixed = precision == "mixed"
     reorder = n * (36 + 20 + 8 + 8 + 12 + 53 + 65 + 16 + (16 if mixed else 0)) + 8 * n_cells
-    return {"vv1": 130.0 * n,
+    return {"integrate": 130.0 * n + 72.0 * n / steps,
             "reorder": float(reorder),
             "nlist": float(n * (16 + 4 + 4 + 8) + 4 * nnz + 8 * n_cells),
-            "forces": float(force_bytes(n, nnz, n_bond_ends, precision)),
-            "vv2_stats": 72.0 * n}
+            "forces": float(force_bytes(n, nnz, n_bond_ends, precision))}
 
 
 def alu_roofline(form, precision):
@@ -141,11 +147,14 @@ def run_precision(P, torch, sysd, precision, steps, warmup):
     wall = time.perf_counter() - wall0
     sim.check_status()
     total_ms = t_start.elapsed_time(t_stop)
-    phase_ms = np.zeros(5)
+    # windows between consecutive events of each step: phase 1 (with the
+    # previous step's phase 2), reorder, list, forces, lone phase 2
+    win = np.zeros(5)
     for k in range(steps):
         for ph in range(5):
-            phase_ms[ph] += evs[6 * k + ph].elapsed_time(evs[6 * k + ph + 1])
-    phase_ms /= steps
+            win[ph] += evs[6 * k + ph].elapsed_time(evs[6 * k + ph + 1])
+    win /= steps
+    phase_ms = np.array([win[0] + win[4], win[1], win[2], win[3]])
     r = red.cpu().numpy()
     nnz = int(sim.nlist.offset[sysd.n].item())
     n_bond_ends = 0 if sysd.partner is None else int((sysd.partner >= 0).sum())
@@ -153,7 +162,11 @@ def run_precision(P, torch, sysd, precision, steps, warmup):
     ms = total_ms / steps
     fb = force_bytes(sysd.n, nnz, n_bond_ends, precision)
     n_cells = int(np.prod(P.cell_grid(P.Params.like(sysd))))
-    pb = phase_bytes(sysd.n, nnz, n_bond_ends, precision, n_cells)
+    pb = phase_bytes(sysd.n, nnz, n_bond_ends, precision, n_cells, steps)
+    hbm_frac = {k: pb[k] / (phase_ms[q] * 1e-3) / 1e9 / HBM_PEAK_GBS for q, k in enumerate(PHASES)}
+    # algorithmic bytes can only exceed what HBM moves if a phase's window
+    # were mis-attributed (or its data served from cache)
+    assert all(v <= 1.0 for v in hbm_frac.values()), hbm_frac
     out = {
         "ms_per_step": ms,
         "wall_s": wall,
@@ -166,14 +179,17 @@ def run_precision(P, torch, sysd, precision, steps, warmup):
         "force_ms": float(phase_ms[3]),
         "force_bytes": fb,
         "phase_gbs": {k: pb[k] / (phase_ms[q] * 1e-3) / 1e9 for q, k in enumerate(PHASES)},
-        "phase_hbm_frac": {k: pb[k] / (phase_ms[q] * 1e-3) / 1e9 / HBM_PEAK_GBS for q, k in enumerate(PHASES)},
+        "phase_hbm_frac": hbm_frac,
         "kbt_last": float(r[-1, 6]),
         "momentum_max": float(np.abs(r[:, :3]).max()),
     }
     out["force_alu_frac"] = alu_roofline(out, precision)["frac"]
+    # the state the timed loop leaves (its forces are checked against the
+    # oracle in the CPU leg): sorted x, v, F, tags, types and the step counter
+    final = sim.host_state() + (sim.step_count,)
     del sim
     torch.cuda.empty_cache()
-    return out
+    return out, final
 
 
 def run_batched(P, torch, steps, warmup, seq_steps, n_sys=256):
@@ -297,66 +313,157 @@ def run_counters(P, torch, sysd):
     print(json.dumps({"counters_run": True, "copy_bytes": COPY_BYTES}), flush=True)
 
 
-CPU_SAMPLE = r"""
-import json, os, sys, time
+# The paper's own speedup, quoted as context beside the oracle comparison.
+PAPER_CONTEXT = {
+    "speedup": "10-30x (best above 30x, at 2 million particles)",
+    "gpu": "one NVIDIA K20X (Kepler, 1.31 TFLOP/s FP64, 250 GB/s)",
+    "cpu": "all 16 cores of one AMD Opteron 6274 at 2.2 GHz (LAMMPS with the authors' DPD pair style)",
+    "workload": "DPD fluids at density 3, 6 and 50, r_c 1 and 1.5, 8,192 to 2 million particles, "
+                "neighbour list every 5 steps",
+    "source": "abstract and Sec. 4.3",
+}
+
+# A child process with its own OpenMP thread count (the oracle fixes its
+# thread count when it first runs): O(N^2) steps of the 3,000-particle fluid
+# and the 64,000-particle channel, and, when the brute-force step is too long
+# to run whole on one thread, the brute-force rows and forces of a bounded
+# sample of rows (the per-step cost is the sample's times N / rows).
+ORACLE_CHILD = r"""
+import json, sys, time
+import numpy as np
 sys.path.insert(0, sys.argv[1])
 import oracle
 import dpd_inputs as di
-n = int(sys.argv[2]); budget = float(sys.argv[3])
-sub = di.amphiphile(n=n, seed=31)
+whole_64k = sys.argv[2] == "1"
+out = {}
+for name, s in (("fluid3000", di.small_fluid(1)), ("channel64000", di.poiseuille(seed=9))):
+    f, _, _ = oracle.forces(s, s.x, s.v, s.tag, s.type, 0, mode="cells")
+    if name == "fluid3000" or whole_64k:
+        reps = 3 if name == "fluid3000" else 1
+        t0 = time.perf_counter()
+        for k in range(reps):
+            oracle.step(s, s.x, s.v, f, s.tag, s.type, 1, use_cells=False)
+        el = (time.perf_counter() - t0) / reps
+        out[name] = {"n": s.n, "s_per_step": el, "steps": reps, "sampled_rows": None}
+    else:
+        q = np.sort(np.random.default_rng(5).choice(s.n, size=1000, replace=False)).astype(np.int32)
+        vh = s.v + 0.5 * s.dt * f
+        t0 = time.perf_counter()
+        nbr = oracle.neighbors(s.x, s.box, s.r_c, query=q)
+        oracle.forces(s, s.x, vh, s.tag, s.type, 1, nbr=nbr, query=q)
+        el = (time.perf_counter() - t0) * s.n / q.size
+        out[name] = {"n": s.n, "s_per_step": el, "steps": 0, "sampled_rows": int(q.size)}
+sub = di.amphiphile(n=100_000, seed=31)
 f, _, _ = oracle.forces(sub, sub.x, sub.v, sub.tag, sub.type, 0, mode="cells")
-x, v, k = sub.x, sub.v, 0
 t0 = time.perf_counter()
-while True:
-    x, v, f, red, _ = oracle.run(sub, x, v, f, sub.tag, sub.type, k, 1, use_cells=True)
-    k += 1
-    el = time.perf_counter() - t0
-    if el > budget or k >= 60:
-        break
-print(json.dumps({"n": n, "steps": k, "seconds": el}))
+oracle.run(sub, sub.x, sub.v, f, sub.tag, sub.type, 0, 5, use_cells=True)
+out["cells_amphiphile100000"] = {"n": sub.n, "s_per_step": (time.perf_counter() - t0) / 5, "steps": 5}
+print(json.dumps(out))
 """
 
 
-def cpu_single_thread():
-    """The oracle on one host thread (a child process with OMP_NUM_THREADS=1;
-    the oracle takes its thread count when it first runs), on a 100,000
-    particle box of the same density and chemistry, for about 8 s."""
-    env = dict(os.environ, OMP_NUM_THREADS="1")
-    out = subprocess.run([sys.executable, "-c", CPU_SAMPLE, ROOT, "100000", "8.0"], env=env,
-                         capture_output=True, text=True, check=True).stdout
-    r = json.loads(out.strip().splitlines()[-1])
-    return {"value": r["n"] * r["steps"] / r["seconds"], "unit": "particle-steps/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{r['steps']} full oracle steps (cell-list neighbour search, FP64) of a "
-                      f"{r['n']}-particle amphiphile box of the same density and chemistry on one thread, "
-                      f"{r['seconds']:.1f} s"}
+def _oracle_child(threads, whole_64k):
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+    res = subprocess.run([sys.executable, "-c", ORACLE_CHILD, ROOT, "1" if whole_64k else "0"], env=env,
+                         capture_output=True, text=True, check=True)
+    return json.loads(res.stdout.strip().splitlines()[-1])
 
 
-def cpu_baseline(sysd):
-    """The CPU oracle on a bounded sample: whole oracle time steps (cell-list
-    neighbour search, all host threads) on a slab of the same workload."""
+def host_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cpus": affinity}
+
+
+def form_errors(oracle, sysd, final, precision, n_sample=1000, seed=12):
+    """Forces of the state a timed loop left, on a seeded sample of rows,
+    against the FP64 oracle at the same state (x, v_h = v - dt/2 F, step):
+    FP64 the largest |dF_i| / S_i (S_i = sum of the magnitudes of the row's
+    terms) and the sample's L2; mixed the sample's L2 relative to |F| and
+    |dF_i| / rms |F| at the 99.99th percentile and at the maximum."""
+    x, v, f, tag, typ, step = final
+    q = np.sort(np.random.default_rng(seed).choice(sysd.n, size=n_sample, replace=False)).astype(np.int32)
+    vh = v - 0.5 * sysd.dt * f
+    nbr = oracle.neighbors(x, sysd.box, sysd.r_c, query=q)
+    f_ref, _, _, scale = oracle.forces(sysd, x, vh, tag, typ, step, nbr=nbr, query=q, with_scale=True)
+    fq = f[:, q]
+    d = np.linalg.norm(fq - f_ref, axis=0)
+    l2 = float(np.linalg.norm(fq - f_ref) / np.linalg.norm(f_ref))
+    rms = float(np.sqrt(np.mean(np.sum(f_ref ** 2, axis=0))))
+    out = {"rows": int(n_sample), "step": int(step), "l2_rel": l2}
+    if precision == "fp64":
+        out["max_rel_to_row_scale"] = float(np.max(d / scale))
+        out["bar"] = "|dF_i| <= 1e-12 S_i"
+    else:
+        out["p9999_rel_to_rms"] = float(np.percentile(d / rms, 99.99))
+        out["max_rel_to_rms"] = float(np.max(d / rms))
+        out["bar"] = "L2 and 99.99th percentile <= 1e-5"
+    return out
+
+
+def cpu_baseline(sysd, finals, gpu_value):
+    """The CPU leg: the FP64 oracle on the host (plain, untuned, cell-list
+    neighbour search for the large systems, FP64 throughout).
+
+    * value: whole oracle time steps of the benchmark workload itself (the
+      16M amphiphile system), 3 steps on all host threads;
+    * O(N^2) per-step times of the 3,000-particle fluid and the
+      64,000-particle channel on all threads and on one thread (the one-thread
+      64,000 step from a 1,000-row sample, scaled by N / rows);
+    * the errors of the GPU forms against the oracle on the states their
+      timed loops left (forms.*.error)."""
     import oracle
-    import dpd_inputs as di
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    # a cubic sub-box of the same density, chemistry and chain fraction
-    n_sample = 1_000_000
-    sub = di.amphiphile(n=n_sample, seed=31)
-    f, _, _ = oracle.forces(sub, sub.x, sub.v, sub.tag, sub.type, 0, mode="cells")
+    errors = {}
+    for prec, final in finals.items():
+        t0 = time.perf_counter()
+        errors[prec] = form_errors(oracle, sysd, final, prec)
+        errors[prec]["oracle_s"] = time.perf_counter() - t0
+        log(f"cpu leg: {prec} error {errors[prec]}")
+    finals.clear()
     t0 = time.perf_counter()
-    k = 0
-    x, v = sub.x, sub.v
-    while True:
-        x, v, f, red, _ = oracle.run(sub, x, v, f, sub.tag, sub.type, k, 1, use_cells=True)
-        k += 1
-        el = time.perf_counter() - t0
-        if el > 10.0 or k >= 60:
-            break
-    rate = n_sample * k / el
+    f0, _, _ = oracle.forces(sysd, sysd.x, sysd.v, sysd.tag, sysd.type, 0, mode="cells")
+    t_force = time.perf_counter() - t0
+    k = 3
+    t0 = time.perf_counter()
+    oracle.run(sysd, sysd.x, sysd.v, f0, sysd.tag, sysd.type, 0, k, use_cells=True)
+    el = time.perf_counter() - t0
+    del f0
+    rate = sysd.n * k / el
+    log(f"cpu leg: 16M oracle {el / k:.2f} s/step on {threads} threads")
+    all_threads = _oracle_child(threads, True)
+    one_thread = _oracle_child(1, False)
+    log(f"cpu leg: O(N^2) all threads {all_threads}; one thread {one_thread}")
+
+    def per_step(d):
+        return {name: {"n": r["n"], "s_per_step": r["s_per_step"],
+                       "particle_steps_per_s": r["n"] / r["s_per_step"],
+                       "measured": "whole steps" if r.get("sampled_rows") is None else
+                       f"{r['sampled_rows']} rows (brute-force rows and forces), scaled by N / rows"}
+                for name, r in d.items()}
+
     return {"value": rate, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{k} full oracle steps (cell-list neighbour search, FP64) of a "
-                      f"{n_sample}-particle amphiphile box of the same density and chemistry, "
-                      f"{el:.1f} s",
-            "single_thread": cpu_single_thread()}
+            "sample": f"{k} whole oracle time steps of the {sysd.n}-particle amphiphile workload itself "
+                      f"(cell-list neighbour search, FP64, all {threads} threads), {el:.1f} s "
+                      f"(+ {t_force:.1f} s for the starting forces)",
+            "host": host_info(),
+            "gpu_over_oracle": gpu_value / rate,
+            "paper_context": PAPER_CONTEXT,
+            "o_n2_all_threads": per_step({k2: v for k2, v in all_threads.items() if k2 != "cells_amphiphile100000"}),
+            "o_n2_one_thread": per_step({k2: v for k2, v in one_thread.items() if k2 != "cells_amphiphile100000"}),
+            "cells_one_thread": per_step({"amphiphile100000": one_thread["cells_amphiphile100000"]}),
+            "errors": errors}
 
 
 def main():
@@ -391,8 +498,9 @@ def main():
         return
 
     results = {}
+    finals = {}
     for prec in (["fp64", "mixed"] if args.precision == "both" else [args.precision]):
-        results[prec] = run_precision(P, torch, sysd, prec, args.steps, args.warmup)
+        results[prec], finals[prec] = run_precision(P, torch, sysd, prec, args.steps, args.warmup)
         log(f"{prec}: {results[prec]['ms_per_step']:.3f} ms/step, phases {results[prec]['phase_ms']}")
 
     if not args.no_batched:
@@ -440,7 +548,10 @@ def main():
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(sysd)
+        cb = cpu_baseline(sysd, finals, line["value"])
+        for prec, err in cb.pop("errors").items():
+            results[prec]["error"] = err
+        line["cpu_baseline"] = cb
     print(json.dumps(line), flush=True)
 
 

@@ -64,6 +64,7 @@ typedef enum dpd_status {
 #define DPD_STATUS_NLIST_OVERFLOW 1   /* neighbour list exceeded its capacity   */
 #define DPD_STATUS_NONFINITE      2   /* a step produced non-finite totals      */
 #define DPD_STATUS_BAD_BOND       4   /* a bond partner tag has no particle     */
+#define DPD_STATUS_HALO_OVERFLOW  8   /* a send list or ghost range did not fit */
 
 typedef enum dpd_precision {
     DPD_FP64 = 0,   /* pair arithmetic in FP64                                 */
@@ -76,7 +77,8 @@ typedef enum dpd_precision {
 typedef struct dpd_params {
     double box[3];          /* periodic box lengths                             */
     double r_c;             /* force cutoff, Eqs (3)-(6)                         */
-    double skin;            /* neighbour radius is r_c + skin (>= 0)            */
+    double skin;            /* neighbour radius is r_c + skin (>= 0); dpd_step
+                               rebuilds lists on displacement when > 0      */
     double dt;              /* time step; F^R scales as dt^-1/2 (Eq (5))        */
     double lambda;          /* velocity-prediction factor of the integrator:
                                F^D sees v + lambda dt F (0.5 = half-step v)     */
@@ -225,12 +227,21 @@ int dpd_forces(const dpd_params* p, int32_t precision, const dpd_state* sorted,
                double* stats, int32_t* d_status,
                void* ws, size_t ws_bytes, void* stream);
 
-/* n_steps time steps of Algorithm 1 on one system, rebuilding the cell list
- * and neighbour list every step:
+/* n_steps time steps of Algorithm 1 on one system:
  *   v_h = v + dt/2 F;  x <- x + dt v_h, wrapped into [0, L);
  *   v~  = v + lambda dt F (= v_h when lambda = 1/2);
  *   reorder, rebuild the list, F <- F(x, v~, step + 1);
  *   v   = v_h + dt/2 F;  step <- step + 1.
+ * With p->skin = 0 the cell and neighbour lists are rebuilt every step.
+ * With p->skin > 0 (Sec. 3.3: lists of radius r_c + skin, rebuilt every few
+ * steps) the first step of the call rebuilds them; each later step rebuilds
+ * (reorders and builds the list) only when some particle has moved more than
+ * skin / 2 from where the last rebuild saw it, which keeps every pair inside
+ * r_c in the list; otherwise the state keeps its order and the step goes
+ * straight to the forces (which skip listed pairs at r >= r_c: the FP64
+ * separation decides in the FP64 form, the FP32 one in the mixed form).  The
+ * decision is taken on the device, step by step.  cells->perm then describes
+ * the last reorder of the call.
  * On entry st->f must hold the forces of the current state (e.g. from
  * dpd_forces at the current step).  x32 (packed FP32 in-cell offsets,
  * float4 [n], see dpd_bin_reorder) is always required; v32 (float4 [n])
@@ -243,7 +254,8 @@ int dpd_forces(const dpd_params* p, int32_t precision, const dpd_state* sorted,
  * finds partners through sorted partner indices kept in the workspace and
  * cells->idx_of_tag is written at the first and the last step).  d_reductions (nullable, device double[n_steps][8])
  * receives per step: P_x, P_y, P_z, sum |v|^2, potential energy, unique
- * pairs, sum |v - v_mean|^2 / (3 (n - 1)) (k_B T), 0.
+ * pairs, sum |v - v_mean|^2 / (3 (n - 1)) (k_B T), and 1 when the step
+ * rebuilt the cell and neighbour lists (always with skin 0), else 0.
  * phase_events (nullable): hipEvent_t[6 * n_steps], created by the caller;
  * for step k, events 6k .. 6k+5 are recorded on `stream` before the first
  * integration phase, after it, after reordering, after the neighbour list,
@@ -289,6 +301,67 @@ int dpd_step_backward(const dpd_params* p, const dpd_state* st, const dpd_cells*
                       const dpd_nlist* nl, uint64_t step, const double* gx_in, const double* gv_in,
                       const double* gf_in, double* gx_out, double* gv_out, double* gf_out,
                       double* grad_a, double* grad_gamma, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Border determination and ghost exchange (Sec. 3.6, Algorithm 6)
+ *
+ * In a spatial decomposition each GPU owns a brick [lo, hi) and sends
+ * copies of the particles within `width` (r_c + skin) of each face to the
+ * neighbour across it, which keeps them as ghosts.  These calls are the one
+ * GPU's part of that exchange: flags, a multi-block scan and a compaction
+ * that produce the six send lists (after each reorder, since indices
+ * change), then packing of the listed particles into ghost records, and
+ * unpacking of received records into the ghost range of a state.  Moving
+ * the records between GPUs (e.g. RCCL send / recv of the record buffers)
+ * is the caller's.  Exchanging the x faces first, then the y faces with the
+ * x ghosts included, then the z faces with all ghosts, reaches the edge and
+ * corner neighbours too.
+ * ------------------------------------------------------------------------- */
+
+/* One ghost record (56 bytes). */
+typedef struct dpd_ghost {
+    double x[3];            /* position plus the face's shift (the periodic
+                               image the receiving neighbour sees)           */
+    double v[3];
+    uint32_t tag;
+    uint32_t type;
+} dpd_ghost;
+
+/* Workspace bytes of dpd_border_lists for n particles (0 for n < 0). */
+size_t dpd_border_workspace_bytes(int32_t n);
+
+/* Send lists of the faces selected by face_mask (bit f, f = 2 d + s for axis
+ * d = 0, 1, 2 and s = 0 the low face, 1 the high face) of the brick
+ * [lo, hi) (host double[3] each, lo < hi), over the st->n particles of st
+ * (ghosts included when the caller appended some): face f lists, in
+ * ascending index order, every particle with x_d < lo_d + width (s = 0) or
+ * x_d >= hi_d - width (s = 1).  send_offset (device int32[7]) receives the
+ * exclusive offsets of the six lists in send_index (unselected faces are
+ * empty; send_offset[6] = the total).  When the total exceeds capacity,
+ * send_index is not written and DPD_STATUS_HALO_OVERFLOW is set in
+ * *d_status (send_offset still holds the sizes).  ws: device memory of
+ * dpd_border_workspace_bytes(st->n) bytes, 256-byte aligned. */
+int dpd_border_lists(const dpd_state* st, const double lo[3], const double hi[3], double width, int32_t face_mask,
+                     int32_t* send_offset, int32_t* send_index, int64_t capacity, int32_t* d_status, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* One record per send-list entry r (send lists and offsets from
+ * dpd_border_lists on the same state): records[r] = (x_j + shift[f],
+ * v_j, tag_j, type_j), j = send_index[r], f its face; shift is host
+ * double[6][3] (e.g. +L_d for the low face and -L_d for the high face of a
+ * brick that spans the periodic box along d).  records: device
+ * dpd_ghost[capacity].  Nothing is written when the lists overflowed; an
+ * entry that is no index of st sets DPD_STATUS_HALO_OVERFLOW. */
+int dpd_border_pack(const dpd_state* st, const int32_t* send_offset, const int32_t* send_index, int64_t capacity,
+                    const double shift[18], dpd_ghost* records, int32_t* d_status, void* stream);
+
+/* Unpacks records[0 .. *d_count) (device count, e.g. send_offset + 6 of the
+ * sender) into dst at indices first .. first + count - 1: x, v, tag, type.
+ * dst->n is the size of dst's arrays (owned particles plus room for
+ * ghosts).  A count above capacity or past dst->n sets
+ * DPD_STATUS_HALO_OVERFLOW and writes nothing. */
+int dpd_border_unpack(const dpd_ghost* records, const int32_t* d_count, int64_t capacity, dpd_state* dst,
+                      int32_t first, int32_t* d_status, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Batched replicas
@@ -388,7 +461,7 @@ int dpd_batch_forces(const dpd_batch* b, int32_t precision, const dpd_state* sor
                      void* stream);
 
 /* dpd_step over all systems (same preconditions per system, shared step
- * counter *d_step).  d_reductions (nullable): device double[n_steps][n_sys][8]
+ * counter *d_step; the lists are rebuilt every step whatever the skin).  d_reductions (nullable): device double[n_steps][n_sys][8]
  * with dpd_step's eight per-step totals for every system.  use_graph != 0:
  * one step is captured into a HIP graph held by the handle (captured again
  * when an argument or the tiles change) and the graph is launched n_steps

@@ -97,6 +97,10 @@ def _declare(L):
     L.orc_run.restype = C.c_int
     L.orc_forces_vjp.argtypes = [P, C.c_int32, P, P, P, P, P, P, C.c_uint64, P, P, P, P, P]
     L.orc_forces_vjp.restype = C.c_int
+    L.orc_border_lists.argtypes = [C.c_int32, P, P, P, C.c_double, C.c_int32, P, P]
+    L.orc_border_lists.restype = C.c_int64
+    L.orc_border_pack.argtypes = [C.c_int32, P, P, P, P, P, P, P, P, P, P, P]
+    L.orc_border_pack.restype = None
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -315,6 +319,74 @@ def run(sys_, x, v, f, tag, typ, step0: int, n_steps: int, *, use_cells: bool = 
         raise RuntimeError("orc_run failed")
     prof_mean = None if prof is None else prof / np.maximum(cnt, 1.0)
     return x, v, f, red, prof_mean
+
+
+# ------------------------------------------------- border exchange ----
+
+def border_lists(x, lo, hi, width: float, face_mask: int = 63):
+    """(off int64[7], idx int32[total]): the ascending send list of every
+    selected face of the brick [lo, hi) (Sec. 3.6, Algorithm 6)."""
+    x = _c(x, np.float64)
+    lo = _c(lo, np.float64)
+    hi = _c(hi, np.float64)
+    n = x.shape[1]
+    off = np.zeros(7, dtype=np.int64)
+    total = lib().orc_border_lists(n, _ptr(x), _ptr(lo), _ptr(hi), float(width), int(face_mask), _ptr(off), None)
+    idx = np.empty(max(total, 1), dtype=np.int32)
+    lib().orc_border_lists(n, _ptr(x), _ptr(lo), _ptr(hi), float(width), int(face_mask), _ptr(off), _ptr(idx))
+    return off, idx[:total]
+
+
+def border_pack(x, v, tag, typ, off, idx, shift):
+    """Ghost records of the send lists: (gx float64[3, total], gv, gtag
+    uint32[total], gtype uint32[total]); shift is float64[6, 3]."""
+    x = _c(x, np.float64)
+    v = _c(v, np.float64)
+    tag = _c(tag, np.uint32)
+    typ = _c(typ, np.uint8)
+    off = _c(off, np.int64)
+    idx = _c(idx, np.int32)
+    shift = _c(shift, np.float64).reshape(6, 3)
+    total = int(off[6])
+    gx = np.empty((3, total)); gv = np.empty((3, total))
+    gtag = np.empty(total, dtype=np.uint32); gtype = np.empty(total, dtype=np.uint32)
+    if total:
+        lib().orc_border_pack(x.shape[1], _ptr(x), _ptr(v), _ptr(tag), _ptr(typ), _ptr(off), _ptr(idx),
+                              _ptr(shift), _ptr(gx), _ptr(gv), _ptr(gtag), _ptr(gtype))
+    return gx, gv, gtag, gtype
+
+
+def periodic_shifts(box):
+    """Face shifts of a brick that spans the periodic box: a particle sent
+    through the low face of axis d reappears at x_d + L_d, through the high
+    face at x_d - L_d."""
+    sh = np.zeros((6, 3))
+    for d in range(3):
+        sh[2 * d, d] = float(box[d])
+        sh[2 * d + 1, d] = -float(box[d])
+    return sh
+
+
+def staged_halo(x, v, tag, typ, box, width: float):
+    """The three-stage exchange on one periodic brick [0, L): the x faces
+    over the owned particles, then the y faces over owned + x ghosts, then
+    the z faces over all of them.  Returns (x, v, tag, type) of the owned
+    particles followed by the ghosts, and the per-stage (off, idx)."""
+    lo = np.zeros(3)
+    hi = np.asarray(box, dtype=np.float64)
+    sh = periodic_shifts(box)
+    X, V = np.array(x, dtype=np.float64), np.array(v, dtype=np.float64)
+    T, Y = np.array(tag, dtype=np.uint32), np.array(typ, dtype=np.uint8)
+    stages = []
+    for d in range(3):
+        off, idx = border_lists(X, lo, hi, width, 3 << (2 * d))
+        gx, gv, gt, gy = border_pack(X, V, T, Y, off, idx, sh)
+        stages.append((off, idx))
+        X = np.concatenate([X, gx], axis=1)
+        V = np.concatenate([V, gv], axis=1)
+        T = np.concatenate([T, gt])
+        Y = np.concatenate([Y, gy.astype(np.uint8)])
+    return X, V, T, Y, stages
 
 
 # ------------------------------------------------- trajectory adjoint ----

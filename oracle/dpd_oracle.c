@@ -693,3 +693,56 @@ int orc_run(const orc_params* p, int32_t n, double* x, double* v, double* f,
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Border determination for a spatial decomposition (Sec. 3.6, Algorithm 6): */
+/* each processor keeps, for every neighbour, a send list of the local      */
+/* particles whose copies that neighbour needs.  For the brick [lo, hi) and */
+/* a halo of `width`, face f = 2 d + s (axis d; s = 0 the low face, s = 1   */
+/* the high face) lists, in ascending index order, the particles with       */
+/* x_d < lo_d + width (s = 0) or x_d >= hi_d - width (s = 1); only faces    */
+/* selected in face_mask get a list.  off[7] receives the exclusive offsets */
+/* of the six lists in idx (idx NULL: offsets only).  Returns the total.    */
+/* ------------------------------------------------------------------------ */
+int64_t orc_border_lists(int32_t n, const double* x, const double lo[3], const double hi[3], double width,
+                         int32_t face_mask, int64_t* off, int32_t* idx)
+{
+    int64_t total = 0;
+    for (int f = 0; f < 6; ++f) {
+        const int d = f / 2, high = f % 2;
+        off[f] = total;
+        if (!((face_mask >> f) & 1)) continue;
+        const double band = high ? hi[d] - width : lo[d] + width;
+        for (int64_t i = 0; i < n; ++i) {
+            const double xd = x[d * (int64_t)n + i];
+            const int sent = high ? (xd >= band) : (xd < band);
+            if (sent) {
+                if (idx) idx[total] = (int32_t)i;
+                ++total;
+            }
+        }
+    }
+    off[6] = total;
+    return total;
+}
+
+/* The ghost record of each send-list entry: the particle's position moved  */
+/* by its face's shift (the image the receiving neighbour sees; shift is    */
+/* double[6][3]), its velocity, tag and type.  Records are written as        */
+/* separate arrays: gx, gv double[3][total] (component-major), gtag, gtype.  */
+void orc_border_pack(int32_t n, const double* x, const double* v, const uint32_t* tag, const uint8_t* type,
+                     const int64_t* off, const int32_t* idx, const double* shift,
+                     double* gx, double* gv, uint32_t* gtag, uint32_t* gtype)
+{
+    const int64_t total = off[6];
+    for (int f = 0; f < 6; ++f)
+        for (int64_t r = off[f]; r < off[f + 1]; ++r) {
+            const int64_t j = idx[r];
+            for (int d = 0; d < 3; ++d) {
+                gx[d * total + r] = x[d * (int64_t)n + j] + shift[3 * f + d];
+                gv[d * total + r] = v[d * (int64_t)n + j];
+            }
+            gtag[r] = tag[j];
+            gtype[r] = type[j];
+        }
+}

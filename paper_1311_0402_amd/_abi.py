@@ -21,6 +21,7 @@ DPD_EUNSUPPORTED = -4
 STATUS_NLIST_OVERFLOW = 1
 STATUS_NONFINITE = 2
 STATUS_BAD_BOND = 4
+STATUS_HALO_OVERFLOW = 8
 
 FP64 = 0
 MIXED = 1
@@ -77,6 +78,18 @@ class dpd_nlist(C.Structure):
     ]
 
 
+class dpd_ghost(C.Structure):
+    _fields_ = [
+        ("x", C.c_double * 3),
+        ("v", C.c_double * 3),
+        ("tag", C.c_uint32),
+        ("type", C.c_uint32),
+    ]
+
+
+GHOST_BYTES = C.sizeof(dpd_ghost)
+
+
 class dpd_tiles(C.Structure):
     _fields_ = [
         ("force_grid", C.c_int32),
@@ -106,6 +119,10 @@ SIGNATURES = {
     "dpd_step": (C.c_int, [PP, C.c_int32, PS, C.c_int32, P, P, PC, PN, P, P, P, P, P, C.c_size_t, P]),
     "dpd_forces_backward": (C.c_int, [PP, PS, PC, PN, C.c_uint64, P, P, P, P, P, C.c_int32, P, C.c_size_t, P]),
     "dpd_step_backward": (C.c_int, [PP, PS, PC, PN, C.c_uint64, P, P, P, P, P, P, P, P, P, C.c_size_t, P]),
+    "dpd_border_workspace_bytes": (C.c_size_t, [C.c_int32]),
+    "dpd_border_lists": (C.c_int, [PS, P, P, C.c_double, C.c_int32, P, P, C.c_int64, P, P, C.c_size_t, P]),
+    "dpd_border_pack": (C.c_int, [PS, P, P, C.c_int64, P, P, P, P]),
+    "dpd_border_unpack": (C.c_int, [P, P, C.c_int64, PS, C.c_int32, P, P]),
     "dpd_batch_table_bytes": (C.c_size_t, [C.c_int32, C.c_int64]),
     "dpd_batch_create": (C.c_int, [PP, C.c_int32, P, P, C.c_size_t, P, C.POINTER(C.c_void_p)]),
     "dpd_batch_destroy": (None, [P]),

@@ -195,6 +195,7 @@ struct Job {
     int32_t force_grid;  // persistent force workgroups (0 = default)
     int32_t nlist_waves; // waves per list-build workgroup
     int32_t nlist_kind;  // 0: tile builder, 1: wave per 2x2x2 cell block, 2: lane per particle
+    Gate gate = nullptr; // skin steps: rebuild only while *gate != 0
 };
 
 Job single_job(const KParams& kp, int32_t n)
@@ -254,6 +255,9 @@ WsLayout ws_layout(const Job& job, int32_t n, bool aos = false)
     w.pidx_a = bonds ? take(2 * N * sizeof(int32_t)) : 0;
     w.pidx_b = bonds ? take(2 * N * sizeof(int32_t)) : 0;
     w.inv = bonds ? take(N * sizeof(int32_t)) : 0;
+    const bool skin = job.kp.rl2 != job.kp.rc2;
+    w.xref = skin ? take(3 * N * sizeof(double)) : 0;
+    w.gate = skin ? take(2 * sizeof(int32_t)) : 0;
     w.x64 = aos ? take(N * 4 * sizeof(double)) : 0;
     w.v64 = aos ? take(N * 4 * sizeof(double)) : 0;
     w.total = o;
@@ -279,10 +283,11 @@ int enqueue_reorder(const Job& job, const WsLayout& L, void* ws, const dpd_state
     int32_t* tmp_key = carve<int32_t>(ws, L.tmp_key);
     int32_t* part = carve<int32_t>(ws, L.scan_part);
     const int32_t* rank_tab = carve<int32_t>(ws, L.rank_tab);
-    DPD_TRY(launch_fill_i32(cells->cell_start, (int64_t)job.n_cells + 1, 0, s), "fill cell counts");
-    DPD_TRY(launch_bin(job.kp, job.bv, n, in->x, rank_tab, key, slot, cxyz, cells->cell_start, s), "bin");
-    DPD_TRY(launch_scan(cells->cell_start, (int64_t)job.n_cells + 1, part, s), "scan cells");
-    DPD_TRY(launch_place(n, key, slot, cells->cell_start, in->tag, tmp_tag, tmp_src, tmp_key, s), "place");
+    const Gate gt = job.gate;
+    DPD_TRY(launch_fill_i32(cells->cell_start, (int64_t)job.n_cells + 1, 0, s, gt), "fill cell counts");
+    DPD_TRY(launch_bin(job.kp, job.bv, n, in->x, rank_tab, key, slot, cxyz, cells->cell_start, s, gt), "bin");
+    DPD_TRY(launch_scan(cells->cell_start, (int64_t)job.n_cells + 1, part, s, gt), "scan cells");
+    DPD_TRY(launch_place(n, key, slot, cells->cell_start, in->tag, tmp_tag, tmp_src, tmp_key, s, gt), "place");
     GatherArgs g;
     g.x_in = in->x; g.v_in = in->v; g.vt_in = vt_in; g.type_in = in->type; g.cxyz_in = cxyz;
     g.x_out = out->x; g.v_out = out->v; g.vt_out = vt_out; g.tag_out = out->tag; g.type_out = out->type;
@@ -291,7 +296,8 @@ int enqueue_reorder(const Job& job, const WsLayout& L, void* ws, const dpd_state
     g.x32 = x32; g.v32 = v32;
     g.x64 = aos ? carve<double>(ws, L.x64) : nullptr;
     g.v64 = aos ? carve<double>(ws, L.v64) : nullptr;
-    DPD_TRY(launch_finalize(job.kp, job.bv, n, tmp_key, cells->cell_start, tmp_tag, tmp_src, g, s), "finalize");
+    g.xref = job.gate ? carve<double>(ws, L.xref) : nullptr;
+    DPD_TRY(launch_finalize(job.kp, job.bv, n, tmp_key, cells->cell_start, tmp_tag, tmp_src, g, s, gt), "finalize");
     return DPD_OK;
 }
 
@@ -303,7 +309,7 @@ int enqueue_nlist(const Job& job, const WsLayout& L, void* ws, const dpd_state* 
                          cells->cell_start, carve<int32_t>(ws, L.rank_tab), nl->offset, nl->index, nl->capacity,
                          carve<int32_t>(ws, L.slab), L.slab_k, carve<int32_t>(ws, L.slab_flag),
                          carve<int32_t>(ws, L.tile_rest), d_status,
-                         carve<int32_t>(ws, L.scan_part), job.nlist_waves, job.nlist_kind, compact, s),
+                         carve<int32_t>(ws, L.scan_part), job.nlist_waves, job.nlist_kind, compact, s, job.gate),
             "neighbour list");
     return DPD_OK;
 }
@@ -464,6 +470,54 @@ int enqueue_batch_step(const dpd_batch* bt, const WsLayout& L, void* ws, int32_t
     return DPD_OK;
 }
 
+// Argument checks and kernel arguments shared by the force entry points
+// (everything except where the per-workgroup partials go).
+int prepare_forces(const dpd_params* p, int32_t precision, const dpd_state* sorted, const dpd_cells* cells,
+                   const float* x32, const float* v32, const dpd_nlist* nl, uint64_t step, double* f_out,
+                   double* pe_out, int32_t* d_status, KParams* kp_out, ForceArgs* out)
+{
+    KParams& kp = *kp_out;
+    int rc = make_kparams(p, &kp);
+    if (rc) return rc;
+    if (precision != DPD_FP64 && precision != DPD_MIXED) return fail(DPD_EINVAL, "unknown precision %d", precision);
+    if ((rc = check_state(sorted, "sorted", false))) return rc;
+    const int32_t n = sorted->n;
+    if ((rc = check_nlist(nl, n))) return rc;
+    if (n > 0 && !f_out) return fail(DPD_EINVAL, "f_out is NULL");
+    const bool bonds = kp.partner != nullptr;
+    if (bonds && (rc = check_cells(cells, n, true))) return rc;
+    if (precision == DPD_MIXED && n > 0 && (!x32 || !v32))
+        return fail(DPD_EINVAL, "mixed precision needs x32 and v32");
+    if (precision == DPD_MIXED && n > 0 && (!aligned(x32, 16) || !aligned(v32, 16)))
+        return fail(DPD_EINVAL, "x32 / v32 must be 16-byte aligned");
+    ForceArgs& a = *out;
+    a.n = n; a.x = sorted->x; a.v = sorted->v; a.tag = sorted->tag; a.type = sorted->type;
+    a.cell_xyz = cells ? cells->cell_xyz : nullptr; a.x32 = x32; a.v32 = v32;
+    a.offset = nl->offset; a.index = nl->index; a.capacity = nl->capacity;
+    a.idx_of_tag = cells ? cells->idx_of_tag : nullptr;
+    a.d_step = nullptr; a.step_add = step;
+    a.f = f_out; a.pe = pe_out;
+    a.npair = nullptr;
+    a.fred_part = nullptr;
+    a.status = d_status;
+    a.grid = force_blocks(n, precision);
+    a.slab = nullptr; a.slab_k = 0; a.slab_flag = nullptr; a.slab_coded = 0;
+    a.x64 = nullptr; a.v64 = nullptr;
+    return DPD_OK;
+}
+
+// the force pass and, with stats, the fixed-order sum of its partials
+int enqueue_forces(const KParams& kp, int32_t precision, const ForceArgs& a, double* stats, int32_t* d_status,
+                   hipStream_t s)
+{
+    const BatchView none{};
+    DPD_TRY(launch_forces(kp, none, precision, a, s), "forces");
+    if (stats)
+        DPD_TRY(launch_reduce_final(a.n, nullptr, 0, a.fred_part, force_grid(a), nullptr, stats, nullptr,
+                                    d_status, s), "force stats");
+    return DPD_OK;
+}
+
 }  // namespace
 }  // namespace dpd
 
@@ -540,41 +594,13 @@ int dpd_forces(const dpd_params* p, int32_t precision, const dpd_state* sorted, 
                double* pe_out, double* stats, int32_t* d_status, void* ws, size_t ws_bytes, void* stream)
 {
     KParams kp;
-    int rc = make_kparams(p, &kp);
-    if (rc) return rc;
-    if (precision != DPD_FP64 && precision != DPD_MIXED) return fail(DPD_EINVAL, "unknown precision %d", precision);
-    if ((rc = check_state(sorted, "sorted", false))) return rc;
-    const int32_t n = sorted->n;
-    if ((rc = check_nlist(nl, n))) return rc;
-    if (n > 0 && !f_out) return fail(DPD_EINVAL, "f_out is NULL");
-    const bool bonds = kp.partner != nullptr;
-    if (bonds && (rc = check_cells(cells, n, true))) return rc;
-    if (precision == DPD_MIXED && n > 0 && (!x32 || !v32))
-        return fail(DPD_EINVAL, "mixed precision needs x32 and v32");
-    if (precision == DPD_MIXED && n > 0 && (!aligned(x32, 16) || !aligned(v32, 16)))
-        return fail(DPD_EINVAL, "x32 / v32 must be 16-byte aligned");
-    const WsLayout L = ws_layout(kp, n);
-    if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
-    const hipStream_t s = as_stream(stream);
     ForceArgs a;
-    a.n = n; a.x = sorted->x; a.v = sorted->v; a.tag = sorted->tag; a.type = sorted->type;
-    a.cell_xyz = cells ? cells->cell_xyz : nullptr; a.x32 = x32; a.v32 = v32;
-    a.offset = nl->offset; a.index = nl->index; a.capacity = nl->capacity;
-    a.idx_of_tag = cells ? cells->idx_of_tag : nullptr;
-    a.d_step = nullptr; a.step_add = step;
-    a.f = f_out; a.pe = pe_out;
-    a.npair = nullptr;
+    int rc = prepare_forces(p, precision, sorted, cells, x32, v32, nl, step, f_out, pe_out, d_status, &kp, &a);
+    if (rc) return rc;
+    const WsLayout L = ws_layout(kp, a.n);
+    if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
     a.fred_part = stats ? carve<double>(ws, L.fred_part) : nullptr;
-    a.status = d_status;
-    a.grid = force_blocks(n, precision);
-    a.slab = nullptr; a.slab_k = 0; a.slab_flag = nullptr; a.slab_coded = 0;
-    a.x64 = nullptr; a.v64 = nullptr;
-    const BatchView none{};
-    DPD_TRY(launch_forces(kp, none, precision, a, s), "forces");
-    if (stats)
-        DPD_TRY(launch_reduce_final(n, nullptr, 0, a.fred_part, force_grid(a), nullptr, stats, nullptr,
-                                    d_status, s), "force stats");
-    return DPD_OK;
+    return enqueue_forces(kp, precision, a, stats, d_status, as_stream(stream));
 }
 
 int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_steps, uint64_t* d_step,
@@ -647,11 +673,45 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
     // state (v after phase 2 is only needed for the statistics and by the
     // next phase 1); the last step's phase 2 runs alone.
     DriftArgs drift{st->x, st->tag, st->type, b.x, b.v, bvt, b.tag, b.type};
+    // With a skin, the first step of the call rebuilds; every later step
+    // drifts the sorted state in place and rebuilds (copy to the reorder's
+    // source, reorder, list) only when some particle has moved more than
+    // skin / 2 since the last rebuild, which the drift pass reports in the
+    // step's gate (steps alternate between two gate words, so the statistics
+    // of step k - 1, summed during step k, still see their step's word).
+    const bool skin = kp.rl2 != kp.rc2;
+    int32_t* gates = skin ? carve<int32_t>(ws, L.gate) : nullptr;
+    const double half_skin = 0.5 * (p->skin);
+    SkinDriftArgs sd;
+    sd.x = st->x; sd.v = st->v; sd.vt = vt_sorted; sd.f = st->f;
+    sd.tag = st->tag; sd.type = st->type; sd.cell_xyz = cells->cell_xyz;
+    sd.xref = skin ? carve<double>(ws, L.xref) : nullptr;
+    sd.x32 = mixed ? x32 : nullptr;           // (the FP64 step reads x32 only in a rebuild)
+    sd.v32 = mixed ? v32 : nullptr;
+    sd.x64 = aos ? carve<double>(ws, L.x64) : nullptr;
+    sd.v64 = aos ? carve<double>(ws, L.v64) : nullptr;
+    sd.flag = nullptr;
+    // (slightly below (skin/2)^2, so rounding in the displacement can only
+    // rebuild early)
+    sd.disp2 = half_skin * half_skin * (1.0 - std::ldexp(1.0, -20));
     for (int32_t k = 0; k < n_steps; ++k) {
+        Job jk = job;
+        int32_t* g = skin ? gates + (k & 1) : nullptr;
+        jk.gate = g;
         DPD_TRY(mark(k, 0), "event");
         if (k == 0) {
+            if (skin) DPD_TRY(launch_fill_i32(g, 1, 1, s), "rebuild flag");
             DPD_TRY(launch_vv1(kp, job.bv, n, st->x, st->v, st->f, st->tag, st->type, b.x, b.v, bvt, b.tag, b.type, s),
                     "vv1");
+        } else if (skin) {
+            DPD_TRY(launch_fill_i32(g, 1, 0, s), "rebuild flag");
+            sd.flag = g;
+            DPD_TRY(launch_drift_skin(kp, n, sd, red_part, a.fred_part, force_grid(a), fsum_part, s), "vv2 + vv1");
+            DPD_TRY(launch_reduce_final(n, red_part, kRedBlocks, fsum_part, kRedBlocks,
+                                        d_reductions ? d_reductions + 8 * (int64_t)(k - 1) : nullptr, nullptr,
+                                        d_step, d_status, s, gates + ((k - 1) & 1)), "reduce");
+            DPD_TRY(launch_precopy(n, st->x, st->v, vt_sorted, st->tag, st->type, b.x, b.v, bvt, b.tag, b.type, s, g),
+                    "pre-reorder copy");
         } else {
             DPD_TRY(launch_vv2(kp, n, st->v, st->f, red_part, a.fred_part, force_grid(a), fsum_part, s, &drift),
                     "vv2 + vv1");
@@ -660,14 +720,14 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
                                         d_step, d_status, s), "reduce");
         }
         DPD_TRY(mark(k, 1), "event");
-        rc = enqueue_reorder(job, L, ws, &b, bvt, st, vt_sorted, cells, x32, mixed ? v32 : nullptr, s, aos,
-                             k > 0 ? inv : nullptr, !bonds || k == 0 || k == n_steps - 1);
+        rc = enqueue_reorder(jk, L, ws, &b, bvt, st, vt_sorted, cells, x32, mixed ? v32 : nullptr, s, aos,
+                             k > 0 ? inv : nullptr, !bonds || skin || k == 0 || k == n_steps - 1);
         if (rc) return rc;
         if (bonds) {
             if (k == 0) {
                 DPD_TRY(launch_pidx_init(kp, n, st->tag, cells->idx_of_tag, pidx_cur, s), "bond partners");
             } else {
-                DPD_TRY(launch_pidx_update(n, cells->perm, inv, pidx_cur, pidx_nxt, s), "bond partners");
+                DPD_TRY(launch_pidx_update(n, cells->perm, inv, pidx_cur, pidx_nxt, s, g), "bond partners");
                 std::swap(pidx_cur, pidx_nxt);
             }
             a.pidx = pidx_cur;
@@ -675,7 +735,7 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
         DPD_TRY(mark(k, 2), "event");
         // inside a call the force pass reads the builder's slab; the CSR list
         // is written for the last step, which the caller sees
-        rc = enqueue_nlist(job, L, ws, st, cells, x32, nl, d_status, s, k == n_steps - 1);
+        rc = enqueue_nlist(jk, L, ws, st, cells, x32, nl, d_status, s, k == n_steps - 1);
         if (rc) return rc;
         DPD_TRY(mark(k, 3), "event");
         DPD_TRY(launch_forces(kp, job.bv, precision, a, s), "forces");
@@ -684,7 +744,7 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
             DPD_TRY(launch_vv2(kp, n, st->v, st->f, red_part, a.fred_part, force_grid(a), fsum_part, s), "vv2");
             DPD_TRY(launch_reduce_final(n, red_part, kRedBlocks, fsum_part, kRedBlocks,
                                         d_reductions ? d_reductions + 8 * (int64_t)k : nullptr, nullptr, d_step,
-                                        d_status, s), "reduce");
+                                        d_status, s, g), "reduce");
         }
         DPD_TRY(mark(k, 5), "event");
     }
@@ -759,6 +819,67 @@ int dpd_step_backward(const dpd_params* p, const dpd_state* st, const dpd_cells*
     b.xphi = slab;
     b.vphi = slab + 3 * (size_t)(n > 0 ? n : 1);
     DPD_TRY(launch_step_backward(kp, b, as_stream(stream)), "step backward");
+    return DPD_OK;
+}
+
+size_t dpd_border_workspace_bytes(int32_t n)
+{
+    if (n < 0) return 0;
+    return border_ws_layout(n).total;
+}
+
+int dpd_border_lists(const dpd_state* st, const double lo[3], const double hi[3], double width, int32_t face_mask,
+                     int32_t* send_offset, int32_t* send_index, int64_t capacity, int32_t* d_status, void* ws,
+                     size_t ws_bytes, void* stream)
+{
+    if (!st) return fail(DPD_EINVAL, "state is NULL");
+    if (st->n < 0) return fail(DPD_EINVAL, "state->n must be >= 0");
+    if (st->n > 0 && !st->x) return fail(DPD_EINVAL, "state->x is NULL");
+    if (!lo || !hi) return fail(DPD_EINVAL, "lo / hi is NULL");
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(lo[d]) || !std::isfinite(hi[d]) || !(lo[d] < hi[d]))
+            return fail(DPD_EINVAL, "brick must have finite lo[%d] < hi[%d]", d, d);
+    if (!std::isfinite(width) || !(width >= 0.0)) return fail(DPD_EINVAL, "width must be finite and >= 0");
+    if (face_mask < 0 || face_mask > 63) return fail(DPD_EINVAL, "face_mask must be in [0, 63]");
+    if (!send_offset) return fail(DPD_EINVAL, "send_offset is NULL");
+    if (capacity < 0 || capacity >= ((int64_t)1 << 31)) return fail(DPD_EINVAL, "capacity must be in [0, 2^31)");
+    if (capacity > 0 && !send_index) return fail(DPD_EINVAL, "send_index is NULL");
+    int rc;
+    if ((rc = check_ws(ws, ws_bytes, border_ws_layout(st->n).total))) return rc;
+    DPD_TRY(launch_border_lists(st->n, st->x, lo, hi, width, face_mask, send_offset, send_index, capacity, d_status,
+                                ws, as_stream(stream)), "border lists");
+    return DPD_OK;
+}
+
+int dpd_border_pack(const dpd_state* st, const int32_t* send_offset, const int32_t* send_index, int64_t capacity,
+                    const double shift[18], dpd_ghost* records, int32_t* d_status, void* stream)
+{
+    int rc;
+    if ((rc = check_state(st, "state", false))) return rc;
+    if (!send_offset || !shift) return fail(DPD_EINVAL, "send_offset / shift is NULL");
+    if (capacity < 0 || capacity >= ((int64_t)1 << 31)) return fail(DPD_EINVAL, "capacity must be in [0, 2^31)");
+    if (capacity > 0 && (!send_index || !records)) return fail(DPD_EINVAL, "send_index / records is NULL");
+    if (capacity > 0 && !aligned(records, 8)) return fail(DPD_EINVAL, "records must be 8-byte aligned");
+    for (int q = 0; q < 18; ++q)
+        if (!std::isfinite(shift[q])) return fail(DPD_EINVAL, "shift must be finite");
+    if (capacity == 0) return DPD_OK;
+    DPD_TRY(launch_border_pack(st->n, st->x, st->v, st->tag, st->type, send_offset, send_index, capacity, shift,
+                               records, d_status, as_stream(stream)), "border pack");
+    return DPD_OK;
+}
+
+int dpd_border_unpack(const dpd_ghost* records, const int32_t* d_count, int64_t capacity, dpd_state* dst,
+                      int32_t first, int32_t* d_status, void* stream)
+{
+    int rc;
+    if ((rc = check_state(dst, "dst", false))) return rc;
+    if (!d_count) return fail(DPD_EINVAL, "d_count is NULL");
+    if (capacity < 0 || capacity >= ((int64_t)1 << 31)) return fail(DPD_EINVAL, "capacity must be in [0, 2^31)");
+    if (capacity > 0 && !records) return fail(DPD_EINVAL, "records is NULL");
+    if (first < 0 || first > dst->n) return fail(DPD_EINVAL, "first must be in [0, dst->n]");
+    if (capacity == 0) return DPD_OK;
+    DPD_TRY(launch_border_unpack(records, d_count, capacity, dst->n, first, dst->x, dst->v, dst->tag, dst->type,
+                                 d_status, as_stream(stream)), "border unpack");
     return DPD_OK;
 }
 

@@ -168,6 +168,13 @@ DPD_HD uint32_t pack_cell(int32_t cx, int32_t cy, int32_t cz)
     return (uint32_t)cx | ((uint32_t)cy << 10) | ((uint32_t)cz << 20);
 }
 
+// A gate: a kernel given one does its work only while *gate != 0 (a null
+// gate always lets it run).  With a Verlet skin, dpd_step sets the gate of
+// every step from the particles' displacements since the last rebuild, and
+// the kernels of binning, reordering and the list build read it (whole
+// blocks leave at once, so no barrier is skipped by part of a block).
+using Gate = const int32_t*;
+
 // A batch of independent systems: one KParams per system in device memory,
 // particle / cell / list-block offsets (n_sys + 1 entries each) and the
 // static particle -> system map.  kps == nullptr means a single system.
@@ -188,6 +195,8 @@ struct BatchView {
 // ---------------------------------------------------------------------------
 // Device helpers
 // ---------------------------------------------------------------------------
+
+__device__ __forceinline__ bool gated_off(Gate g) { return g != nullptr && *g == 0; }
 
 // largest s in [0, n_seg) with off[s] <= x (off ascending)
 __device__ __forceinline__ int32_t find_segment(const int32_t* __restrict__ off, int32_t n_seg, int32_t x)
@@ -224,9 +233,13 @@ __device__ __forceinline__ int lanes_below(uint64_t mask)
 
 __device__ __forceinline__ int32_t cell_coord(double x, double inv_cell, int32_t n)
 {
-    int32_t c = (int32_t)(x * inv_cell);     // truncation; x >= 0 for a wrapped state
-    c = c < 0 ? 0 : c;
-    return c > n - 1 ? n - 1 : c;
+    // truncation of x n_c / L, clamped to [0, n - 1] before the conversion
+    // (the same cell as clamping after it, since n - 1 is an integer); a
+    // non-finite position lands in cell 0 instead of an undefined integer
+    double q = x * inv_cell;
+    q = q > 0.0 ? q : 0.0;
+    q = q < (double)(n - 1) ? q : (double)(n - 1);
+    return (int32_t)q;
 }
 
 __device__ __forceinline__ double min_image(double d, double L, double halfL)

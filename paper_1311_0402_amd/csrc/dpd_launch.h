@@ -8,6 +8,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "dpd.h"
 #include "dpd_common.h"
 
 namespace dpd {
@@ -40,23 +41,27 @@ struct WsLayout {
     size_t tile_rest;                  // tiles left by the tile list builder: count, then tile ids
     size_t pidx_a, pidx_b, inv;        // bonds inside a step loop: partner indices (2 per particle,
                                        // two generations) and the old -> new index map
+    size_t xref;                       // skin > 0: positions at the last rebuild (sorted order)
+    size_t gate;                       // skin > 0: two rebuild flags (steps alternate between them)
     size_t total;
 };
 
 WsLayout ws_layout(const KParams& kp, int32_t n, bool aos = false);
 
 // ---- reorder (k_reorder.hip) ----
-hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t s, Gate gate = nullptr);
 // rank_tab[c_off + cx + nc_x (cy + nc_y cz)] = c_off + Morton rank of the cell
 // (bv.kps == nullptr: one system, c_off = 0, c_tot = its cell count)
 hipError_t launch_rank_table(const KParams& kp, const BatchView& bv, int32_t c_tot, int32_t* rank_tab,
                              hipStream_t s);
 hipError_t launch_bin(const KParams& kp, const BatchView& bv, int32_t n, const double* x, const int32_t* rank_tab,
-                      int32_t* key, int32_t* slot, uint32_t* cxyz, int32_t* counts, hipStream_t s);
+                      int32_t* key, int32_t* slot, uint32_t* cxyz, int32_t* counts, hipStream_t s,
+                      Gate gate = nullptr);
 // in-place exclusive scan of data[0 .. count); partials needs ceil(count/kScanTile) ints
-hipError_t launch_scan(int32_t* data, int64_t count, int32_t* partials, hipStream_t s);
+hipError_t launch_scan(int32_t* data, int64_t count, int32_t* partials, hipStream_t s, Gate gate = nullptr);
 hipError_t launch_place(int32_t n, const int32_t* key, const int32_t* slot, const int32_t* cell_start,
-                        const uint32_t* tag, uint32_t* tmp_tag, int32_t* tmp_src, int32_t* tmp_key, hipStream_t s);
+                        const uint32_t* tag, uint32_t* tmp_tag, int32_t* tmp_src, int32_t* tmp_key, hipStream_t s,
+                        Gate gate = nullptr);
 struct GatherArgs {
     const double* x_in; const double* v_in; const double* vt_in; const uint8_t* type_in;
     const uint32_t* cxyz_in;
@@ -65,18 +70,25 @@ struct GatherArgs {
     int32_t* inv = nullptr;         // nullable: inv[source index] = sorted index
     float* x32; float* v32;
     double* x64; double* v64;       // nullable: packed FP64 copies, double4 per particle
+    double* xref = nullptr;         // nullable: a second copy of the sorted positions ([3][n])
 };
 // bond partners of the sorted particles as sorted indices: pidx[2 i + b] =
 // idx_of_tag[partner[2 tag[i] + b]], -1 without a partner, -2 when the
 // partner tag has no particle
 hipError_t launch_pidx_init(const KParams& kp, int32_t n, const uint32_t* tag, const int32_t* idx_of_tag,
                             int32_t* pidx, hipStream_t s);
-// after a reorder: pidx_new[2 d + b] = inv[pidx_old[2 perm[d] + b]] (negative values kept)
+// after a reorder: pidx_new[2 d + b] = inv[pidx_old[2 perm[d] + b]] (negative values kept);
+// a step that did not reorder (gate off) copies pidx_old
 hipError_t launch_pidx_update(int32_t n, const int32_t* perm, const int32_t* inv, const int32_t* pidx_old,
-                              int32_t* pidx_new, hipStream_t s);
+                              int32_t* pidx_new, hipStream_t s, Gate gate = nullptr);
 hipError_t launch_finalize(const KParams& kp, const BatchView& bv, int32_t n, const int32_t* tmp_key,
                            const int32_t* cell_start, const uint32_t* tmp_tag, const int32_t* tmp_src,
-                           const GatherArgs& g, hipStream_t s);
+                           const GatherArgs& g, hipStream_t s, Gate gate = nullptr);
+// (gated) copy of a sorted state into the reorder's source buffers: x, v
+// ([3][n]), vt (nullable), tag, type
+hipError_t launch_precopy(int32_t n, const double* x, const double* v, const double* vt, const uint32_t* tag,
+                          const uint8_t* type, double* bx, double* bv, double* bvt, uint32_t* btag,
+                          uint8_t* btype, hipStream_t s, Gate gate);
 
 // ---- neighbour list (k_nlist.hip) ----
 int32_t nlist_slab_width(double density, double rl2);
@@ -97,7 +109,8 @@ hipError_t launch_nlist(const KParams& kp, const BatchView& bv, int32_t n_cells,
                         int32_t n, const double* x, const float* x32, const uint32_t* cell_xyz,
                         const int32_t* cell_start, const int32_t* rank_tab, int32_t* offset, int32_t* index,
                         int64_t capacity, int32_t* slab, int32_t slab_k, int32_t* flag, int32_t* tile_rest,
-                        int32_t* status, int32_t* scan_part, int waves, int kind, bool compact, hipStream_t s);
+                        int32_t* status, int32_t* scan_part, int waves, int kind, bool compact, hipStream_t s,
+                        Gate gate = nullptr);
 // whether that build leaves coded slab entries (tile and lane builders, n < 2^26)
 bool nlist_slab_coded(int kind, const uint32_t* cell_xyz, int32_t n_cells, int32_t n);
 // waves per workgroup of the tile builder for n particles in n_cells cells
@@ -178,11 +191,58 @@ struct DriftArgs {
 hipError_t launch_vv2(const KParams& kp, int32_t n, double* v, const double* f, double* red_part,
                       const double* fred_part, int32_t n_fred, double* fsum_part, hipStream_t s,
                       const DriftArgs* drift = nullptr);
-// sums the partials in a fixed order; red (nullable) gets the 8 step totals;
-// stats (nullable) gets (PE, pairs); increments *d_step when non-null
+// The first phase of a step with a Verlet skin, in place on the sorted
+// state (no reorder follows unless the gate says so): v~ / v_h and x from
+// the previous step's v_h and F (its second phase v = v_h + dt/2 F is summed
+// for the statistics, not stored), the packed copies of the new state (FP32
+// offsets from each particle's cell at the last rebuild, FP64 copies), and
+// *flag |= 1 when some particle is more than skin / 2 (disp2: the squared
+// threshold) from its position at the last rebuild.  Momentum and |v|^2
+// partials and the force partials' fold as launch_vv2.
+struct SkinDriftArgs {
+    double* x; double* v; double* vt;             // sorted state, in place (vt nullable)
+    const double* f;
+    const uint32_t* tag; const uint8_t* type; const uint32_t* cell_xyz;
+    const double* xref;                            // positions at the last rebuild
+    float* x32; float* v32;                        // nullable
+    double* x64; double* v64;                      // nullable
+    int32_t* flag;
+    double disp2;
+};
+hipError_t launch_drift_skin(const KParams& kp, int32_t n, const SkinDriftArgs& d, double* red_part,
+                             const double* fred_part, int32_t n_fred, double* fsum_part, hipStream_t s);
+// sums the partials in a fixed order; red (nullable) gets the 8 step totals
+// (the last one: 1 when the step rebuilt the lists, read from *rebuilt, or
+// 1 when rebuilt is null); stats (nullable) gets (PE, pairs); increments
+// *d_step when non-null
 hipError_t launch_reduce_final(int32_t n, const double* red_part, int n_red, const double* fred_part,
                                int n_fred, double* red, double* stats, uint64_t* d_step,
-                               int32_t* status, hipStream_t s);
+                               int32_t* status, hipStream_t s, const int32_t* rebuilt = nullptr);
+
+// ---- border determination and ghosts (k_border.hip) ----
+struct BorderWs {
+    int32_t n_blk;                     // blocks of kBlock particles
+    size_t flags;                      // uint8 face bits per particle
+    size_t cnt;                        // int32 [6 n_blk + 1]: per-block counts, scanned in place
+    size_t scan_part;                  // partials of the scan
+    size_t total;
+};
+BorderWs border_ws_layout(int32_t n);
+// send lists of the selected faces (face_mask bit f = 2 d + s) of the brick
+// [lo, hi): flag, scan of the per-block counts, compaction; send_offset[7]
+// gets the face offsets, send_index the ascending lists (nothing written
+// past capacity; the status bit reports a short buffer)
+hipError_t launch_border_lists(int32_t n, const double* x, const double lo[3], const double hi[3], double width,
+                               int32_t face_mask, int32_t* send_offset, int32_t* send_index, int64_t capacity,
+                               int32_t* status, void* ws, hipStream_t s);
+// one record per send-list entry: position + shift[face], velocity, tag, type
+hipError_t launch_border_pack(int32_t n, const double* x, const double* v, const uint32_t* tag, const uint8_t* type,
+                              const int32_t* send_offset, const int32_t* send_index, int64_t capacity,
+                              const double shift[18], dpd_ghost* out, int32_t* status, hipStream_t s);
+// records [0, *d_count) into the state arrays at [first, first + count)
+hipError_t launch_border_unpack(const dpd_ghost* in, const int32_t* d_count, int64_t capacity, int32_t n_dst,
+                                int32_t first, double* x, double* v, uint32_t* tag, uint8_t* type, int32_t* status,
+                                hipStream_t s);
 
 // ---- adjoint (k_adjoint.hip) ----
 struct BackwardArgs {

@@ -125,7 +125,8 @@ __global__ __launch_bounds__(kBlock) void k_sys_reduce(BatchView bat, const doub
         if (red) {
             const int64_t row = base ? (int64_t)(*d_step - *base) : 0;
             double* r = red + 8 * (row * bat.n_sys + sy);
-            r[0] = P0; r[1] = P1; r[2] = P2; r[3] = v2; r[4] = s[4][0]; r[5] = 0.5 * s[5][0]; r[6] = kbt; r[7] = 0.0;
+            // (a batch rebuilds its lists every step)
+            r[0] = P0; r[1] = P1; r[2] = P2; r[3] = v2; r[4] = s[4][0]; r[5] = 0.5 * s[5][0]; r[6] = kbt; r[7] = 1.0;
         }
         const double chk = P0 + P1 + P2 + v2 + s[4][0];
         if (status && !(chk - chk == 0.0)) atomicOr(status, 2 /* DPD_STATUS_NONFINITE */);
@@ -216,6 +217,109 @@ __global__ __launch_bounds__(kBlock) void k_vv2(KParams kp, int32_t n, double* _
     }
 }
 
+// The first phase of a step with a Verlet skin, in place on the sorted state
+// (the same arithmetic as k_vv2 followed by k_vv1), one thread per particle
+// over a fixed grid of kRedBlocks blocks so the momentum and |v|^2 partials
+// keep k_vv2's layout.  Besides the new x and v~ it writes the packed copies
+// the list-free steps' force pass reads, and raises the rebuild flag when a
+// particle is more than skin / 2 from where the last rebuild saw it.
+__global__ __launch_bounds__(kBlock) void k_drift_skin(KParams kp, int32_t n, SkinDriftArgs d,
+                                                       double* __restrict__ part, const double* __restrict__ fred,
+                                                       int32_t n_fred, double* __restrict__ fsum)
+{
+    __shared__ double s_p[3][kBlock / kWave], s_q[3][kBlock / kWave];
+    const int64_t N = n;
+    double p[3] = {0.0, 0.0, 0.0}, q[3] = {0.0, 0.0, 0.0};
+    bool far = false;
+    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += kRedBlocks * kBlock) {
+        const uint32_t cc = d.cell_xyz[i];
+        const int32_t cell[3] = {(int32_t)(cc & 1023u), (int32_t)((cc >> 10) & 1023u), (int32_t)(cc >> 20)};
+        double xn[3], vh[3], vt[3], r2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int64_t a = k * N + i;
+            const double fk = d.f[a];
+            const double vn = __fma_rn(kp.half_dt, fk, d.v[a]);     // phase 2 of the previous step
+            vh[k] = __fma_rn(kp.half_dt, fk, vn);                   // phase 1 of this step
+            double x = __fma_rn(kp.dt, vh[k], d.x[a]);
+            if (x < 0.0) x = x + kp.L[k];
+            if (x >= kp.L[k]) x = x - kp.L[k];
+            xn[k] = x;
+            vt[k] = d.vt ? __fma_rn(kp.lam_dt, fk, vn) : vh[k];
+            d.x[a] = x;
+            d.v[a] = vh[k];
+            if (d.vt) d.vt[a] = vt[k];
+            p[k] += vn;
+            q[k] += vn * vn;
+            const double dk = min_image(x - d.xref[a], kp.L[k], kp.halfL[k]);
+            r2 = __fma_rn(dk, dk, r2);
+        }
+        far = far || r2 > d.disp2;
+        if (d.x32) {
+            // offset from the cell the particle had at the last rebuild,
+            // taken to the periodic image next to that cell
+            float o[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                o[k] = (float)min_image(xn[k] - (double)cell[k] * kp.cell_len[k], kp.L[k], kp.halfL[k]);
+            reinterpret_cast<float4*>(d.x32)[i] = make_float4(o[0], o[1], o[2], __uint_as_float(d.tag[i]));
+        }
+        if (d.v32)
+            reinterpret_cast<float4*>(d.v32)[i] =
+                make_float4((float)vt[0], (float)vt[1], (float)vt[2], __uint_as_float((uint32_t)d.type[i]));
+        if (d.x64) {
+            double4 px, pv;
+            px.x = xn[0]; px.y = xn[1]; px.z = xn[2]; px.w = __longlong_as_double((long long)d.tag[i]);
+            pv.x = vt[0]; pv.y = vt[1]; pv.z = vt[2]; pv.w = __longlong_as_double((long long)d.type[i]);
+            reinterpret_cast<double4*>(d.x64)[i] = px;
+            reinterpret_cast<double4*>(d.v64)[i] = pv;
+        }
+    }
+    if (__ballot(far) && lane_id() == 0) atomicOr(d.flag, 1);
+    if (fred) {
+        // the force kernel's (PE, pairs) partials folded as k_vv2 does
+        __shared__ double s_fa[kBlock], s_fb[kBlock];
+        double fa = 0.0, fb = 0.0;
+        for (int32_t m = blockIdx.x + kRedBlocks * threadIdx.x; m < n_fred; m += kRedBlocks * kBlock) {
+            fa += fred[2 * (int64_t)m];
+            fb += fred[2 * (int64_t)m + 1];
+        }
+        s_fa[threadIdx.x] = fa;
+        s_fb[threadIdx.x] = fb;
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) {
+                s_fa[threadIdx.x] += s_fa[threadIdx.x + w];
+                s_fb[threadIdx.x] += s_fb[threadIdx.x + w];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            fsum[2 * blockIdx.x] = s_fa[0];
+            fsum[2 * blockIdx.x + 1] = s_fb[0];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int dd = kWave / 2; dd > 0; dd >>= 1) {
+            p[k] += __shfl_down(p[k], dd, kWave);
+            q[k] += __shfl_down(q[k], dd, kWave);
+        }
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { s_p[k][w] = p[k]; s_q[k][w] = q[k]; }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int k = threadIdx.x;
+        double tp = 0.0, tq = 0.0;
+        for (int m = 0; m < kBlock / kWave; ++m) { tp += s_p[k][m]; tq += s_q[k][m]; }
+        part[2 * ((int64_t)k * kRedBlocks + blockIdx.x)] = tp;
+        part[2 * ((int64_t)k * kRedBlocks + blockIdx.x) + 1] = tq;
+    }
+}
+
 // fixed-order block sum: thread t adds entries t, t + 256, ... of a strided
 // array, then a fixed tree over the block
 __device__ double block_sum_strided(const double* __restrict__ src, int count, int stride, int offset)
@@ -238,7 +342,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_final(int32_t n, const double
                                                          int n_red, const double* __restrict__ fred_part,
                                                          int n_fred, double* __restrict__ red,
                                                          double* __restrict__ stats, uint64_t* d_step,
-                                                         int32_t* status)
+                                                         int32_t* status, const int32_t* __restrict__ rebuilt)
 {
     double P[3] = {0.0, 0.0, 0.0}, v2 = 0.0, pe = 0.0, pairs = 0.0;
     if (red_part) {
@@ -256,7 +360,8 @@ __global__ __launch_bounds__(kBlock) void k_reduce_final(int32_t n, const double
         const double kbt = n > 1 ? (v2 - (P[0] * P[0] + P[1] * P[1] + P[2] * P[2]) / nn) / (3.0 * (nn - 1.0)) : 0.0;
         if (red) {
             red[0] = P[0]; red[1] = P[1]; red[2] = P[2];
-            red[3] = v2; red[4] = pe; red[5] = pairs; red[6] = kbt; red[7] = 0.0;
+            red[3] = v2; red[4] = pe; red[5] = pairs; red[6] = kbt;
+            red[7] = rebuilt ? (*rebuilt != 0 ? 1.0 : 0.0) : 1.0;
         }
         if (stats) { stats[0] = pe; stats[1] = pairs; }
         const double chk = P[0] + P[1] + P[2] + v2 + pe;
@@ -317,12 +422,20 @@ hipError_t launch_vv2(const KParams& kp, int32_t n, double* v, const double* f, 
     return hipGetLastError();
 }
 
+hipError_t launch_drift_skin(const KParams& kp, int32_t n, const SkinDriftArgs& d, double* red_part,
+                             const double* fred_part, int32_t n_fred, double* fsum_part, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_drift_skin, dim3(kRedBlocks), dim3(kBlock), 0, s, kp, n, d, red_part, fred_part, n_fred,
+                       fsum_part);
+    return hipGetLastError();
+}
+
 hipError_t launch_reduce_final(int32_t n, const double* red_part, int n_red, const double* fred_part,
                                int n_fred, double* red, double* stats, uint64_t* d_step, int32_t* status,
-                               hipStream_t s)
+                               hipStream_t s, const int32_t* rebuilt)
 {
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, s, n, red_part, n_red, fred_part, n_fred,
-                       red, stats, d_step, status);
+                       red, stats, d_step, status, rebuilt);
     return hipGetLastError();
 }
 

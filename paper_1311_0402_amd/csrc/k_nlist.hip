@@ -222,8 +222,9 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist(KParams kp, BatchView bv, 
                                                       const int32_t* __restrict__ rank_tab,
                                                       int32_t* __restrict__ offset, int32_t* __restrict__ index,
                                                       int64_t capacity, int32_t* __restrict__ slab, int32_t slab_k,
-                                                      int32_t* __restrict__ flag)
+                                                      int32_t* __restrict__ flag, Gate gate)
 {
+    if (gated_off(gate)) return;
     const int32_t blk = xcd_logical_id(blockIdx.x, gridDim.x) * kW + threadIdx.x / kWave;
     if (blk >= n_blocks) return;
     if (kDirect && (*flag == 0 || (int64_t)offset[n] > capacity)) return;
@@ -339,8 +340,9 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_lanes(KParams kp, BatchVie
                                                             int32_t* __restrict__ offset,
                                                             int32_t* __restrict__ index, int64_t capacity,
                                                             int32_t* __restrict__ slab, int32_t slab_k,
-                                                            int32_t* __restrict__ flag)
+                                                            int32_t* __restrict__ flag, Gate gate)
 {
+    if (gated_off(gate)) return;
     const int32_t i = xcd_logical_id(blockIdx.x, gridDim.x) * (kW * kWave) + threadIdx.x;
     if (i >= n) return;
     if (kDirect && (*flag == 0 || (int64_t)offset[n] > capacity)) return;
@@ -355,64 +357,64 @@ template <bool kDirect, int kW>
 void launch_nlist_lanes(const KParams& kp, const BatchView& bv, int32_t n, const double* x, const float* x32,
                         const uint32_t* cell_xyz, const int32_t* cell_start, const int32_t* rank_tab,
                         int32_t* offset, int32_t* index, int64_t capacity, int32_t* slab, int32_t slab_k,
-                        int32_t* flag, hipStream_t s)
+                        int32_t* flag, hipStream_t s, Gate gate)
 {
     const dim3 grid(ceil_div(n, kW * kWave)), block(kW * kWave);
     if (bv.kps)
         hipLaunchKernelGGL((k_nlist_lanes<kDirect, true, kW>), grid, block, 0, s, kp, bv, n, x, x32, cell_xyz,
-                           cell_start, rank_tab, offset, index, capacity, slab, slab_k, flag);
+                           cell_start, rank_tab, offset, index, capacity, slab, slab_k, flag, gate);
     else
         hipLaunchKernelGGL((k_nlist_lanes<kDirect, false, kW>), grid, block, 0, s, kp, bv, n, x, x32, cell_xyz,
-                           cell_start, rank_tab, offset, index, capacity, slab, slab_k, flag);
+                           cell_start, rank_tab, offset, index, capacity, slab, slab_k, flag, gate);
 }
 
 template <bool kDirect>
 void launch_nlist_lanes(int waves, const KParams& kp, const BatchView& bv, int32_t n, const double* x,
                         const float* x32, const uint32_t* cell_xyz, const int32_t* cell_start,
                         const int32_t* rank_tab, int32_t* offset, int32_t* index, int64_t capacity,
-                        int32_t* slab, int32_t slab_k, int32_t* flag, hipStream_t s)
+                        int32_t* slab, int32_t slab_k, int32_t* flag, hipStream_t s, Gate gate)
 {
     if (waves == 1)
         launch_nlist_lanes<kDirect, 1>(kp, bv, n, x, x32, cell_xyz, cell_start, rank_tab, offset, index, capacity,
-                                       slab, slab_k, flag, s);
+                                       slab, slab_k, flag, s, gate);
     else if (waves == 2)
         launch_nlist_lanes<kDirect, 2>(kp, bv, n, x, x32, cell_xyz, cell_start, rank_tab, offset, index, capacity,
-                                       slab, slab_k, flag, s);
+                                       slab, slab_k, flag, s, gate);
     else
         launch_nlist_lanes<kDirect, 4>(kp, bv, n, x, x32, cell_xyz, cell_start, rank_tab, offset, index, capacity,
-                                       slab, slab_k, flag, s);
+                                       slab, slab_k, flag, s, gate);
 }
 
 template <bool kDirect, int kW>
 void launch_nlist_pass(const KParams& kp, const BatchView& bv, int32_t n_blocks, int32_t n, const double* x,
                        const float* x32, const int32_t* cell_start, const int32_t* rank_tab, int32_t* offset,
                        int32_t* index, int64_t capacity, int32_t* slab, int32_t slab_k, int32_t* flag,
-                       hipStream_t s)
+                       hipStream_t s, Gate gate)
 {
     const dim3 grid(ceil_div(n_blocks, kW)), block(kW * kWave);
     if (bv.kps)
         hipLaunchKernelGGL((k_nlist<kDirect, true, kW>), grid, block, 0, s, kp, bv, n_blocks, n, x, x32, cell_start,
-                           rank_tab, offset, index, capacity, slab, slab_k, flag);
+                           rank_tab, offset, index, capacity, slab, slab_k, flag, gate);
     else
         hipLaunchKernelGGL((k_nlist<kDirect, false, kW>), grid, block, 0, s, kp, bv, n_blocks, n, x, x32,
-                           cell_start, rank_tab, offset, index, capacity, slab, slab_k, flag);
+                           cell_start, rank_tab, offset, index, capacity, slab, slab_k, flag, gate);
 }
 
 template <bool kDirect>
 void launch_nlist_pass(int waves, const KParams& kp, const BatchView& bv, int32_t n_blocks, int32_t n,
                        const double* x, const float* x32, const int32_t* cell_start, const int32_t* rank_tab,
                        int32_t* offset, int32_t* index, int64_t capacity, int32_t* slab, int32_t slab_k,
-                       int32_t* flag, hipStream_t s)
+                       int32_t* flag, hipStream_t s, Gate gate)
 {
     if (waves == 1)
         launch_nlist_pass<kDirect, 1>(kp, bv, n_blocks, n, x, x32, cell_start, rank_tab, offset, index, capacity,
-                                      slab, slab_k, flag, s);
+                                      slab, slab_k, flag, s, gate);
     else if (waves == 2)
         launch_nlist_pass<kDirect, 2>(kp, bv, n_blocks, n, x, x32, cell_start, rank_tab, offset, index, capacity,
-                                      slab, slab_k, flag, s);
+                                      slab, slab_k, flag, s, gate);
     else
         launch_nlist_pass<kDirect, 4>(kp, bv, n_blocks, n, x, x32, cell_start, rank_tab, offset, index, capacity,
-                                      slab, slab_k, flag, s);
+                                      slab, slab_k, flag, s, gate);
 }
 
 // ---- tile builder ----
@@ -526,8 +528,9 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
                                                             int32_t* __restrict__ offset,
                                                             int32_t* __restrict__ slab, int32_t slab_k,
                                                             int32_t* __restrict__ flag,
-                                                            int32_t* __restrict__ rest)
+                                                            int32_t* __restrict__ rest, Gate gate)
 {
+    if (gated_off(gate)) return;
     constexpr int kThreads = kW * kWave;
     static_assert(kThreads >= kTU && kThreads >= kTC, "one thread per union cell and per tile cell");
     __shared__ int32_t s_rank[kTU];
@@ -717,8 +720,9 @@ __global__ __launch_bounds__(kBlock) void k_nlist_tile_rest(KParams kp, BatchVie
                                                             int32_t* __restrict__ offset,
                                                             int32_t* __restrict__ slab, int32_t slab_k,
                                                             int32_t* __restrict__ flag,
-                                                            const int32_t* __restrict__ rest)
+                                                            const int32_t* __restrict__ rest, Gate gate)
 {
+    if (gated_off(gate)) return;
     const int32_t count = rest[0];
     for (int32_t t = blockIdx.x; t < count; t += gridDim.x) {
         const TileGeom g = tile_geom<kB>(kp, bv, rest[1 + t], cell_start, rank_tab);
@@ -732,10 +736,10 @@ template <bool kB, int kW>
 void launch_nlist_tiles_t(const KParams& kp, const BatchView& bv, int32_t n_tiles, int32_t n, const double* x,
                           const float* x32, const uint32_t* cell_xyz, const int32_t* cell_start,
                           const int32_t* rank_tab, int32_t* offset, int32_t* slab, int32_t slab_k, int32_t* flag,
-                          int32_t* rest, hipStream_t s)
+                          int32_t* rest, hipStream_t s, Gate gate)
 {
     hipLaunchKernelGGL((k_nlist_tiles<kB, kW>), dim3(n_tiles), dim3(kW * kWave), 0, s, kp, bv, n_tiles, n, x, x32,
-                       cell_xyz, cell_start, rank_tab, offset, slab, slab_k, flag, rest);
+                       cell_xyz, cell_start, rank_tab, offset, slab, slab_k, flag, rest, gate);
 }
 
 // tile pass, then the pass over the tiles it left; rest[0] must be 0
@@ -743,11 +747,11 @@ template <bool kB>
 void launch_nlist_tiles(int waves, const KParams& kp, const BatchView& bv, int32_t n_tiles, int32_t n,
                         const double* x, const float* x32, const uint32_t* cell_xyz, const int32_t* cell_start,
                         const int32_t* rank_tab, int32_t* offset, int32_t* slab, int32_t slab_k, int32_t* flag,
-                        int32_t* rest, hipStream_t s)
+                        int32_t* rest, hipStream_t s, Gate gate)
 {
 #define DPD_TILE_CASE(W)                                                                                         \
     launch_nlist_tiles_t<kB, W>(kp, bv, n_tiles, n, x, x32, cell_xyz, cell_start, rank_tab, offset, slab, slab_k, \
-                                flag, rest, s)
+                                flag, rest, s, gate)
     if (waves <= 6) DPD_TILE_CASE(6);
     else if (waves <= 7) DPD_TILE_CASE(7);
     else if (waves <= 8) DPD_TILE_CASE(8);
@@ -757,7 +761,7 @@ void launch_nlist_tiles(int waves, const KParams& kp, const BatchView& bv, int32
 #undef DPD_TILE_CASE
     const int grid = n_tiles < 1024 ? n_tiles : 1024;
     hipLaunchKernelGGL((k_nlist_tile_rest<kB>), dim3(grid), dim3(kBlock), 0, s, kp, bv, n, x, x32, cell_xyz,
-                       cell_start, rank_tab, offset, slab, slab_k, flag, (const int32_t*)rest);
+                       cell_start, rank_tab, offset, slab, slab_k, flag, (const int32_t*)rest, gate);
 }
 
 }  // namespace
@@ -810,8 +814,9 @@ __global__ __launch_bounds__(kBlock) void k_nlist_compact(int32_t n, const int32
 }
 
 __global__ void k_nlist_check(int32_t n, const int32_t* __restrict__ offset, int64_t capacity,
-                              int32_t* __restrict__ status)
+                              int32_t* __restrict__ status, Gate gate)
 {
+    if (gated_off(gate)) return;
     if (threadIdx.x == 0 && blockIdx.x == 0 && (int64_t)offset[n] > capacity)
         atomicOr(status, 1 /* DPD_STATUS_NLIST_OVERFLOW */);
 }
@@ -844,33 +849,39 @@ hipError_t launch_nlist(const KParams& kp, const BatchView& bv, int32_t n_cells,
                         int32_t n, const double* x, const float* x32, const uint32_t* cell_xyz,
                         const int32_t* cell_start, const int32_t* rank_tab, int32_t* offset, int32_t* index,
                         int64_t capacity, int32_t* slab, int32_t slab_k, int32_t* flag, int32_t* tile_rest,
-                        int32_t* status, int32_t* scan_part, int waves, int kind, bool compact, hipStream_t s)
+                        int32_t* status, int32_t* scan_part, int waves, int kind, bool compact, hipStream_t s,
+                        Gate gate)
 {
     if (n <= 0) return hipSuccess;
     hipError_t e;
     const bool tiles = kind == 0 && ranks_fit(cell_xyz, n_cells);
     const bool lanes = tiles || (kind == 2 && ranks_fit(cell_xyz, n_cells));
-    if ((e = launch_fill_i32(offset + n, 1, 0, s)) != hipSuccess) return e;
-    if ((e = launch_fill_i32(flag, 1, 0, s)) != hipSuccess) return e;
+    if ((e = launch_fill_i32(offset + n, 1, 0, s, gate)) != hipSuccess) return e;
+    if ((e = launch_fill_i32(flag, 1, 0, s, gate)) != hipSuccess) return e;
     if (tiles) {
-        if ((e = launch_fill_i32(tile_rest, 1, 0, s)) != hipSuccess) return e;
+        if ((e = launch_fill_i32(tile_rest, 1, 0, s, gate)) != hipSuccess) return e;
         const int tw = nlist_tile_waves(n, n_cells);
         if (bv.kps)
             launch_nlist_tiles<true>(tw, kp, bv, n_tiles, n, x, x32, cell_xyz, cell_start, rank_tab, offset, slab,
-                                     slab_k, flag, tile_rest, s);
+                                     slab_k, flag, tile_rest, s, gate);
         else
             launch_nlist_tiles<false>(tw, kp, bv, n_tiles, n, x, x32, cell_xyz, cell_start, rank_tab, offset, slab,
-                                      slab_k, flag, tile_rest, s);
+                                      slab_k, flag, tile_rest, s, gate);
     } else if (lanes)
         launch_nlist_lanes<false>(waves, kp, bv, n, x, x32, cell_xyz, cell_start, rank_tab, offset, index, capacity,
-                                  slab, slab_k, flag, s);
+                                  slab, slab_k, flag, s, gate);
     else
         launch_nlist_pass<false>(waves, kp, bv, n_blocks, n, x, x32, cell_start, rank_tab, offset, index, capacity,
-                                 slab, slab_k, flag, s);
-    if ((e = launch_scan(offset, (int64_t)n + 1, scan_part, s)) != hipSuccess) return e;
-    if ((e = launch_nlist_check(n, offset, capacity, status, s)) != hipSuccess) return e;
+                                 slab, slab_k, flag, s, gate);
+    if ((e = launch_scan(offset, (int64_t)n + 1, scan_part, s, gate)) != hipSuccess) return e;
+    if (status) {
+        hipLaunchKernelGGL(k_nlist_check, dim3(1), dim3(64), 0, s, n, (const int32_t*)offset, capacity, status, gate);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     // without compaction the CSR index is left unwritten unless a row
-    // overflowed the slab (then the direct pass below writes it)
+    // overflowed the slab (then the direct pass below writes it).  The
+    // compaction takes no gate: after a step that kept the last build's
+    // rows it copies those rows again.
     if (compact)
         hipLaunchKernelGGL(k_nlist_compact, dim3(ceil_div(ceil_div(n, kWave), kWavesPerBlock)), dim3(kBlock), 0,
                            s, n, (const int32_t*)offset, capacity, (const int32_t*)slab, slab_k,
@@ -879,10 +890,10 @@ hipError_t launch_nlist(const KParams& kp, const BatchView& bv, int32_t n_cells,
     // rows directly (the same rows the tile builder would give)
     if (lanes)
         launch_nlist_lanes<true>(waves, kp, bv, n, x, x32, cell_xyz, cell_start, rank_tab, offset, index, capacity,
-                                 slab, slab_k, flag, s);
+                                 slab, slab_k, flag, s, gate);
     else
         launch_nlist_pass<true>(waves, kp, bv, n_blocks, n, x, x32, cell_start, rank_tab, offset, index, capacity,
-                                slab, slab_k, flag, s);
+                                slab, slab_k, flag, s, gate);
     return hipGetLastError();
 }
 
@@ -899,7 +910,7 @@ hipError_t launch_nlist_check(int32_t n, const int32_t* offset, int64_t capacity
                               hipStream_t s)
 {
     if (!status) return hipSuccess;
-    hipLaunchKernelGGL(k_nlist_check, dim3(1), dim3(64), 0, s, n, offset, capacity, status);
+    hipLaunchKernelGGL(k_nlist_check, dim3(1), dim3(64), 0, s, n, offset, capacity, status, nullptr);
     return hipGetLastError();
 }
 

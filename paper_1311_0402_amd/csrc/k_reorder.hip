@@ -12,16 +12,17 @@
 
 namespace dpd {
 
-__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t count, int32_t value)
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t count, int32_t value, Gate gate)
 {
+    if (gated_off(gate)) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) p[i] = value;
 }
 
-hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t s)
+hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t s, Gate gate)
 {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_i32, dim3(ceil_div(count, kBlock)), dim3(kBlock), 0, s, p, count, value);
+    hipLaunchKernelGGL(k_fill_i32, dim3(ceil_div(count, kBlock)), dim3(kBlock), 0, s, p, count, value, gate);
     return hipGetLastError();
 }
 
@@ -80,8 +81,10 @@ template <bool kB>
 __global__ __launch_bounds__(kBlock) void k_bin(KParams kp, BatchView bv, int32_t n, const double* __restrict__ x,
                                                 const int32_t* __restrict__ rank_tab,
                                                 int32_t* __restrict__ key, int32_t* __restrict__ slot,
-                                                uint32_t* __restrict__ cxyz, int32_t* __restrict__ counts)
+                                                uint32_t* __restrict__ cxyz, int32_t* __restrict__ counts,
+                                                Gate gate)
 {
+    if (gated_off(gate)) return;
     const int32_t i = blockIdx.x * kBlock + threadIdx.x;
     const bool live = i < n;
     int32_t r = -1;
@@ -105,15 +108,15 @@ __global__ __launch_bounds__(kBlock) void k_bin(KParams kp, BatchView bv, int32_
 }
 
 hipError_t launch_bin(const KParams& kp, const BatchView& bv, int32_t n, const double* x, const int32_t* rank_tab,
-                      int32_t* key, int32_t* slot, uint32_t* cxyz, int32_t* counts, hipStream_t s)
+                      int32_t* key, int32_t* slot, uint32_t* cxyz, int32_t* counts, hipStream_t s, Gate gate)
 {
     if (n <= 0) return hipSuccess;
     if (bv.kps)
         hipLaunchKernelGGL(k_bin<true>, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, kp, bv, n, x, rank_tab, key,
-                           slot, cxyz, counts);
+                           slot, cxyz, counts, gate);
     else
         hipLaunchKernelGGL(k_bin<false>, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, kp, bv, n, x, rank_tab, key,
-                           slot, cxyz, counts);
+                           slot, cxyz, counts, gate);
     return hipGetLastError();
 }
 
@@ -155,8 +158,9 @@ __device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t* s_wave, i
 }
 
 __global__ __launch_bounds__(kBlock) void k_scan_tiles(const int32_t* __restrict__ data, int64_t count,
-                                                       int32_t* __restrict__ partials)
+                                                       int32_t* __restrict__ partials, Gate gate)
 {
+    if (gated_off(gate)) return;
     __shared__ int32_t s_wave[kBlock / kWave];
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
     int32_t sum = 0;
@@ -169,8 +173,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const int32_t* __restrict
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(1024) void k_scan_partials(int32_t* __restrict__ partials, int32_t n_tiles)
+__global__ __launch_bounds__(1024) void k_scan_partials(int32_t* __restrict__ partials, int32_t n_tiles, Gate gate)
 {
+    if (gated_off(gate)) return;
     __shared__ int32_t s_wave[1024 / kWave];
     int32_t carry = 0;
     for (int32_t base = 0; base < n_tiles; base += 1024) {
@@ -184,8 +189,9 @@ __global__ __launch_bounds__(1024) void k_scan_partials(int32_t* __restrict__ pa
 }
 
 __global__ __launch_bounds__(kBlock) void k_scan_apply(int32_t* __restrict__ data, int64_t count,
-                                                       const int32_t* __restrict__ partials)
+                                                       const int32_t* __restrict__ partials, Gate gate)
 {
+    if (gated_off(gate)) return;
     constexpr int kItems = kScanTile / kBlock;   // 16
     // +1 padding per 16 items so the per-thread runs do not share banks
     __shared__ int32_t s_tile[kScanTile + kScanTile / kItems];
@@ -216,13 +222,13 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(int32_t* __restrict__ dat
     }
 }
 
-hipError_t launch_scan(int32_t* data, int64_t count, int32_t* partials, hipStream_t s)
+hipError_t launch_scan(int32_t* data, int64_t count, int32_t* partials, hipStream_t s, Gate gate)
 {
     if (count <= 0) return hipSuccess;
     const int tiles = ceil_div(count, kScanTile);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(kBlock), 0, s, data, count, partials);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials, tiles);
-    hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(kBlock), 0, s, data, count, partials);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(kBlock), 0, s, data, count, partials, gate);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials, tiles, gate);
+    hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(kBlock), 0, s, data, count, partials, gate);
     return hipGetLastError();
 }
 
@@ -235,8 +241,9 @@ __global__ __launch_bounds__(kBlock) void k_place(int32_t n, const int32_t* __re
                                                   const int32_t* __restrict__ cell_start,
                                                   const uint32_t* __restrict__ tag,
                                                   uint32_t* __restrict__ tmp_tag, int32_t* __restrict__ tmp_src,
-                                                  int32_t* __restrict__ tmp_key)
+                                                  int32_t* __restrict__ tmp_key, Gate gate)
 {
+    if (gated_off(gate)) return;
     const int32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const int32_t k = key[i];
@@ -247,11 +254,12 @@ __global__ __launch_bounds__(kBlock) void k_place(int32_t n, const int32_t* __re
 }
 
 hipError_t launch_place(int32_t n, const int32_t* key, const int32_t* slot, const int32_t* cell_start,
-                        const uint32_t* tag, uint32_t* tmp_tag, int32_t* tmp_src, int32_t* tmp_key, hipStream_t s)
+                        const uint32_t* tag, uint32_t* tmp_tag, int32_t* tmp_src, int32_t* tmp_key, hipStream_t s,
+                        Gate gate)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_place, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, n, key, slot, cell_start,
-                       tag, tmp_tag, tmp_src, tmp_key);
+                       tag, tmp_tag, tmp_src, tmp_key, gate);
     return hipGetLastError();
 }
 
@@ -292,6 +300,10 @@ __device__ __forceinline__ void finalize_one(const KParams& P, int32_t n, int32_
     for (int k = 0; k < 3; ++k) {
         g.x_out[k * N + dst] = xs[k];
         g.v_out[k * N + dst] = vs[k];
+    }
+    if (g.xref) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) g.xref[k * N + dst] = xs[k];
     }
     if (g.vt_in) {
 #pragma unroll
@@ -334,8 +346,9 @@ __global__ __launch_bounds__(kBlock) void k_finalize(KParams kp, BatchView bv, i
                                                      const int32_t* __restrict__ tmp_key,
                                                      const int32_t* __restrict__ cell_start,
                                                      const uint32_t* __restrict__ tmp_tag,
-                                                     const int32_t* __restrict__ tmp_src, GatherArgs g)
+                                                     const int32_t* __restrict__ tmp_src, GatherArgs g, Gate gate)
 {
+    if (gated_off(gate)) return;
     const int32_t p = blockIdx.x * kBlock + threadIdx.x;
     if (p >= n) return;
     // a particle never leaves its system, so position p and its source share it
@@ -370,10 +383,15 @@ __global__ __launch_bounds__(kBlock) void k_pidx_init(int32_t n, const uint32_t*
 __global__ __launch_bounds__(kBlock) void k_pidx_update(int32_t n, const int32_t* __restrict__ perm,
                                                         const int32_t* __restrict__ inv,
                                                         const int32_t* __restrict__ pidx_old,
-                                                        int32_t* __restrict__ pidx_new)
+                                                        int32_t* __restrict__ pidx_new, Gate gate)
 {
     const int32_t d = blockIdx.x * kBlock + threadIdx.x;
     if (d >= n) return;
+    if (gated_off(gate)) {
+        // no reorder this step: the indices carry over unchanged
+        reinterpret_cast<int2*>(pidx_new)[d] = reinterpret_cast<const int2*>(pidx_old)[d];
+        return;
+    }
     const int32_t src = perm[d];
     // a particle's two partners as one 8-byte access (the arrays are
     // 8-byte aligned workspace)
@@ -397,25 +415,61 @@ hipError_t launch_pidx_init(const KParams& kp, int32_t n, const uint32_t* tag, c
 }
 
 hipError_t launch_pidx_update(int32_t n, const int32_t* perm, const int32_t* inv, const int32_t* pidx_old,
-                              int32_t* pidx_new, hipStream_t s)
+                              int32_t* pidx_new, hipStream_t s, Gate gate)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pidx_update, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, n, perm, inv, pidx_old,
-                       pidx_new);
+                       pidx_new, gate);
+    return hipGetLastError();
+}
+
+namespace {
+
+__global__ __launch_bounds__(kBlock) void k_precopy(int32_t n, const double* __restrict__ x,
+                                                    const double* __restrict__ v, const double* __restrict__ vt,
+                                                    const uint32_t* __restrict__ tag,
+                                                    const uint8_t* __restrict__ type, double* __restrict__ bx,
+                                                    double* __restrict__ bv, double* __restrict__ bvt,
+                                                    uint32_t* __restrict__ btag, uint8_t* __restrict__ btype,
+                                                    Gate gate)
+{
+    if (gated_off(gate)) return;
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int64_t N = n;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        bx[k * N + i] = x[k * N + i];
+        bv[k * N + i] = v[k * N + i];
+        if (vt) bvt[k * N + i] = vt[k * N + i];
+    }
+    btag[i] = tag[i];
+    btype[i] = type[i];
+}
+
+}  // namespace
+
+hipError_t launch_precopy(int32_t n, const double* x, const double* v, const double* vt, const uint32_t* tag,
+                          const uint8_t* type, double* bx, double* bv, double* bvt, uint32_t* btag,
+                          uint8_t* btype, hipStream_t s, Gate gate)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_precopy, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, n, x, v, vt, tag, type, bx, bv,
+                       bvt, btag, btype, gate);
     return hipGetLastError();
 }
 
 hipError_t launch_finalize(const KParams& kp, const BatchView& bv, int32_t n, const int32_t* tmp_key,
                            const int32_t* cell_start, const uint32_t* tmp_tag, const int32_t* tmp_src,
-                           const GatherArgs& g, hipStream_t s)
+                           const GatherArgs& g, hipStream_t s, Gate gate)
 {
     if (n <= 0) return hipSuccess;
     if (bv.kps)
         hipLaunchKernelGGL(k_finalize<true>, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, kp, bv, n, tmp_key,
-                           cell_start, tmp_tag, tmp_src, g);
+                           cell_start, tmp_tag, tmp_src, g, gate);
     else
         hipLaunchKernelGGL(k_finalize<false>, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, kp, bv, n, tmp_key,
-                           cell_start, tmp_tag, tmp_src, g);
+                           cell_start, tmp_tag, tmp_src, g, gate);
     return hipGetLastError();
 }
 

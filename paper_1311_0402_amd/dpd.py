@@ -279,6 +279,49 @@ def dpd_step_backward(params: Params, st: State, cells: Cells, nl: NList, step: 
           "dpd_step_backward")
 
 
+# ------------------------------------------------- border exchange (Alg 6) --
+
+def border_workspace(n: int, device="cuda") -> torch.Tensor:
+    nb = lib().dpd_border_workspace_bytes(int(n))
+    if nb == 0:
+        raise DPDError(_abi.DPD_EINVAL, "dpd_border_workspace_bytes")
+    return torch.empty(int(nb), dtype=torch.uint8, device=device)
+
+
+def ghost_records(capacity: int, device="cuda") -> torch.Tensor:
+    """Device buffer of `capacity` dpd_ghost records (56 bytes each), as
+    float64 words [capacity, 7]: x, y, z, vx, vy, vz, (tag, type) bits."""
+    assert _abi.GHOST_BYTES == 56
+    return torch.empty((max(int(capacity), 1), 7), dtype=torch.float64, device=device)
+
+
+def dpd_border_lists(st: State, lo, hi, width: float, face_mask: int, send_offset: torch.Tensor,
+                     send_index: torch.Tensor, status: torch.Tensor, ws: torch.Tensor, stream=None) -> None:
+    s = st.c()
+    lo_c = (C.c_double * 3)(*[float(v) for v in lo])
+    hi_c = (C.c_double * 3)(*[float(v) for v in hi])
+    check(lib().dpd_border_lists(C.byref(s), lo_c, hi_c, float(width), int(face_mask), _ptr(send_offset),
+                                 _ptr(send_index), int(send_index.numel()), _ptr(status), _ptr(ws), ws.numel(),
+                                 _stream(stream)), "dpd_border_lists")
+
+
+def dpd_border_pack(st: State, send_offset: torch.Tensor, send_index: torch.Tensor, shift, records: torch.Tensor,
+                    status: torch.Tensor, stream=None) -> None:
+    s = st.c()
+    sh = np.ascontiguousarray(shift, dtype=np.float64).reshape(18)
+    sh_c = (C.c_double * 18)(*[float(v) for v in sh])
+    cap = min(int(send_index.numel()), int(records.shape[0]))
+    check(lib().dpd_border_pack(C.byref(s), _ptr(send_offset), _ptr(send_index), cap, sh_c, _ptr(records),
+                                _ptr(status), _stream(stream)), "dpd_border_pack")
+
+
+def dpd_border_unpack(records: torch.Tensor, d_count: torch.Tensor, dst: State, first: int, status: torch.Tensor,
+                      stream=None) -> None:
+    s = dst.c()
+    check(lib().dpd_border_unpack(_ptr(records), _ptr(d_count), int(records.shape[0]), C.byref(s), int(first),
+                                  _ptr(status), _stream(stream)), "dpd_border_unpack")
+
+
 # ------------------------------------------------------------------ System --
 
 class System:
@@ -372,6 +415,35 @@ class System:
         dpd_step(self.params, self.precision, self.state, n_steps, self.d_step, self.cells, self.nlist,
                  self.status, self.ws, reductions=reductions,
                  x32=self.x32, v32=self.v32 if mixed else None, phase_events=phase_events)
+
+    def advance(self, n_steps: int, reductions: Optional[torch.Tensor] = None, slack: float = 1.25,
+                max_grow: int = 4) -> int:
+        """``step`` with recovery from a neighbour-list overflow inside the
+        call: the state entering the call is kept on the device; when the
+        status word reports an overflow after the call, the state is put
+        back, the list grown to the last build's size times ``slack`` (or
+        the capacity times ``slack`` when that is larger) and the call run
+        again, so the result equals an uninterrupted run with a large
+        enough list bit for bit.  The status word is cleared before each
+        attempt.  Synchronises once per attempt.  Returns the number of
+        times the list was grown."""
+        st = self.state
+        snap = (st.x.clone(), st.v.clone(), st.f.clone(), st.tag.clone(), st.type.clone(),
+                self.d_step.clone())
+        for grown in range(max_grow + 1):
+            self.status.zero_()
+            self.step(n_steps, reductions=reductions)
+            flags = int(self.status.item())
+            if not flags & _abi.STATUS_NLIST_OVERFLOW:
+                return grown
+            if grown == max_grow:
+                break
+            for dst, src in zip((st.x, st.v, st.f, st.tag, st.type, self.d_step), snap):
+                dst.copy_(src)
+            need = int(self.nlist.offset[self.n].item())
+            cap = int(max(need, self.nlist.capacity) * slack) + 1
+            self.nlist = NList.empty(self.n, cap, self.device)
+        raise DPDError(_abi.DPD_ECAPACITY, f"neighbour list still overflows after growing {max_grow} times")
 
     def check_status(self) -> int:
         st = int(self.status.item())

@@ -270,6 +270,43 @@ def test_steps_in_one_call_equal_single_step_calls(precision):
         np.testing.assert_array_equal(u, w)
 
 
+@pytest.mark.parametrize("precision", [P.FP64, P.MIXED])
+def test_step_call_forces_match_oracle_bonded(precision):
+    """The path a multi-step dpd_step call runs (list rows read from the
+    builder's slab with stencil-coded entries, FP64 pairs inside a chunk
+    evaluated once, bond partners carried from reorder to reorder instead of
+    looked up by tag), on the bonded amphiphile system: after one 12-step
+    call the returned forces equal the oracle's forces at the final state
+    (x, v_h = v - dt/2 F, step 12), FP64 within 1e-12 S_i per particle, the
+    mixed form within 1e-5 of |F| (global L2 and 99.99th percentile)."""
+    s = di.amphiphile(n=6000, seed=23)
+    sim = _sorted_system(s, precision)
+    red = torch.zeros((12, 8), dtype=torch.float64, device="cuda")
+    sim.step(12, reductions=red)
+    torch.cuda.synchronize()
+    assert sim.check_status() == 0
+    x, v, f, tag, typ = sim.host_state()
+    vh = v - 0.5 * s.dt * f
+    f_ref, pe_ref, npair_ref, scale = oracle.forces(s, x, vh, tag, typ, 12, with_scale=True)
+    if precision == P.FP64:
+        _check_fp64(f, f_ref, scale)
+    else:
+        rel = np.linalg.norm(f - f_ref) / np.linalg.norm(f_ref)
+        assert rel <= MIXED_TOL, rel
+        d = np.linalg.norm(f - f_ref, axis=0)
+        rms = np.sqrt(np.mean(np.sum(f_ref**2, axis=0)))
+        assert np.percentile(d / rms, 99.99) <= MIXED_TOL
+    # the last step's statistics: pair count and potential energy
+    r = red.cpu().numpy()[-1]
+    assert r[5] == npair_ref.sum() / 2
+    np.testing.assert_allclose(r[4], pe_ref.sum(), rtol=1e-12 if precision == P.FP64 else 1e-5)
+    # the CSR list the call leaves (its last step's rows) is the oracle's
+    off, idx = sim.host_nlist()
+    off_ref, idx_ref = oracle.neighbors(x, s.box, s.r_c)
+    np.testing.assert_array_equal(off, off_ref)
+    np.testing.assert_array_equal(idx, idx_ref)
+
+
 def test_step_mixed_tracks_fp64():
     s = di.small_fluid(4)
     a = _sorted_system(s, precision=P.MIXED)

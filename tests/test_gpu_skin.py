@@ -1,0 +1,156 @@
+"""Verlet skin: neighbour lists at r_list = r_c + skin, and dpd_step calls
+that rebuild the cell and neighbour lists only when some particle has moved
+more than skin / 2 since the last rebuild (the paper's lists are built with
+a skin and rebuilt every few steps, Sec. 3.3 and 4.3).
+
+Bars as elsewhere: rows bit-exact against the oracle's brute-force rows at
+r_list; forces of a call's final state against the oracle's forces there
+(pairs beyond r_c contribute nothing), FP64 within 1e-12 S_i per particle,
+the mixed form within 1e-5 of |F|."""
+import numpy as np
+import pytest
+
+import dpd_inputs as di
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+P = pytest.importorskip("paper_1311_0402_amd")
+
+SKIN = 0.3
+
+
+def _systems():
+    return {
+        "fluid3000": di.small_fluid(31),
+        "ragged": di.uniform_fluid(2717, (9.3, 7.6, 12.9), 32),
+        "amphiphile": di.amphiphile(n=6000, seed=33),
+    }
+
+
+def _loaded(s, precision=P.FP64, skin=SKIN):
+    sim = P.System(P.Params.like(s, skin=skin), s.n, precision)
+    sim.load(s.x, s.v, s.tag, s.type, step=0)
+    torch.cuda.synchronize()
+    assert sim.check_status() == 0
+    return sim
+
+
+def _check_forces(f, f_ref, scale, precision):
+    if precision == P.FP64:
+        d = np.linalg.norm(f - f_ref, axis=0)
+        assert np.all(d <= 1e-12 * scale), float(np.max(d / scale))
+    else:
+        rel = np.linalg.norm(f - f_ref) / np.linalg.norm(f_ref)
+        assert rel <= 1e-5, rel
+
+
+@pytest.mark.parametrize("name", list(_systems()))
+def test_skin_rows_bitexact(name):
+    s = _systems()[name]
+    sim = _loaded(s)
+    assert P.cell_grid(sim.params) == tuple(oracle.cell_grid(s.box, s.r_c + SKIN))
+    x = sim.host_state()[0]
+    off, idx = sim.host_nlist()
+    off_ref, idx_ref = oracle.neighbors(x, s.box, s.r_c + SKIN)
+    np.testing.assert_array_equal(off, off_ref)
+    np.testing.assert_array_equal(idx, idx_ref)
+
+
+@pytest.mark.parametrize("name", list(_systems()))
+@pytest.mark.parametrize("precision", [P.FP64, P.MIXED])
+def test_skin_forces_match_oracle(name, precision):
+    s = _systems()[name]
+    sim = _loaded(s, precision)
+    x, v, f, tag, typ = sim.host_state()
+    f_ref, _, _, scale = oracle.forces(s, x, v, tag, typ, 0, skin=SKIN, with_scale=True)
+    _check_forces(f, f_ref, scale, precision)
+
+
+@pytest.mark.parametrize("precision", [P.FP64, P.MIXED])
+def test_skin_step_call_rebuilds_on_displacement(precision):
+    """12 steps in one call on the bonded amphiphile system: the first step
+    rebuilds, later steps rebuild only sometimes; the forces of the final
+    state match the oracle; the list the call leaves (the last rebuild's)
+    holds every pair now inside r_c, each row strictly ascending."""
+    s = di.amphiphile(n=6000, seed=34)
+    sim = _loaded(s, precision)
+    red = torch.zeros((12, 8), dtype=torch.float64, device="cuda")
+    sim.step(12, reductions=red)
+    torch.cuda.synchronize()
+    assert sim.check_status() == 0
+    r = red.cpu().numpy()
+    rebuilt = r[:, 7]
+    assert set(np.unique(rebuilt)) <= {0.0, 1.0}
+    assert rebuilt[0] == 1.0
+    assert 2 <= rebuilt.sum() <= 10, rebuilt
+    x, v, f, tag, typ = sim.host_state()
+    vh = v - 0.5 * s.dt * f
+    f_ref, pe_ref, npair_ref, scale = oracle.forces(s, x, vh, tag, typ, 12, skin=SKIN, with_scale=True)
+    _check_forces(f, f_ref, scale, precision)
+    pairs = npair_ref.sum() / 2
+    assert abs(r[-1, 5] - pairs) <= (0 if precision == P.FP64 else 2)
+    off, idx = sim.host_nlist()
+    off_rc, idx_rc = oracle.neighbors(x, s.box, s.r_c)
+    for i in range(s.n):
+        row = idx[off[i]:off[i + 1]]
+        assert np.all(np.diff(row) > 0)
+        assert np.isin(idx_rc[off_rc[i]:off_rc[i + 1]], row).all(), i
+
+
+def _frozen_fluid(fast=None):
+    s = di.uniform_fluid(1500, (8.0, 8.0, 8.0), 35, a=0.0, gamma=0.0, sigma=0.0)
+    s.v = np.zeros_like(s.v)
+    if fast is not None:
+        s.v[:, 5] = fast
+    return s
+
+
+def test_skin_no_motion_rebuilds_once():
+    s = _frozen_fluid()
+    sim = _loaded(s)
+    red = torch.zeros((6, 8), dtype=torch.float64, device="cuda")
+    sim.step(6, reductions=red)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(red.cpu().numpy()[:, 7], [1, 0, 0, 0, 0, 0])
+
+
+@pytest.mark.parametrize("precision", [P.FP64, P.MIXED])
+def test_skin_fast_particle_rebuilds_every_step(precision):
+    """Forces vanish (a = gamma = sigma = 0): one particle moving 0.25 per
+    step (more than skin / 2) forces a rebuild at every step; every position
+    equals ballistic motion computed by the oracle's integrator."""
+    s = _frozen_fluid(fast=(25.0, -10.0, 5.0))
+    sim = _loaded(s, precision)
+    red = torch.zeros((6, 8), dtype=torch.float64, device="cuda")
+    sim.step(6, reductions=red)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(red.cpu().numpy()[:, 7], np.ones(6))
+    x, v, f, tag, typ = sim.host_state()
+    xo, vo, fo = s.x, s.v, np.zeros_like(s.x)
+    for k in range(1, 7):
+        xo, vo, fo, _ = oracle.step(s, xo, vo, fo, s.tag, s.type, k, skin=SKIN)
+    order = np.argsort(tag)
+    np.testing.assert_array_equal(x[:, order], xo)
+
+
+@pytest.mark.parametrize("precision", [P.FP64, P.MIXED])
+def test_skin_call_is_deterministic_and_tracks_the_oracle(precision):
+    """Two identical calls give bitwise the same state; the FP64 trajectory
+    stays within round-off of the oracle's own 12-step run (which rebuilds
+    every step)."""
+    s = di.small_fluid(36)
+    a = _loaded(s, precision)
+    b = _loaded(s, precision)
+    a.step(12)
+    b.step(12)
+    torch.cuda.synchronize()
+    for u, w in zip(a.host_state(), b.host_state()):
+        np.testing.assert_array_equal(u, w)
+    if precision == P.FP64:
+        x, v, f, tag, typ = a.host_state()
+        f0, _, _ = oracle.forces(s, s.x, s.v, s.tag, s.type, 0)
+        xo, vo, fo, _, _ = oracle.run(s, s.x, s.v, f0, s.tag, s.type, 0, 12, use_cells=False, skin=SKIN)
+        order = np.argsort(tag)
+        assert np.max(np.abs(x[:, order] - xo)) < 1e-10
+        assert np.max(np.abs(v[:, order] - vo)) < 1e-8

@@ -556,3 +556,64 @@ def test_force_matching_gradient_finite_differences(s_exp, h, rtol):
     dv = rng.standard_normal(s.v.shape)
     fd = (loss(v=s.v + h * dv) - loss(v=s.v - h * dv)) / (2 * h)
     np.testing.assert_allclose(np.sum(gv * dv), fd, rtol=rtol)
+
+
+# ------------------------------------------------ border exchange (Alg 6) --
+
+@pytest.mark.parametrize("box,n,width", [((7.0, 6.0, 8.0), 1000, 1.0), ((5.0, 9.5, 6.25), 900, 1.3)])
+def test_staged_halo_reproduces_periodic_neighbours(box, n, width):
+    """The border lists and ghost records of the three-stage exchange on one
+    brick spanning the periodic box (x faces, then y faces over owned + x
+    ghosts, then z faces over all): every periodic neighbour pair of an
+    owned particle (scipy's periodic k-d tree) appears exactly once among
+    the owned + ghost particles at plain Euclidean distance (a non-periodic
+    k-d tree), and no other pair does.  A wrong band side, a wrong shift
+    sign or a missing stage loses or duplicates pairs."""
+    from scipy.spatial import cKDTree
+    s = di.uniform_fluid(n, box, 77)
+    X, V, T, Y, stages = oracle.staged_halo(s.x, s.v, s.tag, s.type, s.box, width)
+    assert X.shape[1] > n
+    # positions of the ghosts lie within `width` outside the box, no farther
+    lo = -width * np.ones(3)[:, None]
+    hi = np.asarray(box)[:, None] + width
+    assert np.all(X >= lo - 1e-12) and np.all(X < hi + 1e-12)
+    per = cKDTree(s.x.T, boxsize=np.asarray(box))
+    flat = cKDTree(X.T)
+    r = width * (1.0 - 1e-9)          # away from pairs at the radius itself
+    for i in range(n):
+        want = sorted(s.tag[j] for j in per.query_ball_point(s.x[:, i], r) if j != i)
+        got = sorted(T[j] for j in flat.query_ball_point(X[:, i], r) if j != i)
+        assert got == want, i
+    # the velocities and types travel with the copies (tags are the
+    # original indices here)
+    np.testing.assert_array_equal(V, s.v[:, T])
+    np.testing.assert_array_equal(Y, s.type[T])
+    for d, (off, idx) in enumerate(stages):
+        assert np.all(np.diff(off) >= 0)
+        for f in range(6):
+            seg = idx[off[f]:off[f + 1]]
+            assert np.all(np.diff(seg) > 0)                 # ascending
+            if f // 2 != d:
+                assert seg.size == 0                        # only this stage's faces
+
+
+def test_border_lists_band_edges():
+    """Planted positions on the band edges of a sub-brick: a particle exactly
+    at lo + width is not sent through the low face, one exactly at
+    hi - width is sent through the high face, and a particle outside the
+    brick on the low side is sent through the low face only."""
+    lo = np.array([1.0, 2.0, 3.0])
+    hi = np.array([5.0, 6.5, 7.25])
+    w = 0.75
+    x = np.array([[lo[0] + w, hi[0] - w, lo[0] + w - 2 ** -40, 0.5, 3.0],
+                  [4.0, 4.0, 4.0, 4.0, hi[1] - w],
+                  [5.0, 5.0, 5.0, 5.0, 5.0]])
+    off, idx = oracle.border_lists(x, lo, hi, w)
+    lists = [list(idx[off[f]:off[f + 1]]) for f in range(6)]
+    assert lists[0] == [2, 3]
+    assert lists[1] == [1]
+    assert lists[2] == []
+    assert lists[3] == [4]
+    assert lists[4] == [] and lists[5] == []
+    off_x, idx_x = oracle.border_lists(x, lo, hi, w, face_mask=0b000010)
+    assert list(off_x) == [0, 0, 1, 1, 1, 1, 1] and list(idx_x) == [1]
