@@ -364,6 +364,59 @@ int dpd_border_unpack(const dpd_ghost* records, const int32_t* d_count, int64_t 
                       int32_t first, int32_t* d_status, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * The paper's numerics as A/B variants (Sec. 3.5, Algorithms 4 and 5,
+ * Table 3): the TEA hash on per-particle signatures and reduced-branch
+ * logarithm, cosine and power functions, beside the device library the
+ * force kernels call.  Study entry points: the force kernels keep
+ * Philox4x32-10 and the device library.
+ * ------------------------------------------------------------------------- */
+
+typedef enum dpd_math_fn {
+    DPD_FN_LOG = 0,          /* ln a, device library                                */
+    DPD_FN_FASTLOG = 1,      /* ln a (a > 0, normal): exponent from the bits, the
+                                mantissa's log by the atanh power series          */
+    DPD_FN_COS2PI = 2,       /* cos(2 pi a), device library (cospi)                 */
+    DPD_FN_FASTCOS2PI = 3,   /* cos(2 pi a) for a in [0, 1): symmetry folding and
+                                the cos / sin power series on [0, pi/4]           */
+    DPD_FN_POW = 4,          /* a^b, device library                                 */
+    DPD_FN_FASTPOW = 5       /* a^b (a > 0 normal, result normal) as 2^N 2^r with
+                                r = b log2 a - N, |r| <= 1/2                      */
+} dpd_math_fn;
+
+/* out[i] = fn(a[i], b[i]) for i < n (b read by the power functions only,
+ * nullable otherwise); device arrays. */
+int dpd_math_eval(int32_t fn, int64_t n, const double* a, const double* b, double* out, void* stream);
+
+/* One wavefront evaluates a chain of `chain` dependent calls of fn per lane
+ * (each argument an affine map of the previous result); d_cycles (device
+ * int64[1]) receives the shader-clock ticks of the chain, d_sink (device
+ * double[64]) the lanes' last values. */
+int dpd_math_latency(int32_t fn, int32_t chain, int64_t* d_cycles, double* d_sink, void* stream);
+
+/* Per-particle signatures (Sec. 3.5): 16 TEA rounds on (bit-reversed tag,
+ * the leading 11 mantissa bits of v_x, v_y, v_z interleaved, x lowest, the
+ * 33rd bit dropped), keys (seed low, seed high, step low, step high), the
+ * two halves xor-ed.  v: device double[3][n]; sig: device uint32[n]. */
+int dpd_tea_signatures(int32_t n, const uint32_t* tag, const double* v, uint64_t step, uint64_t seed,
+                       uint32_t* sig, void* stream);
+
+/* Pair Gaussians from signatures: 4 TEA rounds on (min, max) of the two
+ * signatures (same keys) give words (w0, w1); xi = sqrt(-2 ln u1)
+ * cos(2 pi u2) with u1 = (w0 + 1/2) 2^-32, u2 = w1 2^-32, evaluated with
+ * DPD_FN_FASTLOG and DPD_FN_FASTCOS2PI.  words (nullable): uint32[2 n]. */
+int dpd_tea_gaussians(int64_t n, const uint32_t* sig_i, const uint32_t* sig_j, uint64_t step, uint64_t seed,
+                      uint32_t* words, double* xi, void* stream);
+
+/* Throughput probe: every thread t < n_tags draws the Gaussians of pairs
+ * (t, t + 1), ..., (t, t + pairs_per_thread) (tags mod n_tags) and writes
+ * their sum to sink[t].  generator 0: Philox4x32-10 and the device
+ * library's log, sqrt and cospi (the FP64 force pass's generator);
+ * generator 1: TEA-4 on sig[] (from dpd_tea_signatures) with the fast
+ * logarithm and cosine. */
+int dpd_gaussian_throughput(int32_t generator, int32_t n_tags, int32_t pairs_per_thread, uint64_t step,
+                            uint64_t seed, const uint32_t* sig, double* sink, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Batched replicas
  *
  * Many independent periodic systems advanced together.  The paper hides

@@ -101,6 +101,10 @@ def _declare(L):
     L.orc_border_lists.restype = C.c_int64
     L.orc_border_pack.argtypes = [C.c_int32, P, P, P, P, P, P, P, P, P, P, P]
     L.orc_border_pack.restype = None
+    L.orc_tea.argtypes = [C.c_int32, P, P]
+    L.orc_tea_sig_inputs.argtypes = [C.c_uint32, C.c_double, C.c_double, C.c_double, P]
+    L.orc_tea_signatures.argtypes = [C.c_int32, P, P, C.c_uint64, C.c_uint64, P]
+    L.orc_tea_xi_batch.argtypes = [C.c_int64, P, P, C.c_uint64, C.c_uint64, P, P]
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -319,6 +323,40 @@ def run(sys_, x, v, f, tag, typ, step0: int, n_steps: int, *, use_cells: bool = 
         raise RuntimeError("orc_run failed")
     prof_mean = None if prof is None else prof / np.maximum(cnt, 1.0)
     return x, v, f, red, prof_mean
+
+
+# ------------------------------------------- TEA generator (A/B study) ----
+
+def tea(rounds: int, v, key):
+    """TEA cycles on the block (v0, v1) with key k[4]."""
+    w = _c(v, np.uint32).copy()
+    lib().orc_tea(int(rounds), _ptr(w), _ptr(_c(key, np.uint32)))
+    return w
+
+
+def tea_sig_inputs(tag: int, vx: float, vy: float, vz: float):
+    out = np.zeros(2, dtype=np.uint32)
+    lib().orc_tea_sig_inputs(int(tag) & 0xFFFFFFFF, float(vx), float(vy), float(vz), _ptr(out))
+    return out
+
+
+def tea_signatures(tag, v, step: int, seed: int):
+    tag = _c(tag, np.uint32)
+    v = _c(v, np.float64)
+    sig = np.empty(tag.shape[0], dtype=np.uint32)
+    lib().orc_tea_signatures(tag.shape[0], _ptr(tag), _ptr(v), int(step), int(seed) & ((1 << 64) - 1), _ptr(sig))
+    return sig
+
+
+def tea_xi(si, sj, step: int, seed: int):
+    """(words uint32[n, 2], xi float64[n]) of TEA-4 on signature pairs."""
+    si = _c(np.atleast_1d(si), np.uint32)
+    sj = _c(np.atleast_1d(sj), np.uint32)
+    n = si.shape[0]
+    w = np.empty((n, 2), dtype=np.uint32)
+    xi = np.empty(n, dtype=np.float64)
+    lib().orc_tea_xi_batch(n, _ptr(si), _ptr(sj), int(step), int(seed) & ((1 << 64) - 1), _ptr(w), _ptr(xi))
+    return w, xi
 
 
 # ------------------------------------------------- border exchange ----

@@ -746,3 +746,87 @@ void orc_border_pack(int32_t n, const double* x, const double* v, const uint32_t
             gtype[r] = type[j];
         }
 }
+
+/* ------------------------------------------------------------------------ */
+/* The paper's alternative pair generator (Sec. 3.5, Algorithm 4), for the  */
+/* A/B study only.  TEA: Wheeler & Needham, "TEA, a tiny encryption         */
+/* algorithm" (Fast Software Encryption, 1994): each cycle adds the golden- */
+/* ratio constant delta = 0x9E3779B9 to a running sum and updates the two   */
+/* halves with shifts by 4 and 5, key words and the sum.  Readings (the     */
+/* paper gives no key and no pair layout): keys (seed low, seed high, step  */
+/* low, step high); a signature hashes (bit-reversed tag, the leading 11    */
+/* mantissa bits of v_x, v_y, v_z interleaved bit by bit, x lowest, the     */
+/* 33rd bit dropped) with 16 cycles and xors the halves; a pair hashes      */
+/* (smaller signature, larger signature) with 4 cycles into two uniforms of */
+/* the same Box-Muller form as orc_xi.                                       */
+/* ------------------------------------------------------------------------ */
+
+void orc_tea(int32_t rounds, uint32_t v[2], const uint32_t k[4])
+{
+    const uint32_t delta = 0x9E3779B9u;
+    uint32_t y = v[0], z = v[1], sum = 0;
+    for (int32_t r = 0; r < rounds; ++r) {
+        sum += delta;
+        y += ((z << 4) + k[0]) ^ (z + sum) ^ ((z >> 5) + k[1]);
+        z += ((y << 4) + k[2]) ^ (y + sum) ^ ((y >> 5) + k[3]);
+    }
+    v[0] = y;
+    v[1] = z;
+}
+
+static void tea_key_of(uint64_t seed, uint64_t step, uint32_t k[4])
+{
+    k[0] = (uint32_t)seed; k[1] = (uint32_t)(seed >> 32);
+    k[2] = (uint32_t)step; k[3] = (uint32_t)(step >> 32);
+}
+
+/* the two words a signature hashes (before the 16 cycles) */
+void orc_tea_sig_inputs(uint32_t tag, double vx, double vy, double vz, uint32_t out[2])
+{
+    uint32_t rev = 0;
+    for (int b = 0; b < 32; ++b) rev |= ((tag >> b) & 1u) << (31 - b);
+    const double comp[3] = { vx, vy, vz };
+    uint32_t m[3];
+    for (int c = 0; c < 3; ++c) {
+        uint64_t bits;
+        memcpy(&bits, &comp[c], sizeof(bits));
+        m[c] = (uint32_t)((bits >> 41) & 0x7FFu);      /* mantissa bits 51 .. 41 */
+    }
+    uint32_t inter = 0;
+    for (int b = 0; b < 11; ++b)
+        for (int c = 0; c < 3; ++c) {
+            const int pos = 3 * b + c;
+            if (pos < 32) inter |= ((m[c] >> b) & 1u) << pos;
+        }
+    out[0] = rev;
+    out[1] = inter;
+}
+
+void orc_tea_signatures(int32_t n, const uint32_t* tag, const double* v, uint64_t step, uint64_t seed,
+                        uint32_t* sig)
+{
+    uint32_t k[4];
+    tea_key_of(seed, step, k);
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t w[2];
+        orc_tea_sig_inputs(tag[i], v[i], v[(int64_t)n + i], v[2 * (int64_t)n + i], w);
+        orc_tea(16, w, k);
+        sig[i] = w[0] ^ w[1];
+    }
+}
+
+void orc_tea_xi_batch(int64_t n, const uint32_t* si, const uint32_t* sj, uint64_t step, uint64_t seed,
+                      uint32_t* words, double* xi)
+{
+    uint32_t k[4];
+    tea_key_of(seed, step, k);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t w[2] = { si[i] < sj[i] ? si[i] : sj[i], si[i] < sj[i] ? sj[i] : si[i] };
+        orc_tea(4, w, k);
+        if (words) { words[2 * i] = w[0]; words[2 * i + 1] = w[1]; }
+        const double u1 = ((double)w[0] + 0.5) / 4294967296.0;
+        const double u2 = (double)w[1] / 4294967296.0;
+        xi[i] = sqrt(-2.0 * log(u1)) * cos(two_pi * u2);
+    }
+}

@@ -26,6 +26,8 @@ STATUS_HALO_OVERFLOW = 8
 FP64 = 0
 MIXED = 1
 
+FN_LOG, FN_FASTLOG, FN_COS2PI, FN_FASTCOS2PI, FN_POW, FN_FASTPOW = range(6)
+
 
 class dpd_params(C.Structure):
     _fields_ = [
@@ -123,6 +125,11 @@ SIGNATURES = {
     "dpd_border_lists": (C.c_int, [PS, P, P, C.c_double, C.c_int32, P, P, C.c_int64, P, P, C.c_size_t, P]),
     "dpd_border_pack": (C.c_int, [PS, P, P, C.c_int64, P, P, P, P]),
     "dpd_border_unpack": (C.c_int, [P, P, C.c_int64, PS, C.c_int32, P, P]),
+    "dpd_math_eval": (C.c_int, [C.c_int32, C.c_int64, P, P, P, P]),
+    "dpd_math_latency": (C.c_int, [C.c_int32, C.c_int32, P, P, P]),
+    "dpd_tea_signatures": (C.c_int, [C.c_int32, P, P, C.c_uint64, C.c_uint64, P, P]),
+    "dpd_tea_gaussians": (C.c_int, [C.c_int64, P, P, C.c_uint64, C.c_uint64, P, P, P]),
+    "dpd_gaussian_throughput": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.c_uint64, P, P, P]),
     "dpd_batch_table_bytes": (C.c_size_t, [C.c_int32, C.c_int64]),
     "dpd_batch_create": (C.c_int, [PP, C.c_int32, P, P, C.c_size_t, P, C.POINTER(C.c_void_p)]),
     "dpd_batch_destroy": (None, [P]),

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdpd.so")
 SOURCES = ["dpd_api.hip", "k_reorder.hip", "k_nlist.hip", "k_force.hip", "k_integrate.hip",
-           "k_adjoint.hip", "k_border.hip"]
+           "k_adjoint.hip", "k_border.hip", "k_numerics.hip"]
 ARCH = "gfx950"
 
 

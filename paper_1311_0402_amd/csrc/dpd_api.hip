@@ -883,6 +883,55 @@ int dpd_border_unpack(const dpd_ghost* records, const int32_t* d_count, int64_t 
     return DPD_OK;
 }
 
+int dpd_math_eval(int32_t fn, int64_t n, const double* a, const double* b, double* out, void* stream)
+{
+    if (fn < DPD_FN_LOG || fn > DPD_FN_FASTPOW) return fail(DPD_EINVAL, "unknown function %d", fn);
+    if (n < 0) return fail(DPD_EINVAL, "n must be >= 0");
+    if (n > 0 && (!a || !out)) return fail(DPD_EINVAL, "a / out is NULL");
+    if (n > 0 && (fn == DPD_FN_POW || fn == DPD_FN_FASTPOW) && !b) return fail(DPD_EINVAL, "b is NULL");
+    DPD_TRY(launch_numerics_eval(fn, n, a, (fn == DPD_FN_POW || fn == DPD_FN_FASTPOW) ? b : nullptr, out,
+                                 as_stream(stream)), "math eval");
+    return DPD_OK;
+}
+
+int dpd_math_latency(int32_t fn, int32_t chain, int64_t* d_cycles, double* d_sink, void* stream)
+{
+    if (fn < DPD_FN_LOG || fn > DPD_FN_FASTPOW) return fail(DPD_EINVAL, "unknown function %d", fn);
+    if (chain < 1) return fail(DPD_EINVAL, "chain must be >= 1");
+    if (!d_cycles || !d_sink) return fail(DPD_EINVAL, "d_cycles / d_sink is NULL");
+    DPD_TRY(launch_numerics_latency(fn, chain, d_cycles, d_sink, as_stream(stream)), "math latency");
+    return DPD_OK;
+}
+
+int dpd_tea_signatures(int32_t n, const uint32_t* tag, const double* v, uint64_t step, uint64_t seed,
+                       uint32_t* sig, void* stream)
+{
+    if (n < 0) return fail(DPD_EINVAL, "n must be >= 0");
+    if (n > 0 && (!tag || !v || !sig)) return fail(DPD_EINVAL, "tag / v / sig is NULL");
+    DPD_TRY(launch_signatures(n, tag, v, step, seed, sig, as_stream(stream)), "signatures");
+    return DPD_OK;
+}
+
+int dpd_tea_gaussians(int64_t n, const uint32_t* sig_i, const uint32_t* sig_j, uint64_t step, uint64_t seed,
+                      uint32_t* words, double* xi, void* stream)
+{
+    if (n < 0) return fail(DPD_EINVAL, "n must be >= 0");
+    if (n > 0 && (!sig_i || !sig_j || !xi)) return fail(DPD_EINVAL, "sig_i / sig_j / xi is NULL");
+    DPD_TRY(launch_tea_gauss(n, sig_i, sig_j, step, seed, words, xi, as_stream(stream)), "TEA gaussians");
+    return DPD_OK;
+}
+
+int dpd_gaussian_throughput(int32_t generator, int32_t n_tags, int32_t pairs_per_thread, uint64_t step,
+                            uint64_t seed, const uint32_t* sig, double* sink, void* stream)
+{
+    if (generator != 0 && generator != 1) return fail(DPD_EINVAL, "generator must be 0 or 1");
+    if (n_tags < 0 || pairs_per_thread < 0) return fail(DPD_EINVAL, "sizes must be >= 0");
+    if (n_tags > 0 && (!sink || (generator == 1 && !sig))) return fail(DPD_EINVAL, "sink / sig is NULL");
+    DPD_TRY(launch_gauss_throughput(generator, n_tags, pairs_per_thread, step, seed, sig, sink, as_stream(stream)),
+            "gaussian throughput");
+    return DPD_OK;
+}
+
 size_t dpd_batch_table_bytes(int32_t n_sys, int64_t n_total)
 {
     if (n_sys < 1 || n_sys > 65535 || n_total < n_sys || n_total >= ((int64_t)1 << 31)) return 0;

@@ -244,6 +244,16 @@ hipError_t launch_border_unpack(const dpd_ghost* in, const int32_t* d_count, int
                                 int32_t first, double* x, double* v, uint32_t* tag, uint8_t* type, int32_t* status,
                                 hipStream_t s);
 
+// ---- the paper's numerics as A/B variants (k_numerics.hip) ----
+hipError_t launch_numerics_eval(int fn, int64_t n, const double* a, const double* b, double* out, hipStream_t s);
+hipError_t launch_numerics_latency(int fn, int32_t chain, int64_t* cycles, double* sink, hipStream_t s);
+hipError_t launch_signatures(int32_t n, const uint32_t* tag, const double* v, uint64_t step, uint64_t seed,
+                             uint32_t* sig, hipStream_t s);
+hipError_t launch_tea_gauss(int64_t n, const uint32_t* si, const uint32_t* sj, uint64_t step, uint64_t seed,
+                            uint32_t* w, double* xi, hipStream_t s);
+hipError_t launch_gauss_throughput(int gen, int32_t n_tags, int32_t pairs_per_thread, uint64_t step, uint64_t seed,
+                                   const uint32_t* sig, double* sink, hipStream_t s);
+
 // ---- adjoint (k_adjoint.hip) ----
 struct BackwardArgs {
     int32_t n;

@@ -322,6 +322,47 @@ def dpd_border_unpack(records: torch.Tensor, d_count: torch.Tensor, dst: State, 
                                   _ptr(status), _stream(stream)), "dpd_border_unpack")
 
 
+# ------------------------------------- the paper's numerics (A/B study) --
+
+def math_eval(fn: int, a: torch.Tensor, b: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    out = torch.empty_like(a)
+    check(lib().dpd_math_eval(int(fn), int(a.numel()), _ptr(a), _ptr(b), _ptr(out), _stream(stream)),
+          "dpd_math_eval")
+    return out
+
+
+def math_latency(fn: int, chain: int, stream=None) -> int:
+    """Shader-clock ticks of one wave's chain of `chain` dependent calls (synchronises)."""
+    cyc = torch.zeros(1, dtype=torch.int64, device="cuda")
+    sink = torch.empty(64, dtype=torch.float64, device="cuda")
+    check(lib().dpd_math_latency(int(fn), int(chain), _ptr(cyc), _ptr(sink), _stream(stream)), "dpd_math_latency")
+    return int(cyc.item())
+
+
+def tea_signatures(tag: torch.Tensor, v: torch.Tensor, step: int, seed: int, stream=None) -> torch.Tensor:
+    n = int(tag.numel())
+    sig = torch.empty(max(n, 1), dtype=torch.int32, device=tag.device)
+    check(lib().dpd_tea_signatures(n, _ptr(tag), _ptr(v), int(step), int(seed) & ((1 << 64) - 1), _ptr(sig),
+                                   _stream(stream)), "dpd_tea_signatures")
+    return sig[:n]
+
+
+def tea_gaussians(sig_i: torch.Tensor, sig_j: torch.Tensor, step: int, seed: int, stream=None):
+    n = int(sig_i.numel())
+    words = torch.empty((max(n, 1), 2), dtype=torch.int32, device=sig_i.device)
+    xi = torch.empty(max(n, 1), dtype=torch.float64, device=sig_i.device)
+    check(lib().dpd_tea_gaussians(n, _ptr(sig_i), _ptr(sig_j), int(step), int(seed) & ((1 << 64) - 1),
+                                  _ptr(words), _ptr(xi), _stream(stream)), "dpd_tea_gaussians")
+    return words[:n], xi[:n]
+
+
+def gaussian_throughput(generator: int, n_tags: int, pairs_per_thread: int, step: int, seed: int,
+                        sig: Optional[torch.Tensor], sink: torch.Tensor, stream=None) -> None:
+    check(lib().dpd_gaussian_throughput(int(generator), int(n_tags), int(pairs_per_thread), int(step),
+                                        int(seed) & ((1 << 64) - 1), _ptr(sig), _ptr(sink), _stream(stream)),
+          "dpd_gaussian_throughput")
+
+
 # ------------------------------------------------------------------ System --
 
 class System:

@@ -617,3 +617,88 @@ def test_border_lists_band_edges():
     assert lists[4] == [] and lists[5] == []
     off_x, idx_x = oracle.border_lists(x, lo, hi, w, face_mask=0b000010)
     assert list(off_x) == [0, 0, 1, 1, 1, 1, 1] and list(idx_x) == [1]
+
+
+# ------------------------------------------- TEA generator (A/B study) --
+
+def _tea_decipher(rounds, v, k):
+    """TEA's inverse, written from the cipher's definition: the cycles
+    undone in reverse order (second half first, the sum counting down)."""
+    m = 0xFFFFFFFF
+    delta = 0x9E3779B9
+    y, z = int(v[0]), int(v[1])
+    s = (delta * rounds) & m
+    for _ in range(rounds):
+        z = (z - ((((y << 4) & m) + k[2]) ^ ((y + s) & m) ^ ((y >> 5) + k[3]))) & m
+        y = (y - ((((z << 4) & m) + k[0]) ^ ((z + s) & m) ^ ((z >> 5) + k[1]))) & m
+        s = (s - delta) & m
+    return y, z
+
+
+@pytest.mark.parametrize("rounds", [1, 4, 16, 32])
+def test_tea_inverts_and_diffuses(rounds):
+    rng = np.random.default_rng(rounds)
+    flips = []
+    for _ in range(300):
+        v = rng.integers(0, 2 ** 32, size=2, dtype=np.uint64).astype(np.uint32)
+        k = [int(t) for t in rng.integers(0, 2 ** 32, size=4, dtype=np.uint64)]
+        w = oracle.tea(rounds, v, np.array(k, dtype=np.uint32))
+        assert _tea_decipher(rounds, w, k) == (int(v[0]), int(v[1]))
+        bit = int(rng.integers(0, 64))
+        v2 = v.copy()
+        v2[bit // 32] ^= np.uint32(1 << (bit % 32))
+        w2 = oracle.tea(rounds, v2, np.array(k, dtype=np.uint32))
+        flips.append(bin(int(w[0] ^ w2[0])).count("1") + bin(int(w[1] ^ w2[1])).count("1"))
+    if rounds >= 4:
+        assert 28 < np.mean(flips) < 36          # half of the 64 output bits
+
+
+def test_tea_signature_inputs():
+    for t in (0, 1, 7, 0x80000000, 0x12345678, 0xFFFFFFFF):
+        rev = int(format(t, "032b")[::-1], 2)
+        assert oracle.tea_sig_inputs(t, 0.0, 0.0, 0.0)[0] == rev
+    # leading mantissa bits: 1.5 = 1.1b (top bit), 1.25 = 1.01b; bit b of
+    # x, y, z goes to 3b, 3b + 1, 3b + 2; bit 10 of z (position 32) is dropped
+    assert oracle.tea_sig_inputs(0, 1.5, 1.0, 1.0)[1] == 1 << 30
+    assert oracle.tea_sig_inputs(0, 1.0, 1.5, 1.0)[1] == 1 << 31
+    assert oracle.tea_sig_inputs(0, 1.0, 1.0, 1.5)[1] == 0
+    assert oracle.tea_sig_inputs(0, 1.0, -1.25, 1.0)[1] == 1 << 28
+    assert oracle.tea_sig_inputs(0, 1.0 + 2.0 ** -52, 1.0, 1.0)[1] == 0      # below the 11 bits
+    assert oracle.tea_sig_inputs(0, 1.0 + 2.0 ** -11, 1.0, 1.0)[1] == 1      # the 11th bit
+
+
+def test_tea_pair_gaussians_moments_and_symmetry():
+    """The paper checks this generator by the moments of its output (up to
+    the fourth); over 2^20 pairs of random signatures: 0, 1, 0, 3 within a
+    few standard errors, symmetric in the pair, and each pair's words give
+    the Box-Muller value recomputed with numpy."""
+    rng = np.random.default_rng(5)
+    n = 1 << 20
+    si = rng.integers(0, 2 ** 32, size=n, dtype=np.uint64).astype(np.uint32)
+    sj = rng.integers(0, 2 ** 32, size=n, dtype=np.uint64).astype(np.uint32)
+    w, xi = oracle.tea_xi(si, sj, 17, 99)
+    w2, xi2 = oracle.tea_xi(sj, si, 17, 99)
+    np.testing.assert_array_equal(xi, xi2)
+    se = 1.0 / np.sqrt(n)
+    assert abs(xi.mean()) < 5 * se
+    assert abs(np.mean(xi ** 2) - 1.0) < 5 * np.sqrt(2.0) * se
+    assert abs(np.mean(xi ** 3)) < 5 * np.sqrt(15.0) * se
+    assert abs(np.mean(xi ** 4) - 3.0) < 5 * np.sqrt(96.0) * se
+    u1 = (w[:, 0].astype(np.float64) + 0.5) / 2.0 ** 32
+    u2 = w[:, 1].astype(np.float64) / 2.0 ** 32
+    np.testing.assert_allclose(xi, np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2), rtol=0, atol=1e-13)
+    # Step to step, the values decorrelate through the signatures (rehashed
+    # with the step in the key, 16 cycles); four cycles alone do not
+    # decorrelate a key that changes by one: with the signatures held fixed
+    # the next step's values correlate strongly.
+    _, xi_frozen = oracle.tea_xi(si, sj, 18, 99)
+    assert np.corrcoef(xi, xi_frozen)[0, 1] > 0.3
+    m = 1 << 16
+    tags = rng.permutation(m).astype(np.uint32)
+    vel = rng.standard_normal((3, m))
+    a, b = rng.integers(0, m, size=n), rng.integers(0, m, size=n)
+    s17 = oracle.tea_signatures(tags, vel, 17, 99)
+    s18 = oracle.tea_signatures(tags, vel, 18, 99)
+    _, x17 = oracle.tea_xi(s17[a], s17[b], 17, 99)
+    _, x18 = oracle.tea_xi(s18[a], s18[b], 18, 99)
+    assert abs(np.corrcoef(x17, x18)[0, 1]) < 5 * se
