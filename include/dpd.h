@@ -412,7 +412,7 @@ int dpd_tea_gaussians(int64_t n, const uint32_t* sig_i, const uint32_t* sig_j, u
  * their sum to sink[t].  generator 0: Philox4x32-10 and the device
  * library's log, sqrt and cospi (the FP64 force pass's generator);
  * generator 1: TEA-4 on sig[] (from dpd_tea_signatures) with the fast
- * logarithm and cosine. */
+ * logarithm and cosine.  pairs_per_thread < n_tags (else DPD_EINVAL). */
 int dpd_gaussian_throughput(int32_t generator, int32_t n_tags, int32_t pairs_per_thread, uint64_t step,
                             uint64_t seed, const uint32_t* sig, double* sink, void* stream);
 

@@ -927,6 +927,8 @@ int dpd_gaussian_throughput(int32_t generator, int32_t n_tags, int32_t pairs_per
     if (generator != 0 && generator != 1) return fail(DPD_EINVAL, "generator must be 0 or 1");
     if (n_tags < 0 || pairs_per_thread < 0) return fail(DPD_EINVAL, "sizes must be >= 0");
     if (n_tags > 0 && (!sink || (generator == 1 && !sig))) return fail(DPD_EINVAL, "sink / sig is NULL");
+    if (n_tags > 0 && pairs_per_thread >= n_tags)
+        return fail(DPD_EINVAL, "pairs_per_thread must be below n_tags (a partner index wraps once)");
     DPD_TRY(launch_gauss_throughput(generator, n_tags, pairs_per_thread, step, seed, sig, sink, as_stream(stream)),
             "gaussian throughput");
     return DPD_OK;
