@@ -77,19 +77,22 @@ def _uniform_positions(rng, n, box):
     return x
 
 
-def _velocities(rng, n):
+def _velocities(rng, n, kbt=1.0):
     v = rng.standard_normal(size=(3, n))
+    if kbt != 1.0:
+        v *= np.sqrt(kbt)                   # Maxwell-Boltzmann at k_B T (m = 1)
     v -= v.mean(axis=1, keepdims=True)      # zero total momentum
     return np.ascontiguousarray(v)
 
 
 def uniform_fluid(n: int, box, seed: int, *, a=25.0, gamma=4.5, sigma=3.0,
-                  r_c=1.0, s=0.5, dt=0.01, lam=0.5, rng_seed=None) -> System:
-    """Single-species fluid: positions uniform in the box, v ~ N(0,1) minus mean."""
+                  r_c=1.0, s=0.5, dt=0.01, lam=0.5, rng_seed=None, kbt=1.0) -> System:
+    """Single-species fluid: positions uniform in the box, v ~ N(0, k_B T)
+    minus the mean."""
     box = np.asarray(box, dtype=np.float64).reshape(3)
     rng = np.random.Generator(np.random.PCG64(seed if rng_seed is None else rng_seed))
     x = _uniform_positions(rng, n, box)
-    v = _velocities(rng, n)
+    v = _velocities(rng, n, kbt)
     return System(box=box, x=x, v=v, tag=np.arange(n, dtype=np.uint32),
                   type=np.zeros(n, dtype=np.uint8), n_types=1,
                   a=np.array([[a]]), gamma=np.array([[gamma]]), sigma=np.array([[sigma]]),
