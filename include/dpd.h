@@ -227,6 +227,24 @@ int dpd_forces(const dpd_params* p, int32_t precision, const dpd_state* sorted,
                double* stats, int32_t* d_status,
                void* ws, size_t ws_bytes, void* stream);
 
+/* dpd_forces without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and errors as
+ * dpd_forces; the force pass's per-workgroup partials of `stats` (potential
+ * energy, pair count) go to a static device array of the library (8,192 x 2
+ * doubles = 128 KiB per device, held until the process ends) instead of the
+ * caller's workspace, so nothing is allocated.  The array's device address
+ * is looked up on the first call on each device.  Limit: the force grid
+ * never exceeds 8,192 workgroups, so every n fits; a larger grid would be
+ * rejected with DPD_ECAPACITY.  Every call on a device shares that device's
+ * array (each call overwrites the partials it reads, nothing needs to start
+ * at zero): calls whose stats passes overlap on one device, on different
+ * streams or from different threads, race. */
+int dpd_forces_noalloc(const dpd_params* p, int32_t precision, const dpd_state* sorted,
+                       const dpd_cells* cells, const float* x32, const float* v32,
+                       const dpd_nlist* nl, uint64_t step, double* f_out, double* pe_out,
+                       double* stats, int32_t* d_status, void* stream);
+
 /* n_steps time steps of Algorithm 1 on one system:
  *   v_h = v + dt/2 F;  x <- x + dt v_h, wrapped into [0, L);
  *   v~  = v + lambda dt F (= v_h when lambda = 1/2);

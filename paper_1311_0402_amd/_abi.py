@@ -118,6 +118,7 @@ SIGNATURES = {
     "dpd_bin_reorder": (C.c_int, [PP, PS, PS, PC, P, P, P, C.c_size_t, P]),
     "dpd_build_neighbors": (C.c_int, [PP, PS, PC, P, PN, P, P, C.c_size_t, P]),
     "dpd_forces": (C.c_int, [PP, C.c_int32, PS, PC, P, P, PN, C.c_uint64, P, P, P, P, P, C.c_size_t, P]),
+    "dpd_forces_noalloc": (C.c_int, [PP, C.c_int32, PS, PC, P, P, PN, C.c_uint64, P, P, P, P, P]),
     "dpd_step": (C.c_int, [PP, C.c_int32, PS, C.c_int32, P, P, PC, PN, P, P, P, P, P, C.c_size_t, P]),
     "dpd_forces_backward": (C.c_int, [PP, PS, PC, PN, C.c_uint64, P, P, P, P, P, C.c_int32, P, C.c_size_t, P]),
     "dpd_step_backward": (C.c_int, [PP, PS, PC, PN, C.c_uint64, P, P, P, P, P, P, P, P, P, C.c_size_t, P]),

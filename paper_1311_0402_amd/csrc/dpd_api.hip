@@ -9,6 +9,7 @@
 #include <cstring>
 #include <utility>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -521,6 +522,47 @@ int enqueue_forces(const KParams& kp, int32_t precision, const ForceArgs& a, dou
 }  // namespace
 }  // namespace dpd
 
+namespace dpd {
+
+// Scratch of dpd_forces_noalloc: the force pass's per-workgroup (potential
+// energy, pair count) partials, one pair of doubles per workgroup of the
+// largest force grid (kMaxForceGrid), 128 KiB on every device the library
+// runs on, held until the process ends.  Host code never passes `scratch`
+// itself to a kernel (in host code it names a host-side stand-in): each
+// device's address comes from hipGetSymbolAddress, taken once per device
+// with that device current.
+constexpr size_t kScratchDoubles = (size_t)kMaxForceGrid * 2;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// this device's copy of `scratch` (its address looked up on the first call
+// on the device)
+int scratch_on_current_device(double** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(DPD_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(DPD_EUNSUPPORTED, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(DPD_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return DPD_OK;
+}
+
+}  // namespace
+}  // namespace dpd
+
 using namespace dpd;
 
 extern "C" {
@@ -600,6 +642,26 @@ int dpd_forces(const dpd_params* p, int32_t precision, const dpd_state* sorted, 
     const WsLayout L = ws_layout(kp, a.n);
     if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
     a.fred_part = stats ? carve<double>(ws, L.fred_part) : nullptr;
+    return enqueue_forces(kp, precision, a, stats, d_status, as_stream(stream));
+}
+
+int dpd_forces_noalloc(const dpd_params* p, int32_t precision, const dpd_state* sorted, const dpd_cells* cells,
+                       const float* x32, const float* v32, const dpd_nlist* nl, uint64_t step, double* f_out,
+                       double* pe_out, double* stats, int32_t* d_status, void* stream)
+{
+    KParams kp;
+    ForceArgs a;
+    int rc = prepare_forces(p, precision, sorted, cells, x32, v32, nl, step, f_out, pe_out, d_status, &kp, &a);
+    if (rc) return rc;
+    a.fred_part = nullptr;
+    if (stats && a.n > 0) {
+        if ((size_t)force_grid(a) * 2 > kScratchDoubles)
+            return fail(DPD_ECAPACITY, "force grid of %d workgroups exceeds the scratch of %d", force_grid(a),
+                        kMaxForceGrid);
+        double* part = nullptr;
+        if ((rc = scratch_on_current_device(&part))) return rc;
+        a.fred_part = part;                        // every workgroup overwrites its own pair
+    }
     return enqueue_forces(kp, precision, a, stats, d_status, as_stream(stream));
 }
 

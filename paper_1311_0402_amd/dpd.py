@@ -235,6 +235,18 @@ def dpd_forces(params: Params, precision: int, st: State, cells: Optional[Cells]
           "dpd_forces")
 
 
+def dpd_forces_noalloc(params: Params, precision: int, st: State, cells: Optional[Cells], nl: NList, step: int,
+                       f_out: torch.Tensor, *, x32=None, v32=None, pe_out=None, stats=None, status=None,
+                       stream=None) -> None:
+    s, n = st.c(), nl.c()
+    c = cells.c() if cells is not None else None
+    check(lib().dpd_forces_noalloc(C.byref(params.c()), int(precision), C.byref(s),
+                                   C.byref(c) if c is not None else None, _ptr(x32), _ptr(v32), C.byref(n),
+                                   int(step), _ptr(f_out), _ptr(pe_out), _ptr(stats), _ptr(status),
+                                   _stream(stream)),
+          "dpd_forces_noalloc")
+
+
 def dpd_step(params: Params, precision: int, st: State, n_steps: int, d_step: torch.Tensor,
              cells: Cells, nl: NList, status: torch.Tensor, ws: torch.Tensor, *, reductions=None,
              x32=None, v32=None, phase_events=None, stream=None) -> None:
