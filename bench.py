@@ -121,10 +121,14 @@ def alu_roofline(form, precision):
             "frac": ach / VALU_PEAK_TSLOTS, "slots_per_unique_pair": ALU_SLOTS_PER_PAIR[precision]}
 
 
-def run_precision(P, torch, sysd, precision, steps, warmup):
+def run_precision(P, torch, sysd, precision, steps, warmup, skin=0.0):
+    """One form's timed step loop.  With skin > 0 the lists are built at
+    r_c + skin and rebuilt only on steps where some particle has moved more
+    than skin / 2 since the last rebuild; the reorder and list phases' bytes
+    are then counted for the steps that rebuilt."""
     import paper_1311_0402_amd as PK
     prec = PK.FP64 if precision == "fp64" else PK.MIXED
-    params = P.Params.like(sysd)
+    params = P.Params.like(sysd, skin=skin)
     sim = P.System(params, sysd.n, prec)
     sim.load(sysd.x, sysd.v, sysd.tag, sysd.type, step=0)
     torch.cuda.synchronize()
@@ -161,8 +165,11 @@ def run_precision(P, torch, sysd, precision, steps, warmup):
     pairs = float(r[:, 5].mean())
     ms = total_ms / steps
     fb = force_bytes(sysd.n, nnz, n_bond_ends, precision)
-    n_cells = int(np.prod(P.cell_grid(P.Params.like(sysd))))
+    n_cells = int(np.prod(P.cell_grid(params)))
     pb = phase_bytes(sysd.n, nnz, n_bond_ends, precision, n_cells, steps)
+    rebuilt = float(r[:, 7].mean())
+    pb["reorder"] *= rebuilt
+    pb["nlist"] *= rebuilt
     hbm_frac = {k: pb[k] / (phase_ms[q] * 1e-3) / 1e9 / HBM_PEAK_GBS for q, k in enumerate(PHASES)}
     # algorithmic bytes can only exceed what HBM moves if a phase's window
     # were mis-attributed (or its data served from cache)
@@ -182,6 +189,8 @@ def run_precision(P, torch, sysd, precision, steps, warmup):
         "phase_hbm_frac": hbm_frac,
         "kbt_last": float(r[-1, 6]),
         "momentum_max": float(np.abs(r[:, :3]).max()),
+        "skin": skin,
+        "rebuild_fraction": rebuilt,
     }
     out["force_alu_frac"] = alu_roofline(out, precision)["frac"]
     # the state the timed loop leaves (its forces are checked against the
@@ -441,7 +450,7 @@ def cpu_baseline(sysd, finals, gpu_value):
     el = time.perf_counter() - t0
     del f0
     rate = sysd.n * k / el
-    log(f"cpu leg: 16M oracle {el / k:.2f} s/step on {threads} threads")
+    log(f"cpu leg: {sysd.n}-particle oracle {el / k:.2f} s/step on {threads} threads")
     all_threads = _oracle_child(threads, True)
     one_thread = _oracle_child(1, False)
     log(f"cpu leg: O(N^2) all threads {all_threads}; one thread {one_thread}")
@@ -480,6 +489,11 @@ def main():
                          "device copy of COPY_BYTES as the counter calibration; prints no bench line")
     ap.add_argument("--batched-steps", type=int, default=100)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--pair-mode", type=int, default=None,
+                    help="pair evaluation (0 every entry, 1 pairs once, 2 pairs once in FP64 only; "
+                         "default: the library's)")
+    ap.add_argument("--skin", type=float, default=0.3,
+                    help="the mixed form is also timed with this Verlet skin (0: not run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -490,6 +504,8 @@ def main():
     import dpd_inputs as di
     import paper_1311_0402_amd as P
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.pair_mode is not None:
+        P.set_pair_evaluation(args.pair_mode)
     t0 = time.perf_counter()
     sysd = di.amphiphile(n=args.n, seed=3)
     log(f"generated {sysd.n} particles, box {sysd.box[0]:.3f}, in {time.perf_counter() - t0:.1f}s")
@@ -502,6 +518,12 @@ def main():
     for prec in (["fp64", "mixed"] if args.precision == "both" else [args.precision]):
         results[prec], finals[prec] = run_precision(P, torch, sysd, prec, args.steps, args.warmup)
         log(f"{prec}: {results[prec]['ms_per_step']:.3f} ms/step, phases {results[prec]['phase_ms']}")
+
+    if args.skin > 0 and args.precision != "fp64":
+        res_skin, _ = run_precision(P, torch, sysd, "mixed", args.steps, args.warmup, skin=args.skin)
+        results[f"mixed_skin{args.skin:g}"] = res_skin
+        log(f"mixed, skin {args.skin:g}: {res_skin['ms_per_step']:.3f} ms/step, rebuilt on "
+            f"{100 * res_skin['rebuild_fraction']:.0f}% of steps, phases {res_skin['phase_ms']}")
 
     if not args.no_batched:
         results["batched"] = run_batched(P, torch, args.batched_steps, 10, max(5, args.batched_steps // 10))
