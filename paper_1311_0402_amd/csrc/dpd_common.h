@@ -305,9 +305,10 @@ __device__ __forceinline__ double gauss64(U4 w)
 __device__ __forceinline__ float gauss32(U4 w)
 {
     constexpr float kLn2 = 0.693147180559945309f;
-    const float u1 = ((float)w.x + 0.5f) * 0x1p-32f;
-    const float t = ((float)(0xFFFFFFFFu - w.x) + 0.5f) * 0x1p-32f;
-    const float series = -t * (1.0f + t * (0.5f + t * (0.333333333f + t * 0.25f)));
+    // (w + 1/2) 2^-32 as one fused multiply-add on the converted word
+    const float u1 = __fmaf_rn((float)w.x, 0x1p-32f, 0x1p-33f);
+    const float t = __fmaf_rn((float)(0xFFFFFFFFu - w.x), 0x1p-32f, 0x1p-33f);
+    const float series = -t * __fmaf_rn(t, __fmaf_rn(t, __fmaf_rn(t, 0.25f, 0.333333333f), 0.5f), 1.0f);
     const float lg = __builtin_amdgcn_logf(w.x >= 0x80000000u ? 1.0f - t : u1) * kLn2;
     const float lnu = (w.x >= 0x80000000u && t < 0x1p-7f) ? series : lg;
     const float u2 = (float)w.y * 0x1p-32f;

@@ -109,10 +109,10 @@ __device__ __forceinline__ void add_bonds_body(const KParams& kp, const ForceArg
 // Work layout.  A wavefront owns 64 consecutive particles ("rows"); their
 // neighbour rows are one contiguous run of CSR entries, which the wave walks
 // 64 entries at a time, one pair per lane (coalesced index loads, no idle
-// lanes waiting for long rows).  Each lane finds its entry's row by a binary
-// search over the rows' end offsets held one per lane, evaluates the pair,
-// and a segmented scan (one segment per row) carries the sums to the lane
-// that ends the row's part of the batch; the row's own lane then adds it to
+// lanes waiting for long rows).  Each lane finds its entry's row (row_pos
+// below), evaluates the pair, and a prefix sum over the batch's 64 lanes
+// gives each row's part of the batch as the difference of the prefix values
+// at the row's last and first lanes; the row's own lane adds that part to
 // its accumulator.  The grid is persistent: each wave takes a contiguous
 // range of 64-particle chunks, numbered XCD by XCD.
 
@@ -176,31 +176,6 @@ __device__ __forceinline__ double dpp_move(double v)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Inclusive scan over lanes [ss, lane] of this lane's segment (segments are
-// runs of lanes; ss is the first lane of this lane's run).  Four shifts
-// inside 16-lane rows, then the row tails are carried across rows (lane 15
-// to row 1, lane 47 to row 3, then lane 31 to rows 2 and 3).  A fixed
-// order: every lane's sum is formed the same way on every call.
-template <typename T>
-__device__ __forceinline__ T seg_scan(T v, int lane, int ss)
-{
-    const int in_row = lane & 15;
-    T t;
-    t = dpp_move<kDppRowShr | 1, 0xF>(v);
-    v = (in_row >= 1 && lane - 1 >= ss) ? v + t : v;
-    t = dpp_move<kDppRowShr | 2, 0xF>(v);
-    v = (in_row >= 2 && lane - 2 >= ss) ? v + t : v;
-    t = dpp_move<kDppRowShr | 4, 0xF>(v);
-    v = (in_row >= 4 && lane - 4 >= ss) ? v + t : v;
-    t = dpp_move<kDppRowShr | 8, 0xF>(v);
-    v = (in_row >= 8 && lane - 8 >= ss) ? v + t : v;
-    t = dpp_move<kDppBcast15, 0xA>(v);
-    v = (((lane >> 4) & 1) && ss <= (lane & ~15) - 1) ? v + t : v;
-    t = dpp_move<kDppBcast31, 0xC>(v);
-    v = (lane >= 32 && ss <= 31) ? v + t : v;
-    return v;
-}
-
 // Inclusive prefix sum over all 64 lanes (no segments): shifts inside the
 // 16-lane rows, then the row tails carried across rows.  Lanes without a
 // source add 0, so no selects are needed.  A row of the batch is then the
@@ -241,6 +216,13 @@ __device__ __forceinline__ float row_part(float prefix, int32_t first, int32_t l
     const float hi = __shfl(prefix, last < 0 ? 0 : last, kWave);
     const float lo = __shfl(prefix, first > 0 ? first - 1 : 0, kWave);
     return last < 0 ? 0.f : (first > 0 ? hi - lo : hi);
+}
+
+__device__ __forceinline__ double row_part(double prefix, int32_t first, int32_t last)
+{
+    const double hi = __shfl(prefix, last < 0 ? 0 : last, kWave);
+    const double lo = __shfl(prefix, first > 0 ? first - 1 : 0, kWave);
+    return last < 0 ? 0.0 : (first > 0 ? hi - lo : hi);
 }
 
 // a slab entry's particle index and stencil code (-1: not coded)
@@ -414,7 +396,7 @@ __device__ __forceinline__ PairJob chunk_job(const BatchView& bv, const ForceArg
 // wave take effect in program order), and an inclusive prefix maximum over
 // the lanes carries each mark to the row's later entries.
 struct RowPos {
-    int32_t r, ss;
+    int32_t r;
     int32_t start;       // first entry of the row (absolute)
 };
 
@@ -450,7 +432,6 @@ __device__ __forceinline__ RowPos row_pos(const PairJob& jb, int32_t eb, int lan
     RowPos rp;
     rp.r = r;
     rp.start = __shfl(jb.rstart, r, kWave);
-    rp.ss = rp.start - eb > 0 ? rp.start - eb : 0;
     return rp;
 }
 
@@ -499,12 +480,42 @@ struct Op64 {
     int32_t type;
 };
 
-__device__ __forceinline__ Op64 load_op64(const ForceArgs& a, int64_t N, int32_t i)
+// The packed FP64 records through buffer resources (32-bit byte offsets,
+// n < 2^26), as two 16-byte loads each.
+struct Src64 {
+    __amdgpu_buffer_rsrc_t x, v;
+};
+
+__device__ __forceinline__ Src64 src64(const ForceArgs& a)
+{
+    const int32_t bytes = a.x64 && a.n < (1 << 26) ? a.n * (int32_t)sizeof(double4) : 0;
+    return Src64{__builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(a.x64), (short)0, bytes, 0x00020000),
+                 __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(a.v64), (short)0, bytes, 0x00020000)};
+}
+
+__device__ __forceinline__ double4 rec64(__amdgpu_buffer_rsrc_t r, int32_t k)
+{
+    const int32_t o = k * (int32_t)sizeof(double4);
+    const auto lo = __builtin_amdgcn_raw_buffer_load_b128(r, o, 0, 0);
+    const auto hi = __builtin_amdgcn_raw_buffer_load_b128(r, o + 16, 0, 0);
+    auto d = [](int a, int b) { return __longlong_as_double(((long long)(uint32_t)b << 32) | (uint32_t)a); };
+    double4 r4;
+    r4.x = d(lo[0], lo[1]); r4.y = d(lo[2], lo[3]); r4.z = d(hi[0], hi[1]); r4.w = d(hi[2], hi[3]);
+    return r4;
+}
+
+__device__ __forceinline__ Op64 load_op64(const ForceArgs& a, const Src64& sr, int64_t N, int32_t i)
 {
     Op64 o;
     if (a.x64) {
-        const double4 p = reinterpret_cast<const double4*>(a.x64)[i];
-        const double4 q = reinterpret_cast<const double4*>(a.v64)[i];
+        double4 p, q;
+        if (a.n < (1 << 26)) {
+            p = rec64(sr.x, i);
+            q = rec64(sr.v, i);
+        } else {
+            p = reinterpret_cast<const double4*>(a.x64)[i];
+            q = reinterpret_cast<const double4*>(a.v64)[i];
+        }
         o.x = p.x; o.y = p.y; o.z = p.z;
         o.vx = q.x; o.vy = q.y; o.vz = q.z;
         o.tag = (uint32_t)__double_as_longlong(p.w);
@@ -595,6 +606,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     double pe_tot = 0.0, np_tot = 0.0;
     const int32_t* __restrict__ slab = usable_slab(a);
     const bool coded = slab && a.slab_coded;
+    const Src64 sr = src64(a);
     for (int32_t c = cw.first; c < cw.end; c += cw.stride) {
         const PairJob jb = chunk_job<kB, kSym>(bv, a, slab, coded, sk, c, ok, lane);
         PairParams pp_sys;
@@ -622,11 +634,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             if (valid) {
                 bool hit;
                 if constexpr (kB) {
-                    hit = pair64<kWMode, true>(pp_sys, wt, wt + kTab, wt + 2 * kTab, load_op64(a, N, i),
-                                               load_op64(a, N, j), step, px, py, pz, pp);
+                    hit = pair64<kWMode, true>(pp_sys, wt, wt + kTab, wt + 2 * kTab, load_op64(a, sr, N, i),
+                                               load_op64(a, sr, N, j), step, px, py, pz, pp);
                 } else {
-                    hit = pair64<kWMode, true>(kp, s_a, s_g, s_s, load_op64(a, N, i), load_op64(a, N, j), step,
-                                         px, py, pz, pp);
+                    hit = pair64<kWMode, true>(kp, s_a, s_g, s_s, load_op64(a, sr, N, i), load_op64(a, sr, N, j),
+                                               step, px, py, pz, pp);
                 }
                 pn = hit ? 1.0 : 0.0;
                 np_tot += pn;
@@ -645,19 +657,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 }
             }
             pe_tot += pp;
-            const int ss = rp.ss;
-            px = seg_scan(px, lane, ss);
-            py = seg_scan(py, lane, ss);
-            pz = seg_scan(pz, lane, ss);
-            if (want_pe) pp = seg_scan(pp, lane, ss);
-            if (want_np) pn = seg_scan(pn, lane, ss);
+            // each row's part of the batch as the difference of two prefix
+            // sums over the batch (the prefix values stay within a few
+            // hundred, so a part carries an error of a few ulp of that,
+            // far below the per-particle bar)
+            px = wave_prefix(px);
+            py = wave_prefix(py);
+            pz = wave_prefix(pz);
+            if (want_pe) pp = wave_prefix(pp);
+            if (want_np) pn = wave_prefix(pn);
             const int32_t src = row_end_lane(jb, eb);
-            const int32_t sl = src < 0 ? 0 : src;
-            const double tx = __shfl(px, sl, kWave);
-            const double ty = __shfl(py, sl, kWave);
-            const double tz = __shfl(pz, sl, kWave);
-            const double tp2 = want_pe ? __shfl(pp, sl, kWave) : 0.0;
-            const double tn = want_np ? __shfl(pn, sl, kWave) : 0.0;
+            const int32_t first = jb.rstart - eb;
+            const double tx = row_part(px, first, src);
+            const double ty = row_part(py, first, src);
+            const double tz = row_part(pz, first, src);
+            const double tp2 = want_pe ? row_part(pp, first, src) : 0.0;
+            const double tn = want_np ? row_part(pn, first, src) : 0.0;
             if (src >= 0) { fx += tx; fy += ty; fz += tz; pe_row += tp2; np_row += tn; }
         }
         if constexpr (kSym) {
@@ -709,12 +724,32 @@ struct PairIn {
     uint32_t ci, cj;
 };
 
-__device__ __forceinline__ PairIn load_pair(const ForceArgs& a, const float4* __restrict__ xw,
-                                            const float4* __restrict__ vw, int32_t i, int32_t j, bool coded)
+// The packed records through buffer resources: 32-bit byte offsets (n <
+// 2^28) instead of 64-bit addresses per gather, and a record past the end
+// reads zero instead of faulting.
+struct MixedSrc {
+    __amdgpu_buffer_rsrc_t xw, vw;
+};
+
+__device__ __forceinline__ MixedSrc mixed_src(const ForceArgs& a)
+{
+    const int32_t bytes = a.n * (int32_t)sizeof(float4);
+    return MixedSrc{__builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(a.x32), (short)0, bytes, 0x00020000),
+                    __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(a.v32), (short)0, bytes, 0x00020000)};
+}
+
+__device__ __forceinline__ float4 rec4(__amdgpu_buffer_rsrc_t r, int32_t k)
+{
+    const auto w = __builtin_amdgcn_raw_buffer_load_b128(r, k * (int32_t)sizeof(float4), 0, 0);
+    return make_float4(__int_as_float(w[0]), __int_as_float(w[1]), __int_as_float(w[2]), __int_as_float(w[3]));
+}
+
+__device__ __forceinline__ PairIn load_pair(const ForceArgs& a, const MixedSrc& src, int32_t i, int32_t j,
+                                            bool coded)
 {
     PairIn in;
-    in.pi = xw[i]; in.qi = vw[i];
-    in.pj = xw[j]; in.qj = vw[j];
+    in.pi = rec4(src.xw, i); in.qi = rec4(src.vw, i);
+    in.pj = rec4(src.xw, j); in.qj = rec4(src.vw, j);
     in.ci = 0u; in.cj = 0u;
     if (!coded) { in.ci = a.cell_xyz[i]; in.cj = a.cell_xyz[j]; }
     return in;
@@ -729,19 +764,20 @@ struct Stage {
 
 template <int kWMode, bool kUniform, typename PT, typename Tab>
 __device__ __forceinline__ bool pair32(const PT& P, const Tab* A, const Tab* G, const Tab* S,
-                                       const ForceArgs& a, const PairIn& in, int64_t N, int32_t i, int32_t j,
-                                       int32_t code, bool coded, bool valid, uint64_t step, float& px,
-                                       float& py, float& pz, float& pp)
+                                       const float4* __restrict__ offs, bool skin, const ForceArgs& a,
+                                       const PairIn& in, int64_t N, int32_t i, int32_t j, int32_t code,
+                                       bool coded, bool valid, uint64_t step, float& px, float& py, float& pz,
+                                       float& pp)
 {
     const float4 pi = in.pi, qi = in.qi;
     const float4 pj = in.pj, qj = in.qj;
     // whole-cell offset of i's cell from j's: from the list entry's stencil
-    // code when it has one, else from the two cells' coordinates
+    // code when it has one (a table of the 27 offsets in the wave's LDS),
+    // else from the two cells' coordinates
     float ox, oy, oz;
     if (coded) {
-        ox = (float)(1 - (code & 3)) * P.cell_len32[0];
-        oy = (float)(1 - ((code >> 2) & 3)) * P.cell_len32[1];
-        oz = (float)(1 - (code >> 4)) * P.cell_len32[2];
+        const float4 o = offs[code];
+        ox = o.x; oy = o.y; oz = o.z;
     } else {
         const uint32_t ci = in.ci, cj = in.cj;
         ox = (float)cell_delta((int32_t)(ci & 1023u), (int32_t)(cj & 1023u), P.nc[0]) * P.cell_len32[0];
@@ -756,7 +792,8 @@ __device__ __forceinline__ bool pair32(const PT& P, const Tab* A, const Tab* G, 
     // the FP32 test (documented reading).  Lanes without a pair (past the
     // batch's end) run the same arithmetic on their own particle and are
     // zeroed at the end, so the common path has no branches.
-    bool hit = valid && (P.rl2 == P.rc2 || r2 < (float)P.rc2);
+    bool hit = valid;
+    if (skin) hit = hit && r2 < (float)P.rc2;
     const float inv_r = __builtin_amdgcn_rsqf(r2);
     float rr = r2 * inv_r;
     float ex = dx * inv_r, ey = dy * inv_r, ez = dz * inv_r;
@@ -774,17 +811,17 @@ __device__ __forceinline__ bool pair32(const PT& P, const Tab* A, const Tab* G, 
             hit = false;                               // coincident: no direction, no force
         }
     }
-    float wc = 1.0f - rr * (float)P.inv_rc;
+    float wc = __fmaf_rn(-rr, (float)P.inv_rc, 1.0f);
     wc = wc > 0.f ? wc : 0.f;
     const float wr = weight_r32(wc, kWMode, (float)P.s);
     const float wd = kWMode == 0 ? wc : wr * wr;     // s = 1/2: w_D = w_R^2 = w_C exactly
-    const float ev = ex * (qi.x - qj.x) + ey * (qi.y - qj.y) + ez * (qi.z - qj.z);
+    const float ev = __fmaf_rn(ez, qi.z - qj.z, __fmaf_rn(ey, qi.y - qj.y, ex * (qi.x - qj.x)));
     const int tp = (int)__float_as_uint(qi.w) * P.n_types + (int)__float_as_uint(qj.w);
     uint32_t s0 = P.seed_lo, s1 = P.seed_hi;
     opaque_keys<kUniform>(s0, s1);
     const float xi_ij = gauss32(pair_words(__float_as_uint(pi.w), __float_as_uint(pj.w), step, s0, s1));
     const float at = (float)A[tp], gt = (float)G[tp], st = (float)S[tp];
-    const float phi = at * wc - gt * wd * ev + st * wr * xi_ij;
+    const float phi = __fmaf_rn(at, wc, __fmaf_rn(-(gt * wd), ev, (st * wr) * xi_ij));
     px = hit ? phi * ex : 0.f;
     py = hit ? phi * ey : 0.f;
     pz = hit ? phi * ez : 0.f;
@@ -792,8 +829,8 @@ __device__ __forceinline__ bool pair32(const PT& P, const Tab* A, const Tab* G, 
     return hit;
 }
 
-// Mixed form.  Pair terms in FP32, the segmented scan in FP32, each row's
-// batches added with a two-sum, the result stored in FP64.
+// Mixed form.  Pair terms in FP32, the batch prefix sums in FP32, each row's
+// batch parts added with a two-sum, the result stored in FP64.
 template <int kWMode, bool kB, bool kSym>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_force_mixed(KParams kp, BatchView bv, ForceArgs a, int32_t n_chunks)
 {
@@ -806,15 +843,30 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     __shared__ int32_t s_raw[kSym ? kBlock : 1], s_skip[kSym ? kBlock : 1];
     // a batch: each wave's own copy of its chunk's tables
     __shared__ float s_wt[kB ? 3 * (kBlock / kWave) * kTab : 1];
+    // each wave's table of the whole-cell offsets of the 64 stencil codes
+    // (ex | ey << 2 | ez << 4 -> ((1 - ex) l_x, (1 - ey) l_y, (1 - ez) l_z),
+    // the cell lengths of the wave's system)
+    __shared__ float4 s_off[(kBlock / kWave) * kWave];
+    const int lane = threadIdx.x & (kWave - 1);
+    float4* const offs = s_off + (threadIdx.x - lane);
+    auto stage_offsets = [&](const KParams& P) {
+        __asm__ __volatile__("" ::: "memory");
+        offs[lane] = make_float4((float)(1 - (lane & 3)) * P.cell_len32[0],
+                                 (float)(1 - ((lane >> 2) & 3)) * P.cell_len32[1],
+                                 (float)(1 - (lane >> 4)) * P.cell_len32[2], 0.f);
+        __asm__ __volatile__("" ::: "memory");
+    };
     if (!kB) {
         const int nt2 = kp.n_types * kp.n_types;
         for (int t = threadIdx.x; t < nt2; t += kBlock) {
             s_a[t] = (float)kp.a[t]; s_g[t] = (float)kp.g[t]; s_s[t] = (float)kp.srdt[t];
         }
+        stage_offsets(kp);
         __syncthreads();
     }
+    // lists built with a skin: the FP32 separation decides r < r_c
+    bool skin = __builtin_amdgcn_readfirstlane(kp.rl2 != kp.rc2 ? 1 : 0) != 0;
     float* const wt = s_wt + (kB ? 3 * kTab * (int)(threadIdx.x / kWave) : 0);
-    const int lane = threadIdx.x & (kWave - 1);
     int32_t* const s_mark = s_rowm + (threadIdx.x - lane);
     const int wbase = threadIdx.x - lane;
     const int sb = kSym ? wbase : 0;
@@ -829,8 +881,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const bool ok = (int64_t)a.offset[a.n] <= a.capacity;
     const bool want_pe = a.pe != nullptr;
     const bool want_np = a.npair != nullptr;
-    const float4* __restrict__ xw = reinterpret_cast<const float4*>(a.x32);
-    const float4* __restrict__ vw = reinterpret_cast<const float4*>(a.v32);
+    const MixedSrc src = mixed_src(a);
     const int32_t* __restrict__ slab = usable_slab(a);
     const bool coded = slab && a.slab_coded;
     double pe_tot = 0.0;
@@ -840,7 +891,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         PairParams pp_sys;
         if constexpr (kB) {
             stage_tables(bv.kps[jb.sys], wt, wt + kTab, wt + 2 * kTab, lane);
+            stage_offsets(bv.kps[jb.sys]);
             pp_sys = pair_params(bv.kps[jb.sys]);
+            skin = pp_sys.rl2 != pp_sys.rc2;
         }
         float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, pe_row = 0.f, np_row = 0.f;
         // software pipeline: the list entry two batches ahead and the pair
@@ -853,7 +906,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         const int32_t raw0 = jb.e0 + lane < jb.e1 ? entry_at<kSym>(slab, a.slab_k, a, jb, A.rp, sk, jb.e0 + lane) : A.i;
         A.j = entry_j(raw0, coded);
         A.code = entry_code(raw0, coded);
-        A.in = load_pair(a, xw, vw, A.i, A.j, coded);
+        A.in = load_pair(a, src, A.i, A.j, coded);
         RowPos rp_nxt = row_pos(jb, jb.e0 + kWave, lane, s_mark);
         bool has_nxt = jb.e0 + kWave + lane < jb.e1;
         int32_t raw_nxt = has_nxt ? entry_at<kSym>(slab, a.slab_k, a, jb, rp_nxt, sk, jb.e0 + kWave + lane) : 0;
@@ -863,7 +916,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 nxt.i = jb.i0 + nxt.rp.r;
                 nxt.j = has_nxt ? entry_j(raw_nxt, coded) : nxt.i;
                 nxt.code = entry_code(raw_nxt, coded);
-                nxt.in = load_pair(a, xw, vw, nxt.i, nxt.j, coded);
+                nxt.in = load_pair(a, src, nxt.i, nxt.j, coded);
                 const int32_t e2 = eb + 2 * kWave + lane;
                 has_nxt = e2 < jb.e1;
                 if (eb + 2 * kWave < jb.e1) {
@@ -875,11 +928,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             float px, py, pz, pp;
             bool hit;
             if constexpr (kB) {
-                hit = pair32<kWMode, true>(pp_sys, wt, wt + kTab, wt + 2 * kTab, a, cur.in, N, cur.i, cur.j,
-                                           cur.code, coded, valid, step, px, py, pz, pp);
+                hit = pair32<kWMode, true>(pp_sys, wt, wt + kTab, wt + 2 * kTab, offs, skin, a, cur.in, N, cur.i,
+                                           cur.j, cur.code, coded, valid, step, px, py, pz, pp);
             } else {
-                hit = pair32<kWMode, true>(kp, s_a, s_g, s_s, a, cur.in, N, cur.i, cur.j, cur.code, coded, valid,
-                                           step, px, py, pz, pp);
+                hit = pair32<kWMode, true>(kp, s_a, s_g, s_s, offs, skin, a, cur.in, N, cur.i, cur.j, cur.code,
+                                           coded, valid, step, px, py, pz, pp);
             }
             float pn = hit ? 1.f : 0.f;
             np_tot += hit ? 1 : 0;

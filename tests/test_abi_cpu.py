@@ -234,3 +234,18 @@ def test_batch_create_validates_before_touching_memory():
     assert b"system 0" in lib.dpd_last_error()
     assert h.value is None
     lib.dpd_batch_destroy(None)
+
+
+def test_autotune_staged_search_space():
+    """The tile builder ignores nlist_waves, so it is one candidate; the
+    force grid is searched once, with the chosen builder."""
+    from paper_1311_0402_amd import autotune as A
+    b = A.builder_candidates()
+    assert sum(1 for t in b if t.nlist_kind == 0) == 1
+    assert sorted(t.nlist_waves for t in b if t.nlist_kind == 1) == [1, 2, 4]
+    assert sorted(t.nlist_waves for t in b if t.nlist_kind == 2) == [1, 2, 4]
+    assert all(t.force_grid == 0 for t in b)
+    f = A.force_candidates(b[3])
+    assert [t.force_grid for t in f] == list(A.FORCE_GRIDS)
+    assert all((t.nlist_kind, t.nlist_waves) == (b[3].nlist_kind, b[3].nlist_waves) for t in f)
+    assert len(A.default_candidates()) == len(b) * len(A.FORCE_GRIDS)
