@@ -260,6 +260,91 @@ def run_batched(P, torch, steps, warmup, seq_steps, n_sys=256):
             "speedup_vs_sequential": ms_seq / ms}
 
 
+def _time_ms(torch, fn, reps=5):
+    """Median milliseconds of fn() over reps, HIP events on the current stream."""
+    out = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        out.append(e0.elapsed_time(e1))
+    return float(np.median(out))
+
+
+def run_border(P, torch, sysd):
+    """One GPU's share of the border exchange on the workload's own state:
+    the send lists of the six faces of the box (band width r_c: the
+    particles a neighbouring brick would need as ghosts), the 56-byte ghost
+    records packed (position shifted by the face's periodic image), and the
+    records unpacked into a ghost state.  Algorithmic bytes: lists 24 per
+    particle (x) + 2 (flags) + 4 per listed entry; pack 113 per record
+    (index, x, v, tag, type read; record written); unpack 109 per record."""
+    n = sysd.n
+    st = P.State.empty(n)
+    st.x.copy_(torch.as_tensor(np.ascontiguousarray(sysd.x)))
+    st.v.copy_(torch.as_tensor(np.ascontiguousarray(sysd.v)))
+    st.tag.copy_(torch.as_tensor(np.ascontiguousarray(sysd.tag).astype(np.uint32).view(np.int32)))
+    st.type.copy_(torch.as_tensor(np.ascontiguousarray(sysd.type, dtype=np.uint8)))
+    lo, hi = np.zeros(3), np.asarray(sysd.box, dtype=np.float64)
+    width = float(sysd.r_c)
+    off = torch.zeros(7, dtype=torch.int32, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ws = P.border_workspace(n)
+    probe = torch.empty(1, dtype=torch.int32, device="cuda")
+    P.dpd_border_lists(st, lo, hi, width, 63, off, probe[:0], status, ws)     # sizes only
+    total = int(off[6].item())
+    idx = torch.empty(total, dtype=torch.int32, device="cuda")
+    status.zero_()
+    rec = P.ghost_records(total)
+    shift = np.zeros((6, 3))
+    for d in range(3):
+        shift[2 * d, d], shift[2 * d + 1, d] = hi[d], -hi[d]      # low face -> image above, high -> below
+    ghosts = P.State.empty(total)
+    count = off[6:7]
+    t_lists = _time_ms(torch, lambda: P.dpd_border_lists(st, lo, hi, width, 63, off, idx, status, ws))
+    t_pack = _time_ms(torch, lambda: P.dpd_border_pack(st, off, idx, shift, rec, status))
+    t_unpack = _time_ms(torch, lambda: P.dpd_border_unpack(rec, count, ghosts, 0, status))
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0, int(status.item())
+    b_lists, b_pack, b_unpack = 26.0 * n + 4.0 * total, 113.0 * total, 109.0 * total
+    out = {"n": n, "records": total, "faces": 6, "width": width,
+           "ms": {"lists": t_lists, "pack": t_pack, "unpack": t_unpack},
+           "gbs": {"lists": b_lists / (t_lists * 1e-3) / 1e9, "pack": b_pack / (t_pack * 1e-3) / 1e9,
+                   "unpack": b_unpack / (t_unpack * 1e-3) / 1e9}}
+    out["hbm_frac"] = {k: v / HBM_PEAK_GBS for k, v in out["gbs"].items()}
+    del st, ghosts, rec, idx, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_numerics(P, torch, n_tags=4_000_000, pairs=16, chain=4096):
+    """The paper's numerics against the device library (A/B): one wave's
+    dependent chain per function (shader clocks per call), and pair-Gaussian
+    throughput of Philox4x32-10 + library log/sqrt/cos (the FP64 force
+    pass's generator) against TEA-4 on signatures + the fast log and cosine."""
+    from paper_1311_0402_amd import _abi
+    from paper_1311_0402_amd import dpd as D
+    names = {"log": _abi.FN_LOG, "fast_log": _abi.FN_FASTLOG, "cos2pi": _abi.FN_COS2PI,
+             "fast_cos2pi": _abi.FN_FASTCOS2PI, "pow": _abi.FN_POW, "fast_pow": _abi.FN_FASTPOW}
+    D.math_latency(_abi.FN_LOG, 64)                                 # warm-up (code load)
+    lat = {k: D.math_latency(f, chain) / chain for k, f in names.items()}
+    rng = np.random.default_rng(5)
+    tag = torch.as_tensor(np.arange(n_tags, dtype=np.uint32).view(np.int32), device="cuda")
+    v = torch.as_tensor(rng.standard_normal((3, n_tags)), device="cuda")
+    sig = D.tea_signatures(tag, v, 1, 7)
+    sink = torch.empty(n_tags, dtype=torch.float64, device="cuda")
+    thr = {}
+    for gen, name in ((0, "philox_library"), (1, "tea_fast")):
+        ms = _time_ms(torch, lambda: D.gaussian_throughput(gen, n_tags, pairs, 1, 7, sig if gen else None, sink))
+        thr[name] = n_tags * pairs / (ms * 1e-3)
+    t_sig = _time_ms(torch, lambda: D.tea_signatures(tag, v, 1, 7))
+    return {"cycles_per_call": lat, "chain": chain, "gaussians_per_s": thr,
+            "tea_signatures_per_s": n_tags / (t_sig * 1e-3), "pairs_per_thread": pairs, "n_tags": n_tags}
+
+
 def run_adjoint(P, torch, steps=50, ckpt=10):
     """Force-matching loss over a 50-step trajectory of the 512,000-particle
     A/B mixture (checkpoints every 10 steps): forward and backward times,
@@ -489,6 +574,8 @@ def main():
                          "device copy of COPY_BYTES as the counter calibration; prints no bench line")
     ap.add_argument("--batched-steps", type=int, default=100)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the border-exchange and numerics A/B measurements")
     ap.add_argument("--pair-mode", type=int, default=None,
                     help="pair evaluation (0 every entry, 1 pairs once, 2 pairs once in FP64 only; "
                          "default: the library's)")
@@ -530,6 +617,13 @@ def main():
         bt = results["batched"]
         log(f"batched: {bt['ms_per_step']:.3f} ms/step for {bt['n_total']} particles in {bt['n_sys']} systems "
             f"(tiles {bt['tiles']}); sequential {bt['sequential']['ms_per_step']:.3f} ms/step")
+
+    if not args.no_extras:
+        results["border"] = run_border(P, torch, sysd)
+        bd = results["border"]
+        log(f"border exchange: {bd['records']} records, ms {bd['ms']}, GB/s {bd['gbs']}")
+        results["numerics_ab"] = run_numerics(P, torch)
+        log(f"numerics A/B: {results['numerics_ab']}")
 
     if not args.no_adjoint:
         results["adjoint"] = run_adjoint(P, torch)

@@ -259,6 +259,9 @@ WsLayout ws_layout(const Job& job, int32_t n, bool aos = false)
     const bool skin = job.kp.rl2 != job.kp.rc2;
     w.xref = skin ? take(3 * N * sizeof(double)) : 0;
     w.gate = skin ? take(2 * sizeof(int32_t)) : 0;
+    w.kept = skin ? take(N * (size_t)w.slab_k * sizeof(int32_t)) : 0;
+    w.kept_off = skin ? take((N + 1) * sizeof(int32_t)) : 0;
+    w.kept_flag = skin ? take(sizeof(int32_t)) : 0;
     w.x64 = aos ? take(N * 4 * sizeof(double)) : 0;
     w.v64 = aos ? take(N * 4 * sizeof(double)) : 0;
     w.total = o;
@@ -756,6 +759,18 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
     // (slightly below (skin/2)^2, so rounding in the displacement can only
     // rebuild early)
     sd.disp2 = half_skin * half_skin * (1.0 - std::ldexp(1.0, -20));
+    // With a skin, each step's force pass reads the rows of the pairs now
+    // inside r_c, filtered out of the list (built at r_c + skin) in order:
+    // the list entries between r_c and r_c + skin would otherwise take a
+    // lane of the force pass each.
+    ForceArgs af = a;
+    int32_t* kept_off = skin ? carve<int32_t>(ws, L.kept_off) : nullptr;
+    if (skin) {
+        af.slab = carve<int32_t>(ws, L.kept);
+        af.slab_flag = carve<int32_t>(ws, L.kept_flag);
+        af.offset = kept_off;
+        af.capacity = a.capacity;                        // kept rows are never longer than the list's
+    }
     for (int32_t k = 0; k < n_steps; ++k) {
         Job jk = job;
         int32_t* g = skin ? gates + (k & 1) : nullptr;
@@ -799,8 +814,17 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
         // is written for the last step, which the caller sees
         rc = enqueue_nlist(jk, L, ws, st, cells, x32, nl, d_status, s, k == n_steps - 1);
         if (rc) return rc;
+        if (skin) {
+            af.pidx = a.pidx;
+            int32_t* kflag = carve<int32_t>(ws, L.kept_flag);
+            DPD_TRY(launch_fill_i32(kflag, 1, 0, s), "kept rows flag");
+            DPD_TRY(launch_skin_filter(kp, precision, a, carve<int32_t>(ws, L.kept), kept_off, kflag, s),
+                    "rows inside r_c");
+            DPD_TRY(launch_fill_i32(kept_off + n, 1, 0, s), "kept rows total");
+            DPD_TRY(launch_scan(kept_off, (int64_t)n + 1, carve<int32_t>(ws, L.scan_part), s), "kept rows scan");
+        }
         DPD_TRY(mark(k, 3), "event");
-        DPD_TRY(launch_forces(kp, job.bv, precision, a, s), "forces");
+        DPD_TRY(launch_forces(kp, job.bv, precision, skin ? af : a, s), "forces");
         DPD_TRY(mark(k, 4), "event");
         if (k == n_steps - 1) {
             DPD_TRY(launch_vv2(kp, n, st->v, st->f, red_part, a.fred_part, force_grid(a), fsum_part, s), "vv2");

@@ -43,6 +43,8 @@ struct WsLayout {
                                        // two generations) and the old -> new index map
     size_t xref;                       // skin > 0: positions at the last rebuild (sorted order)
     size_t gate;                       // skin > 0: two rebuild flags (steps alternate between them)
+    size_t kept, kept_off, kept_flag;  // skin > 0: each step's rows inside r_c (slab layout), their
+                                       // offsets (n + 1) and a zero slab flag
     size_t total;
 };
 
@@ -148,6 +150,13 @@ struct ForceArgs {
 };
 hipError_t launch_forces(const KParams& kp, const BatchView& bv, int precision, const ForceArgs& a,
                          hipStream_t s);
+// a list built at r_c + skin: for each row i of the builder's slab, the
+// entries now inside r_c in order, at kept[i * a.slab_k], their number in
+// count[i] (single system); when the slab overflowed, count[i] gets the CSR
+// row size and *kept_flag is set (the force pass then reads the CSR list);
+// *kept_flag must be 0 before the launch
+hipError_t launch_skin_filter(const KParams& kp, int precision, const ForceArgs& a, int32_t* kept, int32_t* count,
+                              int32_t* kept_flag, hipStream_t s);
 constexpr int kMaxForceGrid = 8192;
 // library default of ForceArgs::pairs_once for a precision (0 FP64, 1
 // mixed) under the process-wide pair mode (0 every entry, 1 pairs once,

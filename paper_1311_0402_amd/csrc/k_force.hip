@@ -623,10 +623,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             const bool valid = e < jb.e1;
             const RowPos rp = rp_nxt;
             const int32_t raw = raw_nxt;
-            if (eb + kWave < jb.e1) {
-                rp_nxt = row_pos(jb, eb + kWave, lane, s_mark);
-                raw_nxt = e + kWave < jb.e1 ? entry_at<kSym>(slab, a.slab_k, a, jb, rp_nxt, sk, e + kWave) : 0;
-            }
+            // (unguarded: a request past the chunk's last entry is masked
+            // off per lane, and no register copy at a join waits for it)
+            rp_nxt = row_pos(jb, eb + kWave, lane, s_mark);
+            raw_nxt = e + kWave < jb.e1 ? entry_at<kSym>(slab, a.slab_k, a, jb, rp_nxt, sk, e + kWave) : 0;
             const int32_t r = rp.r;
             const int32_t i = jb.i0 + r;
             const int32_t j = valid ? entry_j(raw, coded) : i;
@@ -829,6 +829,189 @@ __device__ __forceinline__ bool pair32(const PT& P, const Tab* A, const Tab* G, 
     return hit;
 }
 
+// One particle's operands of the filter's distance test: its FP32
+// cell-relative position and cell word (mixed form; the word only when list
+// entries carry no stencil code), or its FP64 position (FP64 form).
+template <bool kMixed> struct SkinOp;
+template <> struct SkinOp<true> {
+    float x, y, z;
+    uint32_t cell;
+};
+template <> struct SkinOp<false> {
+    double x, y, z;
+};
+
+template <bool kMixed>
+__device__ __forceinline__ SkinOp<kMixed> skin_op(const ForceArgs& a, int32_t k, bool coded)
+{
+    SkinOp<kMixed> o;
+    if constexpr (kMixed) {
+        const float4 p = rec4(mixed_src(a).xw, k);
+        o.x = p.x; o.y = p.y; o.z = p.z;
+        o.cell = coded ? 0u : a.cell_xyz[k];
+    } else {
+        const Op64 q = load_op64(a, src64(a), a.n, k);
+        o.x = q.x; o.y = q.y; o.z = q.z;
+    }
+    return o;
+}
+
+// the operands that lane src holds
+template <bool kMixed>
+__device__ __forceinline__ SkinOp<kMixed> skin_op_of(const SkinOp<kMixed>& own, int src, bool coded)
+{
+    SkinOp<kMixed> o;
+    o.x = __shfl(own.x, src, kWave);
+    o.y = __shfl(own.y, src, kWave);
+    o.z = __shfl(own.z, src, kWave);
+    if constexpr (kMixed) o.cell = coded ? 0u : (uint32_t)__shfl((int32_t)own.cell, src, kWave);
+    return o;
+}
+
+// r < r_c for one entry, on the arithmetic of the form's force pass
+// (offs: the whole-cell offsets of the 64 stencil codes, as the force pass
+// stages them)
+template <bool kMixed>
+__device__ __forceinline__ bool skin_hit(const KParams& kp, const float4* __restrict__ offs,
+                                         const SkinOp<kMixed>& pi, const SkinOp<kMixed>& pj, int32_t code, bool coded)
+{
+    if constexpr (kMixed) {
+        float ox, oy, oz;
+        if (coded) {
+            const float4 o = offs[code];
+            ox = o.x; oy = o.y; oz = o.z;
+        } else {
+            const uint32_t ci = pi.cell, cj = pj.cell;
+            ox = (float)cell_delta((int32_t)(ci & 1023u), (int32_t)(cj & 1023u), kp.nc[0]) * kp.cell_len32[0];
+            oy = (float)cell_delta((int32_t)((ci >> 10) & 1023u), (int32_t)((cj >> 10) & 1023u), kp.nc[1]) *
+                 kp.cell_len32[1];
+            oz = (float)cell_delta((int32_t)(ci >> 20), (int32_t)(cj >> 20), kp.nc[2]) * kp.cell_len32[2];
+        }
+        const float dx = (pi.x - pj.x) + ox;
+        const float dy = (pi.y - pj.y) + oy;
+        const float dz = (pi.z - pj.z) + oz;
+        return __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx)) < (float)kp.rc2;
+    } else {
+        const double dx = min_image(pi.x - pj.x, kp.L[0], kp.halfL[0]);
+        const double dy = min_image(pi.y - pj.y, kp.L[1], kp.halfL[1]);
+        const double dz = min_image(pi.z - pj.z, kp.L[2], kp.halfL[2]);
+        return dist2(dx, dy, dz) < kp.rc2;
+    }
+}
+
+constexpr int kSkinGroup = 4;    // batches of the filter whose loads are in flight together
+
+// Rows of the pairs inside r_c out of a list built at r_c + skin, for the
+// force pass of every step (those between rebuilds keep the last build's
+// rows while the particles move).  A wave takes 64 rows and walks their
+// entries 64 at a time, as the force pass does: each lane tests its entry's
+// current separation, a ballot gives the batch's hits, and a hit goes to
+// its row's next free slot of the kept rows (same slab layout): the row's
+// count so far plus the hits on the row's lower lanes of the batch (mbcnt).
+// count[i] gets each row's kept number (scanned into offsets afterwards).
+// The mixed form decides on the FP32 separation its force pass computes
+// (in-cell offsets plus the whole-cell offset of the entry's stencil code,
+// or of the two cells when entries are not coded), the FP64 form on the
+// FP64 rule.  Each row's own operands come once per chunk, from its lane;
+// the partners' loads of kSkinGroup batches are issued together, with the
+// list entries of the next group behind them, so a wave waits once per
+// group rather than once per batch.  (A lane per row instead spreads every
+// load over 64 rows' cache lines, and ran 2.6 times slower.)
+//
+// When the builder's slab did not hold every row (its rows then come from
+// the CSR list, and a kept row might not fit a slab row), the rows pass
+// unfiltered: count[i] gets the CSR row size and *kept_flag = 1 makes the
+// force pass read the CSR list (whose offsets the scanned counts then are)
+// and test r < r_c itself.
+template <bool kMixed, bool kCoded>
+__global__ __launch_bounds__(kBlock) void k_skin_filter(KParams kp, ForceArgs a, int32_t* __restrict__ kept,
+                                                        int32_t* __restrict__ count, int32_t* __restrict__ kept_flag)
+{
+    __shared__ int32_t s_rowm[kBlock];
+    __shared__ float4 s_off[kWave];
+    const int lane = threadIdx.x & (kWave - 1);
+    int32_t* const s_mark = s_rowm + (threadIdx.x - lane);
+    const bool ok = (int64_t)a.offset[a.n] <= a.capacity;
+    const int32_t* __restrict__ slab = usable_slab(a);
+    if (!slab) {
+        for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < a.n; i += gridDim.x * kBlock)
+            count[i] = ok ? a.offset[i + 1] - a.offset[i] : 0;
+        if (blockIdx.x == 0 && threadIdx.x == 0) *kept_flag = 1;
+        return;
+    }
+    if (threadIdx.x < kWave) {
+        const int t = threadIdx.x;
+        s_off[t] = make_float4((float)(1 - (t & 3)) * kp.cell_len32[0], (float)(1 - ((t >> 2) & 3)) * kp.cell_len32[1],
+                               (float)(1 - (t >> 4)) * kp.cell_len32[2], 0.f);
+    }
+    __syncthreads();
+    const int32_t K = a.slab_k;
+    const int32_t n_chunks = (a.n + kChunk - 1) / kChunk;
+    const int32_t waves = (int32_t)gridDim.x * (kBlock / kWave);
+    const int32_t w0 = __builtin_amdgcn_readfirstlane((int32_t)blockIdx.x * (kBlock / kWave) +
+                                                      (int32_t)(threadIdx.x / kWave));
+    const BatchView none{};
+    const RowSkip sk{nullptr, nullptr};
+    for (int32_t c = w0; c < n_chunks; c += waves) {
+        const PairJob jb = chunk_job<false, false>(none, a, slab, kCoded, sk, c, ok, lane);
+        const SkinOp<kMixed> own = skin_op<kMixed>(a, jb.i0 + (lane < jb.ni ? lane : jb.ni - 1), kCoded);
+        // the chunk's rows of the slab and of the kept rows, addressed from
+        // their first row with 32-bit offsets (64 rows of K entries)
+        const int32_t* __restrict__ cs = slab + (int64_t)jb.i0 * K;
+        int32_t* __restrict__ ck = kept + (int64_t)jb.i0 * K;
+        // a row's entry of batch eb for this lane (its own particle past the end)
+        auto entry = [&](const RowPos& rp, int32_t eb) {
+            const int32_t e = eb + lane;
+            return e < jb.e1 ? cs[rp.r * K + (e - rp.start)] : jb.i0 + rp.r;
+        };
+        RowPos rp_n[kSkinGroup];
+        int32_t raw_n[kSkinGroup];
+#pragma unroll
+        for (int q = 0; q < kSkinGroup; ++q) {
+            rp_n[q] = row_pos(jb, jb.e0 + q * kWave, lane, s_mark);
+            raw_n[q] = entry(rp_n[q], jb.e0 + q * kWave);
+        }
+        int32_t kc = 0;                            // this lane's row (lane < ni): entries kept so far
+        for (int32_t eg = jb.e0; eg < jb.e1; eg += kSkinGroup * kWave) {
+            RowPos rp[kSkinGroup];
+            int32_t raw[kSkinGroup];
+            SkinOp<kMixed> pj[kSkinGroup];
+#pragma unroll
+            for (int q = 0; q < kSkinGroup; ++q) {
+                rp[q] = rp_n[q];
+                raw[q] = raw_n[q];
+                pj[q] = skin_op<kMixed>(a, entry_j(raw[q], kCoded), kCoded);
+            }
+#pragma unroll
+            for (int q = 0; q < kSkinGroup; ++q) {
+                const int32_t e = eg + (kSkinGroup + q) * kWave;
+                rp_n[q] = row_pos(jb, e, lane, s_mark);
+                raw_n[q] = entry(rp_n[q], e);
+            }
+#pragma unroll
+            for (int q = 0; q < kSkinGroup; ++q) {
+                const int32_t eb = eg + q * kWave;
+                const SkinOp<kMixed> pi = skin_op_of<kMixed>(own, rp[q].r, kCoded);
+                const bool hit =
+                    eb + lane < jb.e1 && skin_hit<kMixed>(kp, s_off, pi, pj[q], entry_code(raw[q], kCoded), kCoded);
+                const uint64_t hb = __ballot(hit);
+                const int32_t below = lanes_below(hb);            // hits on lower lanes of the batch
+                const int32_t first = rp[q].start - eb > 0 ? rp[q].start - eb : 0;
+                const int32_t below_first = __shfl(below, first & (kWave - 1), kWave);
+                const int32_t base = __shfl(kc, rp[q].r, kWave);   // the row's kept entries before the batch
+                if (hit) ck[rp[q].r * K + base + (below - below_first)] = raw[q];
+                // each row's own lane adds the row's hits in this batch
+                const int32_t last = row_end_lane(jb, eb);
+                const int32_t my_first = jb.rstart - eb > 0 ? jb.rstart - eb : 0;
+                const int32_t upto = __shfl(below + (hit ? 1 : 0), last < 0 ? 0 : last, kWave);
+                const int32_t from = __shfl(below, my_first & (kWave - 1), kWave);
+                if (last >= 0) kc += upto - from;
+            }
+        }
+        if (lane < jb.ni) count[jb.i0 + lane] = kc;
+    }
+}
+
 // Mixed form.  Pair terms in FP32, the batch prefix sums in FP32, each row's
 // batch parts added with a two-sum, the result stored in FP64.
 template <int kWMode, bool kB, bool kSym>
@@ -908,22 +1091,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         A.code = entry_code(raw0, coded);
         A.in = load_pair(a, src, A.i, A.j, coded);
         RowPos rp_nxt = row_pos(jb, jb.e0 + kWave, lane, s_mark);
-        bool has_nxt = jb.e0 + kWave + lane < jb.e1;
-        int32_t raw_nxt = has_nxt ? entry_at<kSym>(slab, a.slab_k, a, jb, rp_nxt, sk, jb.e0 + kWave + lane) : 0;
+        int32_t raw_nxt = jb.e0 + kWave + lane < jb.e1
+            ? entry_at<kSym>(slab, a.slab_k, a, jb, rp_nxt, sk, jb.e0 + kWave + lane) : jb.i0 + rp_nxt.r;
         auto batch = [&](const Stage& cur, Stage& nxt, int32_t eb) {
-            if (eb + kWave < jb.e1) {                   // requests for the next batches
-                nxt.rp = rp_nxt;
-                nxt.i = jb.i0 + nxt.rp.r;
-                nxt.j = has_nxt ? entry_j(raw_nxt, coded) : nxt.i;
-                nxt.code = entry_code(raw_nxt, coded);
-                nxt.in = load_pair(a, src, nxt.i, nxt.j, coded);
-                const int32_t e2 = eb + 2 * kWave + lane;
-                has_nxt = e2 < jb.e1;
-                if (eb + 2 * kWave < jb.e1) {
-                    rp_nxt = row_pos(jb, eb + 2 * kWave, lane, s_mark);
-                    raw_nxt = has_nxt ? entry_at<kSym>(slab, a.slab_k, a, jb, rp_nxt, sk, e2) : 0;
-                }
-            }
+            // requests for the next batches: past the chunk's last entry a
+            // lane pairs its row's particle with itself (the entry i decodes
+            // to j = i, code 0), so no branch guards them and no register
+            // copy at a join has to wait for a load in flight
+            nxt.rp = rp_nxt;
+            nxt.i = jb.i0 + nxt.rp.r;
+            nxt.j = entry_j(raw_nxt, coded);
+            nxt.code = entry_code(raw_nxt, coded);
+            nxt.in = load_pair(a, src, nxt.i, nxt.j, coded);
+            const int32_t e2 = eb + 2 * kWave + lane;
+            rp_nxt = row_pos(jb, eb + 2 * kWave, lane, s_mark);
+            raw_nxt = e2 < jb.e1 ? entry_at<kSym>(slab, a.slab_k, a, jb, rp_nxt, sk, e2) : jb.i0 + rp_nxt.r;
             const bool valid = eb + lane < jb.e1;
             float px, py, pz, pp;
             bool hit;
@@ -972,7 +1154,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         };
         for (int32_t eb = jb.e0; eb < jb.e1; eb += 2 * kWave) {
             batch(A, B, eb);
-            if (eb + kWave < jb.e1) batch(B, A, eb + kWave);
+            if (eb + kWave >= jb.e1) break;
+            batch(B, A, eb + kWave);
         }
         float jx = 0.f, jy = 0.f, jz = 0.f, jp = 0.f;
         int32_t jn = 0;
@@ -1080,6 +1263,26 @@ void launch_forces_t(const KParams& kp, const BatchView& bv, int precision, cons
 }
 
 }  // namespace
+
+hipError_t launch_skin_filter(const KParams& kp, int precision, const ForceArgs& a, int32_t* kept, int32_t* count,
+                              int32_t* kept_flag, hipStream_t s)
+{
+    if (a.n <= 0) return hipSuccess;
+    // a wave per 64-row chunk over a grid of at most 8,192 workgroups
+    const int blocks = ceil_div(ceil_div(a.n, kChunk), kBlock / kWave);
+    const dim3 grid(blocks < 8192 ? blocks : 8192), block(kBlock);
+    // (whether the slab's entries carry stencil codes is known here; with
+    // the slab unusable at run time the kernel passes the rows unfiltered)
+    const bool coded = a.slab_coded != 0;
+    if (precision == 0) {
+        if (coded) hipLaunchKernelGGL((k_skin_filter<false, true>), grid, block, 0, s, kp, a, kept, count, kept_flag);
+        else hipLaunchKernelGGL((k_skin_filter<false, false>), grid, block, 0, s, kp, a, kept, count, kept_flag);
+    } else {
+        if (coded) hipLaunchKernelGGL((k_skin_filter<true, true>), grid, block, 0, s, kp, a, kept, count, kept_flag);
+        else hipLaunchKernelGGL((k_skin_filter<true, false>), grid, block, 0, s, kp, a, kept, count, kept_flag);
+    }
+    return hipGetLastError();
+}
 
 // In a batch the weight exponent (and so kp.wmode) is shared by all systems.
 hipError_t launch_forces(const KParams& kp, const BatchView& bv, int precision, const ForceArgs& a, hipStream_t s)

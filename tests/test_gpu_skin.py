@@ -154,3 +154,22 @@ def test_skin_call_is_deterministic_and_tracks_the_oracle(precision):
         order = np.argsort(tag)
         assert np.max(np.abs(x[:, order] - xo)) < 1e-10
         assert np.max(np.abs(v[:, order] - vo)) < 1e-8
+
+
+@pytest.mark.parametrize("precision", [P.FP64, P.MIXED])
+def test_skin_steps_with_rows_longer_than_the_slab(precision):
+    """A dense blob whose rows at r_c + skin overflow the builder's slab: the
+    list comes from the CSR pass, each step's force pass then reads it
+    unfiltered (testing r < r_c itself); forces after a 4-step call match
+    the oracle, and a call's steps with an ordinary fluid (filtered rows)
+    match it too."""
+    for s in (di.clustered_fluid(seed=14, box=(12.0, 10.5, 7.0), n_cluster=300, n_rest=1500, size=2.0),
+              di.small_fluid(37)):
+        sim = _loaded(s, precision)
+        sim.step(4)
+        torch.cuda.synchronize()
+        assert sim.check_status() == 0
+        x, v, f, tag, typ = sim.host_state()
+        vh = v - 0.5 * s.dt * f
+        f_ref, _, _, scale = oracle.forces(s, x, vh, tag, typ, 4, skin=SKIN, with_scale=True)
+        _check_forces(f, f_ref, scale, precision)
