@@ -38,11 +38,13 @@ VALU_PEAK_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12
 # weights 5 / 6; the force (e.v, phi, components) 12; the row sum: three
 # compensated two-sums (18, mixed) or three adds (3, FP64).
 ALU_SLOTS_PER_PAIR = {"mixed": 193, "fp64": 182}
-# Phases of a step as dpd_step's events bracket them.  "integrate" is the one
-# pass over the state that ends a step and starts the next (the second
-# half-kick of step k - 1 fused with the half-kick and drift of step k, plus
-# the statistics), timed between events 0 and 1 of step k; the last step's
-# lone second half-kick (events 4 to 5) is added to it.
+# Phases of a step as dpd_step's events bracket them.  "integrate" is timed
+# between events 0 and 1 of step k plus events 4 to 5.  Without a skin the
+# force pass's row epilogue ends each step (second half-kick, and the next
+# step's half-kick and drift), so "forces" holds it and "integrate" only the
+# first step's phase 1 and the statistics' final sums; with a skin one pass
+# over the state ends a step and starts the next (events 0 to 1) and the last
+# step's second half-kick runs alone (events 4 to 5).
 PHASES = ["integrate", "reorder", "nlist", "forces"]
 
 
@@ -91,12 +93,21 @@ def force_bytes(n, nnz, n_bond_ends, precision):
     return n * per + 4 * nnz + 8 * n + 28 * n_bond_ends
 
 
-def phase_bytes(n, nnz, n_bond_ends, precision, n_cells, steps):
+def vv_bytes(n, steps):
+    """Algorithmic HBM bytes per step of the half-kicks the force pass's row
+    epilogue does (no skin): R v_h 24, x 24, tag, type 5; W drifted x, v 48,
+    tag, type 5; the last step of a call only R v 24, W v 24."""
+    return n * (106.0 * (steps - 1) + 48.0) / steps
+
+
+def phase_bytes(n, nnz, n_bond_ends, precision, n_cells, steps, fused=False):
     """Algorithmic HBM bytes of each phase of one step (each datum once).
 
     integrate: R x, v, F (72), tag, type (5); W drifted x, v (48), tag, type
     (5) every step, plus the last step's lone second half-kick (R v, F 48, W
-    v 24) spread over the steps.
+    v 24) spread over the steps.  With the half-kicks in the force pass
+    (fused: no skin) the phase is the first step's phase 1 alone, and the
+    forces phase adds vv_bytes.
     reorder: bin R x 24, W key, slot, cell 12; scan ~8 per cell; place R key,
     slot, tag 12, W tag, source 8; finalize R source, key 8, cell bounds 8,
     in-cell tags 12, x, v 48, type, cell 5, W x, v 48, tag, type, cell,
@@ -107,10 +118,11 @@ def phase_bytes(n, nnz, n_bond_ends, precision, n_cells, steps):
     """
     mixed = precision == "mixed"
     reorder = n * (36 + 20 + 8 + 8 + 12 + 53 + 65 + 16 + (16 if mixed else 0)) + 8 * n_cells
-    return {"integrate": 130.0 * n + 72.0 * n / steps,
+    forces = float(force_bytes(n, nnz, n_bond_ends, precision))
+    return {"integrate": 130.0 * n / steps if fused else 130.0 * n + 72.0 * n / steps,
             "reorder": float(reorder),
             "nlist": float(n * (16 + 4 + 4 + 8) + 4 * nnz + 8 * n_cells),
-            "forces": float(force_bytes(n, nnz, n_bond_ends, precision))}
+            "forces": forces + (vv_bytes(n, steps) if fused else 0.0)}
 
 
 def alu_roofline(form, precision):
@@ -164,9 +176,12 @@ def run_precision(P, torch, sysd, precision, steps, warmup, skin=0.0):
     n_bond_ends = 0 if sysd.partner is None else int((sysd.partner >= 0).sum())
     pairs = float(r[:, 5].mean())
     ms = total_ms / steps
-    fb = force_bytes(sysd.n, nnz, n_bond_ends, precision)
+    # without a skin the step's half-kicks run in the force pass's row
+    # epilogue: its launch moves their bytes too
+    fused = skin == 0
     n_cells = int(np.prod(P.cell_grid(params)))
-    pb = phase_bytes(sysd.n, nnz, n_bond_ends, precision, n_cells, steps)
+    pb = phase_bytes(sysd.n, nnz, n_bond_ends, precision, n_cells, steps, fused)
+    fb = pb["forces"]
     rebuilt = float(r[:, 7].mean())
     pb["reorder"] *= rebuilt
     pb["nlist"] *= rebuilt

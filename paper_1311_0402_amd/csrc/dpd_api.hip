@@ -243,7 +243,9 @@ WsLayout ws_layout(const Job& job, int32_t n, bool aos = false)
     w.slab_k = job.slab_k;
     w.slab = take(N * (size_t)w.slab_k * sizeof(int32_t));
     w.slab_flag = take(sizeof(int32_t));
-    w.red_part = take((size_t)3 * kRedBlocks * 2 * sizeof(double));
+    // (momentum and |v|^2 partials: kRedBlocks of them from the integration
+    // kernels, one per force workgroup from the force pass's epilogue)
+    w.red_part = take((size_t)3 * (kRedBlocks > kMaxForceGrid ? kRedBlocks : kMaxForceGrid) * 2 * sizeof(double));
     w.fred_part = take((size_t)kMaxForceGrid * 2 * sizeof(double));
     w.fsum_part = take((size_t)kRedBlocks * 2 * sizeof(double));
     w.bwd_part = take((size_t)backward_part_doubles(n, job.kp.n_types) * sizeof(double));
@@ -771,6 +773,14 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
         af.offset = kept_off;
         af.capacity = a.capacity;                        // kept rows are never longer than the list's
     }
+    // Mixed form without a skin: each step's second half-kick (and the next
+    // step's first half-kick and drift) runs in the force pass's row
+    // epilogue, which has the row's force at hand; its statistics follow the
+    // force pass.  The pass reads velocities only from the FP32 copies, never
+    // the state's v, which the last step's epilogue rewrites.  (The FP64
+    // pass keeps the separate kernel: with its operands held through the
+    // chunk it has no registers to spare.)
+    const bool fuse_vv = !skin && !job.bv.kps && mixed;
     for (int32_t k = 0; k < n_steps; ++k) {
         Job jk = job;
         int32_t* g = skin ? gates + (k & 1) : nullptr;
@@ -780,6 +790,8 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
             if (skin) DPD_TRY(launch_fill_i32(g, 1, 1, s), "rebuild flag");
             DPD_TRY(launch_vv1(kp, job.bv, n, st->x, st->v, st->f, st->tag, st->type, b.x, b.v, bvt, b.tag, b.type, s),
                     "vv1");
+        } else if (fuse_vv) {
+            // (the previous step's force pass did phase 2 and this phase 1)
         } else if (skin) {
             DPD_TRY(launch_fill_i32(g, 1, 0, s), "rebuild flag");
             sd.flag = g;
@@ -824,6 +836,20 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
             DPD_TRY(launch_scan(kept_off, (int64_t)n + 1, carve<int32_t>(ws, L.scan_part), s), "kept rows scan");
         }
         DPD_TRY(mark(k, 3), "event");
+        if (fuse_vv) {
+            ForceArgs av = a;
+            av.vv_v = st->v;
+            av.vv_part = red_part;
+            // the last step stores v; the others drift into the reorder's source
+            if (k < n_steps - 1) av.vv_drift = drift;
+            DPD_TRY(launch_forces(kp, job.bv, precision, av, s), "forces + vv2");
+            DPD_TRY(mark(k, 4), "event");
+            DPD_TRY(launch_reduce_final(n, red_part, force_grid(a), a.fred_part, force_grid(a),
+                                        d_reductions ? d_reductions + 8 * (int64_t)k : nullptr, nullptr, d_step,
+                                        d_status, s, nullptr, force_grid(a)), "reduce");
+            DPD_TRY(mark(k, 5), "event");
+            continue;
+        }
         DPD_TRY(launch_forces(kp, job.bv, precision, skin ? af : a, s), "forces");
         DPD_TRY(mark(k, 4), "event");
         if (k == n_steps - 1) {

@@ -125,6 +125,12 @@ hipError_t launch_nlist_check(int32_t n, const int32_t* offset, int64_t capacity
                               hipStream_t s);
 
 // ---- forces (k_force.hip) ----
+// the next step's phase 1 fused after phase 2: bx, bv (, bvt) from x and
+// the phase-2 velocity, and btag / btype copied (the outputs of launch_vv1)
+struct DriftArgs {
+    const double* x; const uint32_t* tag; const uint8_t* type;
+    double* bx; double* bv; double* bvt; uint32_t* btag; uint8_t* btype;
+};
 struct ForceArgs {
     int32_t n;
     const double* x; const double* v; const uint32_t* tag; const uint8_t* type;
@@ -147,6 +153,15 @@ struct ForceArgs {
     const double* v64;                            //   and (v~, type bits), double4 each (FP64 pass)
     int32_t pairs_once = -1;                      // pairs of one 64-row chunk evaluated once
                                                   //   (1), every entry (0), the pair mode's choice (-1)
+    // Single systems only (nullable): the step's second half-kick in the
+    // force pass's row epilogue, v = fma(dt/2, F, v_h) with v_h read from
+    // vv_v, as launch_vv2 computes it; with vv_drift.bx the next step's
+    // phase 1 follows (bx, bv, bvt, btag, btype), else v is stored back into
+    // vv_v.  Momentum and |v|^2 partials go to vv_part[3][grid][2] (reduce
+    // with red_stride = grid).  Nothing else in the pass may read vv_v.
+    double* vv_v = nullptr;
+    double* vv_part = nullptr;
+    DriftArgs vv_drift{};
 };
 hipError_t launch_forces(const KParams& kp, const BatchView& bv, int precision, const ForceArgs& a,
                          hipStream_t s);
@@ -187,12 +202,6 @@ hipError_t launch_sys_reduce(const BatchView& bat, int32_t n, double* v, const d
 hipError_t launch_counter(uint64_t* dst, const uint64_t* src, hipStream_t s);
 // particle -> system map of a batch
 hipError_t launch_sys_map(const BatchView& bat, int32_t n, uint16_t* sys_of, hipStream_t s);
-// the next step's phase 1 fused after phase 2: bx, bv (, bvt) from x and
-// the phase-2 velocity, and btag / btype copied (the outputs of launch_vv1)
-struct DriftArgs {
-    const double* x; const uint32_t* tag; const uint8_t* type;
-    double* bx; double* bv; double* bvt; uint32_t* btag; uint8_t* btype;
-};
 // phase 2 + momentum / |v|^2 partials (f == nullptr: the partials of v as it
 // is); also folds the force partials (fred_part, n_fred blocks) into
 // fsum_part[kRedBlocks][2]; drift (nullable) adds the next step's phase 1,
@@ -224,9 +233,11 @@ hipError_t launch_drift_skin(const KParams& kp, int32_t n, const SkinDriftArgs& 
 // (the last one: 1 when the step rebuilt the lists, read from *rebuilt, or
 // 1 when rebuilt is null); stats (nullable) gets (PE, pairs); increments
 // *d_step when non-null
+// (red_part[k] of component k starts at 2 k red_stride)
 hipError_t launch_reduce_final(int32_t n, const double* red_part, int n_red, const double* fred_part,
                                int n_fred, double* red, double* stats, uint64_t* d_step,
-                               int32_t* status, hipStream_t s, const int32_t* rebuilt = nullptr);
+                               int32_t* status, hipStream_t s, const int32_t* rebuilt = nullptr,
+                               int red_stride = kRedBlocks);
 
 // ---- border determination and ghosts (k_border.hip) ----
 struct BorderWs {

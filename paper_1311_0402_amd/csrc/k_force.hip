@@ -68,6 +68,78 @@ __device__ __forceinline__ void block_partials2(double a, double b, double* __re
     }
 }
 
+// The step's second half-kick for row i, in the force pass's row epilogue
+// (single systems): v = fma(dt/2, F, v_h) with v_h from a.vv_v, then with a
+// drift the next step's first half-kick and drift into the reorder's source
+// arrays, else v stored back; the arithmetic of k_vv2 with its drift, so the
+// state is the same bit for bit.  acc: this lane's momentum and |v|^2
+// accumulators (LDS, component k at acc[2k kBlock] and acc[(2k+1) kBlock]).
+// The row's operands of the half-kick (v_h and x, tag and type for the
+// drift), requested when the pass starts the row's chunk so their latency
+// hides behind the chunk's pairs.
+struct VVIn {
+    double v[3], x[3];
+    uint32_t tag;
+    uint8_t type;
+};
+
+__device__ __forceinline__ VVIn vv_load(const ForceArgs& a, int64_t N, int32_t i)
+{
+    VVIn o;
+    const DriftArgs& dr = a.vv_drift;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        o.v[k] = a.vv_v[k * N + i];
+        o.x[k] = dr.bx ? dr.x[k * N + i] : 0.0;
+    }
+    o.tag = dr.bx ? dr.tag[i] : 0u;
+    o.type = dr.bx ? dr.type[i] : (uint8_t)0;
+    return o;
+}
+
+__device__ __forceinline__ void vv_row(const KParams& kp, const ForceArgs& a, int64_t N, int32_t i, const VVIn& in,
+                                       double fx, double fy, double fz, double* __restrict__ acc)
+{
+    const DriftArgs& dr = a.vv_drift;
+    const double fk[3] = {fx, fy, fz};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int64_t o = k * N + i;
+        const double vn = __fma_rn(kp.half_dt, fk[k], in.v[k]);
+        if (dr.bx) {
+            const double vh = __fma_rn(kp.half_dt, fk[k], vn);
+            double xn = __fma_rn(kp.dt, vh, in.x[k]);
+            if (xn < 0.0) xn = xn + kp.L[k];
+            if (xn >= kp.L[k]) xn = xn - kp.L[k];
+            dr.bx[o] = xn;
+            dr.bv[o] = vh;
+            if (dr.bvt) dr.bvt[o] = __fma_rn(kp.lam_dt, fk[k], vn);
+        } else {
+            a.vv_v[o] = vn;
+        }
+        acc[2 * k * kBlock] += vn;
+        acc[(2 * k + 1) * kBlock] += vn * vn;
+    }
+    if (dr.bx) {
+        dr.btag[i] = in.tag;
+        dr.btype[i] = in.type;
+    }
+}
+
+// the workgroup's momentum and |v|^2 partials from the lanes' accumulators
+// (fixed order), into part[k][blockIdx][0..1] with stride gridDim.x
+__device__ __forceinline__ void vv_partials(const double* __restrict__ s_acc, double* __restrict__ part)
+{
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const double* src = s_acc + threadIdx.x * kBlock;
+        double t = 0.0;
+        for (int m = 0; m < kBlock; ++m) t += src[m];
+        const int k = threadIdx.x >> 1;
+        part[2 * ((int64_t)k * gridDim.x + blockIdx.x) + (threadIdx.x & 1)] = t;
+    }
+}
+
 // bonds and body force, shared by both precisions (FP64)
 __device__ __forceinline__ void add_bonds_body(const KParams& kp, const ForceArgs& a, int32_t i,
                                                double xi, double yi, double zi, double& fx, double& fy,
@@ -1014,7 +1086,7 @@ __global__ __launch_bounds__(kBlock) void k_skin_filter(KParams kp, ForceArgs a,
 
 // Mixed form.  Pair terms in FP32, the batch prefix sums in FP32, each row's
 // batch parts added with a two-sum, the result stored in FP64.
-template <int kWMode, bool kB, bool kSym>
+template <int kWMode, bool kB, bool kSym, bool kVV>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_force_mixed(KParams kp, BatchView bv, ForceArgs a, int32_t n_chunks)
 {
     __shared__ float s_a[kTab], s_g[kTab], s_s[kTab];
@@ -1030,6 +1102,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     // (ex | ey << 2 | ez << 4 -> ((1 - ex) l_x, (1 - ey) l_y, (1 - ez) l_z),
     // the cell lengths of the wave's system)
     __shared__ float4 s_off[(kBlock / kWave) * kWave];
+    // kVV (single systems): the step's half-kicks in the row epilogue, with
+    // their momentum and |v|^2 accumulators per lane
+    static_assert(!(kVV && kB), "the fused half-kick is for single systems");
+    constexpr bool vv = kVV;
+    __shared__ double s_vacc[kVV ? 6 * kBlock : 1];
+    if constexpr (kVV) {
+        for (int k = 0; k < 6; ++k) s_vacc[k * kBlock + threadIdx.x] = 0.0;
+    }
     const int lane = threadIdx.x & (kWave - 1);
     float4* const offs = s_off + (threadIdx.x - lane);
     auto stage_offsets = [&](const KParams& P) {
@@ -1079,6 +1159,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             skin = pp_sys.rl2 != pp_sys.rc2;
         }
         float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, pe_row = 0.f, np_row = 0.f;
+        // the half-kick's operands of this lane's row, requested now
+        VVIn vin{};
+        if constexpr (kVV) {
+            if (lane < jb.ni) vin = vv_load(a, N, jb.i0 + lane);
+        }
         // software pipeline: the list entry two batches ahead and the pair
         // operands one batch ahead are requested before a batch is evaluated;
         // two stages alternate (the loop is unrolled by two) so no operand is
@@ -1189,9 +1274,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             a.f[2 * N + i] = fz;
             if (want_pe) a.pe[i] = (double)pe_row + (double)jp + pe_b;
             if (want_np) a.npair[i] = (int32_t)np_row + jn;
+            if constexpr (kVV) vv_row(kp, a, N, i, vin, fx, fy, fz, s_vacc + threadIdx.x);
         }
     }
     if (a.fred_part) block_partials2(pe_tot, 0.5 * (double)np_tot, a.fred_part);
+    if constexpr (kVV) vv_partials(s_vacc, a.vv_part);
 }
 
 }  // namespace
@@ -1224,7 +1311,7 @@ int force_blocks(int32_t n, int precision)
     const int pr = precision ? 1 : 0;
     if (cache[dev][pr] == 0) {
         int per_cu = 0, cus = 0;
-        const void* f = pr ? reinterpret_cast<const void*>(&k_force_mixed<0, false, false>)
+        const void* f = pr ? reinterpret_cast<const void*>(&k_force_mixed<0, false, false, false>)
                            : reinterpret_cast<const void*>(&k_force_fp64<0, false, true>);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kBlock, 0) != hipSuccess || per_cu < 1)
             per_cu = 4;
@@ -1241,6 +1328,19 @@ int force_blocks(int32_t n, int precision)
 namespace {
 
 template <bool kB, bool kSym>
+void launch_mixed_t(const KParams& kp, const BatchView& bv, const ForceArgs& a, int32_t chunks, dim3 grid,
+                    hipStream_t s)
+{
+    const dim3 block(kBlock);
+    switch (kp.wmode) {
+    case 0: hipLaunchKernelGGL((k_force_mixed<0, kB, kSym, false>), grid, block, 0, s, kp, bv, a, chunks); break;
+    case 1: hipLaunchKernelGGL((k_force_mixed<1, kB, kSym, false>), grid, block, 0, s, kp, bv, a, chunks); break;
+    case 2: hipLaunchKernelGGL((k_force_mixed<2, kB, kSym, false>), grid, block, 0, s, kp, bv, a, chunks); break;
+    default: hipLaunchKernelGGL((k_force_mixed<3, kB, kSym, false>), grid, block, 0, s, kp, bv, a, chunks); break;
+    }
+}
+
+template <bool kB, bool kSym>
 void launch_forces_t(const KParams& kp, const BatchView& bv, int precision, const ForceArgs& a, hipStream_t s)
 {
     const dim3 grid(force_grid(a)), block(kBlock);
@@ -1252,13 +1352,19 @@ void launch_forces_t(const KParams& kp, const BatchView& bv, int precision, cons
         case 2: hipLaunchKernelGGL((k_force_fp64<2, kB, kSym>), grid, block, 0, s, kp, bv, a, chunks); break;
         default: hipLaunchKernelGGL((k_force_fp64<3, kB, kSym>), grid, block, 0, s, kp, bv, a, chunks); break;
         }
-    } else {
-        switch (kp.wmode) {
-        case 0: hipLaunchKernelGGL((k_force_mixed<0, kB, kSym>), grid, block, 0, s, kp, bv, a, chunks); break;
-        case 1: hipLaunchKernelGGL((k_force_mixed<1, kB, kSym>), grid, block, 0, s, kp, bv, a, chunks); break;
-        case 2: hipLaunchKernelGGL((k_force_mixed<2, kB, kSym>), grid, block, 0, s, kp, bv, a, chunks); break;
-        default: hipLaunchKernelGGL((k_force_mixed<3, kB, kSym>), grid, block, 0, s, kp, bv, a, chunks); break;
+    } else if constexpr (!kB) {
+        if (a.vv_part) {
+            switch (kp.wmode) {
+            case 0: hipLaunchKernelGGL((k_force_mixed<0, false, kSym, true>), grid, block, 0, s, kp, bv, a, chunks); break;
+            case 1: hipLaunchKernelGGL((k_force_mixed<1, false, kSym, true>), grid, block, 0, s, kp, bv, a, chunks); break;
+            case 2: hipLaunchKernelGGL((k_force_mixed<2, false, kSym, true>), grid, block, 0, s, kp, bv, a, chunks); break;
+            default: hipLaunchKernelGGL((k_force_mixed<3, false, kSym, true>), grid, block, 0, s, kp, bv, a, chunks); break;
+            }
+            return;
         }
+        launch_mixed_t<false, kSym>(kp, bv, a, chunks, grid, s);
+    } else {
+        launch_mixed_t<true, kSym>(kp, bv, a, chunks, grid, s);
     }
 }
 

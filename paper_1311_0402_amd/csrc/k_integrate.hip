@@ -339,7 +339,8 @@ __device__ double block_sum_strided(const double* __restrict__ src, int count, i
 }
 
 __global__ __launch_bounds__(kBlock) void k_reduce_final(int32_t n, const double* __restrict__ red_part,
-                                                         int n_red, const double* __restrict__ fred_part,
+                                                         int n_red, int red_stride,
+                                                         const double* __restrict__ fred_part,
                                                          int n_fred, double* __restrict__ red,
                                                          double* __restrict__ stats, uint64_t* d_step,
                                                          int32_t* status, const int32_t* __restrict__ rebuilt)
@@ -347,8 +348,8 @@ __global__ __launch_bounds__(kBlock) void k_reduce_final(int32_t n, const double
     double P[3] = {0.0, 0.0, 0.0}, v2 = 0.0, pe = 0.0, pairs = 0.0;
     if (red_part) {
         for (int k = 0; k < 3; ++k) {
-            P[k] = block_sum_strided(red_part + 2 * (int64_t)k * kRedBlocks, n_red, 2, 0);
-            v2 += block_sum_strided(red_part + 2 * (int64_t)k * kRedBlocks, n_red, 2, 1);
+            P[k] = block_sum_strided(red_part + 2 * (int64_t)k * red_stride, n_red, 2, 0);
+            v2 += block_sum_strided(red_part + 2 * (int64_t)k * red_stride, n_red, 2, 1);
         }
     }
     if (fred_part) {
@@ -432,10 +433,10 @@ hipError_t launch_drift_skin(const KParams& kp, int32_t n, const SkinDriftArgs& 
 
 hipError_t launch_reduce_final(int32_t n, const double* red_part, int n_red, const double* fred_part,
                                int n_fred, double* red, double* stats, uint64_t* d_step, int32_t* status,
-                               hipStream_t s, const int32_t* rebuilt)
+                               hipStream_t s, const int32_t* rebuilt, int red_stride)
 {
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, s, n, red_part, n_red, fred_part, n_fred,
-                       red, stats, d_step, status, rebuilt);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, s, n, red_part, n_red, red_stride, fred_part,
+                       n_fred, red, stats, d_step, status, rebuilt);
     return hipGetLastError();
 }
 

@@ -271,6 +271,35 @@ def test_steps_in_one_call_equal_single_step_calls(precision):
 
 
 @pytest.mark.parametrize("precision", [P.FP64, P.MIXED])
+def test_step_statistics_match_the_state(precision):
+    """Each step's statistics (in the mixed form summed by the force pass's
+    row epilogue, which also does the step's half-kicks): a 12-step call
+    gives the same rows, bit for bit, as 12 one-step calls, and the last
+    row's momentum, sum of v^2 and k_B T equal those of the velocities the
+    call leaves (sums taken on the host in a different order)."""
+    s = di.amphiphile(n=6000, seed=29)
+    a = _sorted_system(s, precision)
+    red_a = torch.zeros((12, 8), dtype=torch.float64, device="cuda")
+    a.step(12, reductions=red_a)
+    b = _sorted_system(s, precision)
+    red_b = torch.zeros((12, 8), dtype=torch.float64, device="cuda")
+    for k in range(12):
+        b.step(1, reductions=red_b[k:k + 1])
+    torch.cuda.synchronize()
+    assert a.check_status() == 0 and b.check_status() == 0
+    np.testing.assert_array_equal(red_a.cpu().numpy(), red_b.cpu().numpy())
+    v = a.host_state()[1]
+    r = red_a.cpu().numpy()[-1]
+    n = v.shape[1]
+    p = v.sum(axis=1)
+    v2 = float((v * v).sum())
+    np.testing.assert_allclose(r[:3], p, rtol=0, atol=1e-11 * np.abs(v).sum())
+    np.testing.assert_allclose(r[3], v2, rtol=1e-12)
+    kbt = (v2 - float((p * p).sum()) / n) / (3.0 * (n - 1))
+    np.testing.assert_allclose(r[6], kbt, rtol=1e-11)
+
+
+@pytest.mark.parametrize("precision", [P.FP64, P.MIXED])
 def test_step_call_forces_match_oracle_bonded(precision):
     """The path a multi-step dpd_step call runs (list rows read from the
     builder's slab with stencil-coded entries, FP64 pairs inside a chunk
