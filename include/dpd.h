@@ -157,6 +157,20 @@ const char* dpd_version(void);
  * DPD_EINVAL for another value. */
 int dpd_set_pair_evaluation(int32_t mode);
 
+/* Which neighbour-list builder single-system calls (dpd_build_neighbors,
+ * dpd_step) use, a process-wide host setting; every builder writes the same
+ * ordered rows (Sec. 3.3.2: a particle's neighbours in the ascending order
+ * of their cells' ranks over its 27 stencil cells, by index within a cell).
+ *   kind 0 (default): one workgroup per 8x4x4-cell tile, the tile's
+ *          neighbourhood staged in LDS;
+ *   kind 1: one wave per 2x2x2-cell block with ballot compaction (its slab
+ *          entries carry no stencil code);
+ *   kind 2: one lane per particle over global memory.
+ * Batches choose theirs with dpd_batch_set_tiles.  Applies to calls
+ * enqueued afterwards.  Returns the previous kind, or DPD_EINVAL for
+ * another value. */
+int dpd_set_list_builder(int32_t kind);
+
 /* Cells per side for these parameters (rule in the header comment).
  * Returns DPD_EINVAL when the box holds fewer than 3 or more than 1023 cells
  * per side. */

@@ -8,11 +8,12 @@ library was not built.
 from .dpd import (FP64, MIXED, Batch, Cells, NList, Params, State, System, Tiles, alloc_workspace,
                   border_workspace, cell_grid, default_capacity, dpd_bin_reorder, dpd_border_lists,
                   dpd_border_pack, dpd_border_unpack, dpd_build_neighbors, dpd_forces, dpd_forces_backward,
-                  dpd_step, dpd_step_backward, ghost_records, set_pair_evaluation, workspace_bytes)
+                  dpd_step, dpd_step_backward, ghost_records, set_list_builder, set_pair_evaluation,
+                  workspace_bytes)
 from ._abi import DPDError
 
 __all__ = ["FP64", "MIXED", "Batch", "Cells", "NList", "Params", "State", "System", "Tiles", "alloc_workspace",
            "border_workspace", "dpd_border_lists", "dpd_border_pack", "dpd_border_unpack", "ghost_records",
            "cell_grid", "default_capacity", "dpd_bin_reorder", "dpd_build_neighbors", "dpd_forces",
-           "dpd_forces_backward", "dpd_step", "dpd_step_backward", "set_pair_evaluation", "workspace_bytes",
-           "DPDError"]
+           "dpd_forces_backward", "dpd_step", "dpd_step_backward", "set_list_builder", "set_pair_evaluation",
+           "workspace_bytes", "DPDError"]

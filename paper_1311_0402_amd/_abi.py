@@ -113,6 +113,7 @@ SIGNATURES = {
     "dpd_last_error": (C.c_char_p, []),
     "dpd_version": (C.c_char_p, []),
     "dpd_set_pair_evaluation": (C.c_int, [C.c_int32]),
+    "dpd_set_list_builder": (C.c_int, [C.c_int32]),
     "dpd_cell_grid": (C.c_int, [PP, P]),
     "dpd_workspace_bytes": (C.c_size_t, [PP, C.c_int32, C.c_int32]),
     "dpd_bin_reorder": (C.c_int, [PP, PS, PS, PC, P, P, P, C.c_size_t, P]),

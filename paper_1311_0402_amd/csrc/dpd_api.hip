@@ -3,6 +3,7 @@
 // Host-side work only: argument validation, derived parameters, workspace
 // carving and the order in which the kernels of one time step are enqueued.
 // No entry point synchronises, allocates device memory or throws.
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -14,6 +15,8 @@
 #include <vector>
 
 #include "../../include/dpd.h"
+#include <atomic>
+
 #include "dpd_launch.h"
 
 namespace dpd {
@@ -199,6 +202,9 @@ struct Job {
     Gate gate = nullptr; // skin steps: rebuild only while *gate != 0
 };
 
+// the list builder of single-system calls (dpd_set_list_builder)
+std::atomic<int> g_list_builder{0};
+
 Job single_job(const KParams& kp, int32_t n)
 {
     Job j;
@@ -211,7 +217,7 @@ Job single_job(const KParams& kp, int32_t n)
     j.slab_k = nlist_slab_width(n / vol, kp.rl2);
     j.force_grid = 0;
     j.nlist_waves = 4;
-    j.nlist_kind = 0;
+    j.nlist_kind = g_list_builder.load(std::memory_order_relaxed);
     return j;
 }
 
@@ -580,6 +586,12 @@ int dpd_set_pair_evaluation(int32_t mode)
 {
     if (mode < 0 || mode > 2) return fail(DPD_EINVAL, "pair evaluation mode must be 0, 1 or 2");
     return set_pair_mode(mode);
+}
+
+int dpd_set_list_builder(int32_t kind)
+{
+    if (kind < 0 || kind > 2) return fail(DPD_EINVAL, "list builder kind must be 0, 1 or 2");
+    return g_list_builder.exchange(kind);
 }
 
 int dpd_cell_grid(const dpd_params* p, int32_t nc[3])

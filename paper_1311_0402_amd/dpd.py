@@ -186,6 +186,16 @@ def set_pair_evaluation(mode: int) -> int:
     return int(rc)
 
 
+def set_list_builder(kind: int) -> int:
+    """The neighbour-list builder of single-system calls: 0 (default) tile
+    builder, 1 wave per 2x2x2-cell block, 2 lane per particle; all write the
+    same rows.  Returns the previous kind."""
+    rc = lib().dpd_set_list_builder(int(kind))
+    if rc < 0:
+        check(rc, "dpd_set_list_builder")
+    return int(rc)
+
+
 def workspace_bytes(params: Params, n: int, precision: int = FP64) -> int:
     nb = lib().dpd_workspace_bytes(C.byref(params.c()), int(n), int(precision))
     if nb == 0:

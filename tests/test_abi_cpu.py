@@ -110,6 +110,19 @@ def test_null_and_size_errors_before_launch():
     assert b"workspace" in lib.dpd_last_error()
 
 
+def test_process_wide_settings_validate_and_return_the_previous_value():
+    lib = _abi.lib()
+    assert lib.dpd_set_list_builder(3) == _abi.DPD_EINVAL
+    assert lib.dpd_set_list_builder(-1) == _abi.DPD_EINVAL
+    assert lib.dpd_set_list_builder(1) == 0          # default: the tile builder
+    assert lib.dpd_set_list_builder(2) == 1
+    assert lib.dpd_set_list_builder(0) == 2
+    assert lib.dpd_set_pair_evaluation(5) == _abi.DPD_EINVAL
+    prev = lib.dpd_set_pair_evaluation(0)
+    assert prev == 2                                # default: pairs once in the FP64 form
+    assert lib.dpd_set_pair_evaluation(prev) == 0
+
+
 _RANK_PROBE = r"""
 #include <cstdio>
 #include "dpd_common.h"

@@ -156,6 +156,41 @@ def test_skin_call_is_deterministic_and_tracks_the_oracle(precision):
         assert np.max(np.abs(v[:, order] - vo)) < 1e-8
 
 
+@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("precision", [P.FP64, P.MIXED])
+def test_skin_steps_with_the_other_list_builders(kind, precision):
+    """The block builder (kind 1: slab entries without stencil codes, so the
+    filter and the mixed force pass take each cell offset from the two
+    cells) and the lane builder (kind 2): the rows at r_c + skin of the
+    loaded state are the oracle's, and after a 12-step call the forces match
+    the oracle's at its final state and the list the call leaves (its last
+    rebuild's) holds every pair now inside r_c, rows strictly ascending."""
+    s = di.amphiphile(n=6000, seed=38)
+    prev = P.set_list_builder(kind)
+    try:
+        sim = _loaded(s, precision)
+        x0 = sim.host_state()[0]
+        off0, idx0 = sim.host_nlist()
+        sim.step(12)
+        torch.cuda.synchronize()
+        assert sim.check_status() == 0
+        x, v, f, tag, typ = sim.host_state()
+        off, idx = sim.host_nlist()
+    finally:
+        P.set_list_builder(prev)
+    off_ref, idx_ref = oracle.neighbors(x0, s.box, s.r_c + SKIN)
+    np.testing.assert_array_equal(off0, off_ref)
+    np.testing.assert_array_equal(idx0, idx_ref)
+    vh = v - 0.5 * s.dt * f
+    f_ref, _, _, scale = oracle.forces(s, x, vh, tag, typ, 12, skin=SKIN, with_scale=True)
+    _check_forces(f, f_ref, scale, precision)
+    off_rc, idx_rc = oracle.neighbors(x, s.box, s.r_c)
+    for i in range(s.n):
+        row = idx[off[i]:off[i + 1]]
+        assert np.all(np.diff(row) > 0)
+        assert np.isin(idx_rc[off_rc[i]:off_rc[i + 1]], row).all(), i
+
+
 @pytest.mark.parametrize("precision", [P.FP64, P.MIXED])
 def test_skin_steps_with_rows_longer_than_the_slab(precision):
     """A dense blob whose rows at r_c + skin overflow the builder's slab: the
