@@ -587,7 +587,8 @@ def main():
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware counters: 2 steps per precision, then a plain "
                          "device copy of COPY_BYTES as the counter calibration; prints no bench line")
-    ap.add_argument("--batched-steps", type=int, default=100)
+    ap.add_argument("--batched-steps", type=int, default=500,
+                    help="timed steps of the 256-system batch (the batched configuration's length)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the border-exchange and numerics A/B measurements")

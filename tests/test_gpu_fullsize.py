@@ -86,6 +86,46 @@ def test_fullsize_step_call_forces_and_rows(full, precision):
     torch.cuda.empty_cache()
 
 
+def _check_sample(s, sim, step, precision):
+    x, v, f, tag, typ = sim.host_state()
+    vh = v - 0.5 * s.dt * f
+    q = _sample(s.n, seed=step)
+    off_ref, idx_ref = oracle.neighbors(x, s.box, 1.0, query=q)
+    f_ref, _, _, scale = oracle.forces(s, x, vh, tag, typ, step, nbr=(off_ref, idx_ref), query=q,
+                                       with_scale=True)
+    d = np.linalg.norm(f[:, q] - f_ref, axis=0)
+    if precision == P.FP64:
+        assert np.all(d <= 1e-12 * scale), (step, float(np.max(d / scale)))
+    else:
+        rel = np.linalg.norm(f[:, q] - f_ref) / np.linalg.norm(f_ref)
+        assert rel <= 1e-5, (step, rel)
+        rms = np.sqrt(np.mean(np.sum(f_ref**2, axis=0)))
+        assert np.percentile(d / rms, 99.9) <= 1e-5, step
+    return v
+
+
+@pytest.mark.parametrize("precision", [P.FP64, P.MIXED])
+def test_fullsize_thousand_steps_track_the_oracle(full, precision):
+    """The benchmark configuration's full length: 1,000 steps in two 500-step
+    dpd_step calls; after each, the forces of a seeded 1,000-row sample
+    equal the oracle's at that state (bars as above), momentum stays at
+    round-off and k_B T near the Eq (9) value sigma^2 / (2 gamma) = 1."""
+    s = full
+    sim = _loaded(s, precision)
+    red = torch.zeros((500, 8), dtype=torch.float64, device="cuda")
+    for k in (500, 1000):
+        sim.step(500, reductions=red)
+        torch.cuda.synchronize()
+        assert sim.check_status() == 0
+        v = _check_sample(s, sim, k, precision)
+        r = red.cpu().numpy()
+        assert np.abs(r[:, :3]).max() < 1e-6 * np.abs(v).sum(), k
+        assert abs(r[-1, 6] - 1.0) < 0.05, (k, r[-1, 6])
+    assert sim.step_count == 1000
+    del sim
+    torch.cuda.empty_cache()
+
+
 def test_fullsize_border_lists_and_records(full):
     """The six send lists of the benchmark box (one brick spanning it, halo
     width r_c; about 550,000 entries) after the reorder, bit for bit, and
