@@ -200,6 +200,8 @@ def run_precision(P, torch, sysd, precision, steps, warmup, skin=0.0):
         "phase_ms": {k: float(v) for k, v in zip(PHASES, phase_ms)},
         "force_ms": float(phase_ms[3]),
         "force_bytes": fb,
+        # of which the step's half-kicks in the force pass's row epilogue
+        "force_bytes_half_kicks": pb["forces"] - float(force_bytes(sysd.n, nnz, n_bond_ends, precision)),
         "phase_gbs": {k: pb[k] / (phase_ms[q] * 1e-3) / 1e9 for q, k in enumerate(PHASES)},
         "phase_hbm_frac": hbm_frac,
         "kbt_last": float(r[-1, 6]),
@@ -655,7 +657,11 @@ def main():
     achieved = fb / (head["force_ms"] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": "forces", "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(head_name),
-                "algorithmic_bytes": fb, "dominant_phase": dom,
+                "algorithmic_bytes": fb,
+                # the mixed step's force launch also does the half-kicks (a1, a10)
+                "algorithmic_bytes_half_kicks": head["force_bytes_half_kicks"],
+                "kernel_name": "k_force_mixed<..., kVV = true>" if head_name == "mixed" else "k_force_fp64",
+                "dominant_phase": dom,
                 # the bound the counters show: VALU issue, against the
                 # algorithmic work of each unique pair evaluated once
                 "alu": alu_roofline(head, head_name)}
