@@ -15,8 +15,6 @@
 #include <vector>
 
 #include "../../include/dpd.h"
-#include <atomic>
-
 #include "dpd_launch.h"
 
 namespace dpd {
