@@ -309,6 +309,7 @@ __device__ __forceinline__ int32_t entry_code(int32_t raw, bool coded)
 }
 
 struct PairJob {
+    const int32_t* cs;   // the chunk's first slab row (rows at cs[r * K], 32-bit offsets), or null
     int32_t i0, ni;      // first particle of the chunk, particles in it
     int32_t e0, e1;      // the entries walked (CSR positions, or with pairs
                          //   once the kept entries numbered from e0)
@@ -409,6 +410,7 @@ __device__ __forceinline__ PairJob chunk_job(const BatchView& bv, const ForceArg
         j.i0 = c * kChunk;
     }
     j.ni = end - j.i0 < kChunk ? end - j.i0 : kChunk;
+    j.cs = slab ? slab + (int64_t)j.i0 * a.slab_k : nullptr;
     const int32_t own = j.i0 + (lane < j.ni ? lane : j.ni - 1);
     j.e0 = ok ? a.offset[j.i0] : 0;
     j.e1 = ok ? a.offset[j.i0 + j.ni] : 0;
@@ -515,14 +517,15 @@ __device__ __forceinline__ int32_t entry_at(const int32_t* __restrict__ slab, in
                                             const ForceArgs& a, const PairJob& jb, const RowPos& rp,
                                             const RowSkip& sk, int32_t e)
 {
+    // (slab rows through the chunk's base: a 32-bit offset per lane)
     if constexpr (kSym) {
         int32_t p = e - rp.start;
         const int32_t skip = sk.skip[rp.r];
         p += p >= (skip & 0xffff) ? (skip >> 16) : 0;
-        if (slab) return slab[(int64_t)(jb.i0 + rp.r) * slab_k + p];
+        if (slab) return jb.cs[rp.r * slab_k + p];
         return a.index[sk.raw[rp.r] + p];
     } else {
-        return slab ? slab[(int64_t)(jb.i0 + rp.r) * slab_k + (e - rp.start)] : a.index[e];
+        return slab ? jb.cs[rp.r * slab_k + (e - rp.start)] : a.index[e];
     }
 }
 
