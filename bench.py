@@ -184,10 +184,18 @@ def run_precision(P, torch, sysd, precision, steps, warmup, skin=0.0):
     fused = skin == 0 and precision == "mixed"
     n_cells = int(np.prod(P.cell_grid(params)))
     pb = phase_bytes(sysd.n, nnz, n_bond_ends, precision, n_cells, steps, fused)
+    if skin > 0:
+        # with a skin the force pass reads the filtered rows: the ordered
+        # pairs inside r_c, not the list built at r_c + skin
+        pb["forces"] = float(force_bytes(sysd.n, int(round(2 * pairs)), n_bond_ends, precision))
     fb = pb["forces"]
     rebuilt = float(r[:, 7].mean())
     pb["reorder"] *= rebuilt
     pb["nlist"] *= rebuilt
+    if skin > 0:
+        # every step's filter: R the list's entries 4 each, W the kept
+        # entries 4 each, row counts and their scan ~12 per particle
+        pb["nlist"] += 4.0 * nnz + 8.0 * pairs + 12.0 * sysd.n
     hbm_frac = {k: pb[k] / (phase_ms[q] * 1e-3) / 1e9 / HBM_PEAK_GBS for q, k in enumerate(PHASES)}
     # algorithmic bytes can only exceed what HBM moves if a phase's window
     # were mis-attributed (or its data served from cache)
@@ -204,7 +212,7 @@ def run_precision(P, torch, sysd, precision, steps, warmup, skin=0.0):
         "force_ms": float(phase_ms[3]),
         "force_bytes": fb,
         # of which the step's half-kicks in the force pass's row epilogue
-        "force_bytes_half_kicks": pb["forces"] - float(force_bytes(sysd.n, nnz, n_bond_ends, precision)),
+        "force_bytes_half_kicks": vv_bytes(sysd.n, steps) if fused else 0.0,
         "phase_gbs": {k: pb[k] / (phase_ms[q] * 1e-3) / 1e9 for q, k in enumerate(PHASES)},
         "phase_hbm_frac": hbm_frac,
         "kbt_last": float(r[-1, 6]),
