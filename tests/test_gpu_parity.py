@@ -231,6 +231,44 @@ def test_step_teacher_forced_100():
     assert sim.check_status() == 0
 
 
+@pytest.mark.parametrize("precision", [P.FP64, P.MIXED])
+def test_step_with_velocity_prediction(precision):
+    """Groot-Warren prediction factor lambda = 0.65 (the forces see
+    v~ = v + lambda dt F instead of the half-step velocity): each of 8 steps
+    against one oracle step from the GPU's own previous state (positions
+    bit-exact, forces within the form's bar), and a 12-step call equal to 12
+    one-step calls bit for bit (in the mixed form the predicted velocity is
+    then written by the force pass's row epilogue)."""
+    s = di.uniform_fluid(2400, (9.0, 10.0, 8.9), 41, lam=0.65)
+    sim = _sorted_system(s, precision)
+    prev = sim.host_state()
+    for k in range(1, 9):
+        sim.step(1)
+        torch.cuda.synchronize()
+        assert sim.check_status() == 0
+        cur = sim.host_state()
+        xo, vo, fo, _ = oracle.step(s, prev[0], prev[1], prev[2], prev[3], prev[4], k)
+        o_prev = np.argsort(prev[3])
+        o_cur = np.argsort(cur[3])
+        np.testing.assert_array_equal(cur[0][:, o_cur], xo[:, o_prev], err_msg=f"step {k} x")
+        vt = prev[1] + s.lam * s.dt * prev[2]
+        _, _, _, scale = oracle.forces(s, xo, vt, prev[3], prev[4], k, with_scale=True)
+        if precision == P.FP64:
+            _check_fp64(cur[2][:, o_cur], fo[:, o_prev], scale[o_prev])
+        else:
+            rel = np.linalg.norm(cur[2][:, o_cur] - fo[:, o_prev]) / np.linalg.norm(fo)
+            assert rel <= MIXED_TOL, (k, rel)
+        prev = cur
+    a = _sorted_system(s, precision)
+    a.step(12)
+    b = _sorted_system(s, precision)
+    for _ in range(12):
+        b.step(1)
+    torch.cuda.synchronize()
+    for u, w in zip(a.host_state(), b.host_state()):
+        np.testing.assert_array_equal(u, w)
+
+
 def test_step_deterministic_and_resumable():
     s = di.amphiphile(n=6000, seed=2)
     a = _sorted_system(s)
