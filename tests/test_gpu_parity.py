@@ -231,6 +231,30 @@ def test_step_teacher_forced_100():
     assert sim.check_status() == 0
 
 
+@pytest.mark.parametrize("s_exp", [1.0, 2.0, 0.25])
+@pytest.mark.parametrize("precision", [P.FP64, P.MIXED])
+def test_weight_exponents(s_exp, precision):
+    """The weight w_R = (1 - r/r_c)^s of Eq (8) beyond s = 1/2: s = 1 and 2
+    (the pass's own branches) and a general s = 1/4 (a power): the forces
+    of the loaded state and of a 5-step call's final state against the
+    oracle (FP64 within 1e-12 S_i, mixed within 1e-5 of |F|)."""
+    s = di.uniform_fluid(3000, (10.0, 10.0, 10.0), 43, s=s_exp)
+    sim = _sorted_system(s, precision)
+    for k in (0, 5):
+        if k:
+            sim.step(k)
+            torch.cuda.synchronize()
+        assert sim.check_status() == 0
+        x, v, f, tag, typ = sim.host_state()
+        vh = v - 0.5 * s.dt * f if k else v
+        f_ref, _, _, scale = oracle.forces(s, x, vh, tag, typ, k, with_scale=True)
+        if precision == P.FP64:
+            _check_fp64(f, f_ref, scale)
+        else:
+            rel = np.linalg.norm(f - f_ref) / np.linalg.norm(f_ref)
+            assert rel <= MIXED_TOL, (s_exp, k, rel)
+
+
 @pytest.mark.parametrize("precision", [P.FP64, P.MIXED])
 def test_step_with_velocity_prediction(precision):
     """Groot-Warren prediction factor lambda = 0.65 (the forces see
