@@ -538,7 +538,8 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
     __shared__ int32_t s_lstart[kTU + 1];
     constexpr int kTilePos = tile_pos<kW>();
     __shared__ float4 s_pos[kTilePos + kStepW - 1];   // spare slots: a step's reads may run past the end
-    __shared__ uint32_t s_sten[kTC * 27];      // before the sort: union cell of every staged slot
+    // (two spare entries: the walk reads up to two entries past a cell's last)
+    __shared__ uint32_t s_sten[kTC * 27 + 2];  // before the sort: union cell of every staged slot
     __shared__ uint8_t s_nne[kTC];
     __shared__ int32_t s_w[kW];
     uint16_t* s_seg = reinterpret_cast<uint16_t*>(s_sten);
@@ -622,8 +623,14 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
                 if (a < b) st[m++] = (uint32_t)a | ((uint32_t)b << 12) | (code << kSlabCodeShift);
             }
             s_nne[tid] = (uint8_t)m;
+            // the walk reads up to two entries past a cell's last: empty
+            // ranges at slot 0
+            for (int32_t q = m; q < 27; ++q) st[q] = 0u;
+        } else {
+            for (int32_t q = 0; q < 27; ++q) s_sten[tid * 27 + q] = 0u;
         }
     }
+    if (tid < 2) s_sten[kTC * 27 + tid] = 0u;
     __syncthreads();
 
     // ---- the walk: one lane per particle of the tile ----
@@ -654,45 +661,49 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
         const int32_t nne = s_nne[ci];                   // >= 1: i's own cell is in its stencil
         // byte offset of this lane's next entry in the tile's slab rows
         const int32_t row0 = (i - g.i_lo) * slab_k * (int32_t)sizeof(int32_t);
-        int32_t rb = row0, q = 0;
-        uint32_t ent = st[0];
-        uint32_t ent_n = st[nne > 1 ? 1 : 0];
-        int32_t k = (int32_t)(ent & 0xFFFu), e = (int32_t)((ent >> 12) & 0xFFFu);
-        uint32_t cs = ent & kCodeBits;
-        auto test = [&](const float4& w) {
+        int32_t rb = row0;
+        // walk state: the current stencil entry cur (its cell's slots end at
+        // bits 12..23, its slab code in the top bits), the candidate slot k,
+        // and the entry after cur (ent_n, at index pn)
+        uint32_t cur = st[0];
+        int32_t pn = 1;
+        uint32_t ent_n = st[1];
+        int32_t k = (int32_t)(cur & 0xFFFu);
+        auto test = [&](const float4& w, uint32_t ent) {
             const float dx = wi.x - w.x, dy = wi.y - w.y, dz = wi.z - w.z;
             const float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
             const int32_t j = __float_as_int(w.w);
-            bool hit = j != i && r2 < lo;
-            if (j != i && !hit && r2 < hi) hit = exact_hit(P, x, N, i, j);
+            const bool near = r2 < lo;
+            bool hit = near && j != i;
+            // i itself has r2 = 0 < lo, so the band never holds it
+            if (!near && r2 < hi) hit = exact_hit(P, x, N, i, j);
             if (hit) {
-                __builtin_amdgcn_raw_buffer_store_b32((int32_t)((uint32_t)j | cs), rows, rb, 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b32((int32_t)((ent & kCodeBits) | (uint32_t)j), rows, rb, 0, 0);
                 rb += (int32_t)sizeof(int32_t);
             }
         };
         // one step on the candidates at slots k .. k + kStepW - 1 (those below
-        // the cell's end), requesting the next step's into nxt and the
-        // stencil entry after the next; false when the walk has ended
-        auto step = [&](const StepW& cur, StepW& nxt) {
-            const bool adv = k + kStepW >= e;
-            const int32_t k2 = adv ? (int32_t)(ent_n & 0xFFFu) : k + kStepW;
-            const int32_t e2 = adv ? (int32_t)((ent_n >> 12) & 0xFFFu) : e;
-            const uint32_t cs2 = adv ? (ent_n & kCodeBits) : cs;
-            const int32_t q2 = q + (adv ? 1 : 0);
-            const bool more = q2 < nne;
-            const float4* pn = s_pos + (more ? k2 : k);
+        // the cell's end), advancing the state and requesting the next step's
+        // candidates into nxt and the entry after the next; false when the
+        // walk has ended.  Past the end the state runs on into the following
+        // entries of the table (the next cell's, or the zeroed ones), whose
+        // slots are valid reads and never tested.
+        auto step = [&](const StepW& cw, StepW& nxt) {
+            const uint32_t ent = cur;
+            const int32_t left = (int32_t)((ent >> 12) & 0xFFFu) - k;   // >= 1
+            const bool adv = left <= kStepW;
+            k = adv ? (int32_t)(ent_n & 0xFFFu) : k + kStepW;
+            cur = adv ? ent_n : cur;
+            pn += adv ? 1 : 0;
+            const float4* p = s_pos + k;
 #pragma unroll
-            for (int m = 0; m < kStepW; ++m) nxt.w[m] = pn[m];
-            const int32_t qn = q2 + 1 < nne ? q2 + 1 : nne - 1;
-            const uint32_t ent_nn = st[qn];
-            test(cur.w[0]);
+            for (int m = 0; m < kStepW; ++m) nxt.w[m] = p[m];
+            ent_n = st[pn];
+            test(cw.w[0], ent);
 #pragma unroll
             for (int m = 1; m < kStepW; ++m)
-                if (k + m < e) test(cur.w[m]);
-            if (!more) return false;
-            ent_n = adv ? ent_nn : ent_n;
-            k = k2; e = e2; q = q2; cs = cs2;
-            return true;
+                if (m < left) test(cw.w[m], ent);
+            return pn <= nne;
         };
         StepW s0, s1;
 #pragma unroll
