@@ -453,6 +453,9 @@ constexpr int tile_pos() { return (kW * kWave * 29 / 10 + 15) / 16 * 16; }
 constexpr int kTFX = kTileX / 2 + 1, kTFY = kTileY / 2 + 1, kTFZ = kTileZ / 2 + 1;
 // candidates a lane tests per step of the walk, and their operands
 constexpr int kStepW = 2;
+// a byte offset past the slab rows of every tile (a tile's rows span less
+// than INT32_MAX - 4 tile_pos bytes, or it is left to the lane builder)
+constexpr int32_t kDropOff = 0x7FFFFFF0;
 struct StepW {
     float4 w[kStepW];
 };
@@ -669,18 +672,23 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
         int32_t pn = 1;
         uint32_t ent_n = st[1];
         int32_t k = (int32_t)(cur & 0xFFFu);
-        auto test = [&](const float4& w, uint32_t ent) {
+        auto test = [&](const float4& w, uint32_t ent, bool valid) {
             const float dx = wi.x - w.x, dy = wi.y - w.y, dz = wi.z - w.z;
             const float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
             const int32_t j = __float_as_int(w.w);
             const bool near = r2 < lo;
-            bool hit = near && j != i;
-            // i itself has r2 = 0 < lo, so the band never holds it
-            if (!near && r2 < hi) hit = exact_hit(P, x, N, i, j);
-            if (hit) {
-                __builtin_amdgcn_raw_buffer_store_b32((int32_t)((ent & kCodeBits) | (uint32_t)j), rows, rb, 0, 0);
-                rb += (int32_t)sizeof(int32_t);
+            bool hit = valid && near && j != i;
+            // i itself has r2 = 0 < lo, so the band never holds it; the band
+            // is rare, so the wave branches on its ballot
+            const bool band = valid && !near && r2 < hi;
+            if (__builtin_expect(__ballot(band) != 0ull, 0)) {
+                if (band) hit = exact_hit(P, x, N, i, j);
             }
+            // every lane stores: a miss at an offset past the rows' range,
+            // which the buffer's range check drops (no branch per candidate)
+            __builtin_amdgcn_raw_buffer_store_b32((int32_t)((ent & kCodeBits) | (uint32_t)j), rows,
+                                                  hit ? rb : kDropOff, 0, 0);
+            rb += hit ? (int32_t)sizeof(int32_t) : 0;
         };
         // one step on the candidates at slots k .. k + kStepW - 1 (those below
         // the cell's end), advancing the state and requesting the next step's
@@ -699,10 +707,9 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
 #pragma unroll
             for (int m = 0; m < kStepW; ++m) nxt.w[m] = p[m];
             ent_n = st[pn];
-            test(cw.w[0], ent);
+            test(cw.w[0], ent, true);
 #pragma unroll
-            for (int m = 1; m < kStepW; ++m)
-                if (m < left) test(cw.w[m], ent);
+            for (int m = 1; m < kStepW; ++m) test(cw.w[m], ent, m < left);
             return pn <= nne;
         };
         StepW s0, s1;
