@@ -39,8 +39,8 @@ VALU_PEAK_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12
 # compensated two-sums (18, mixed) or three adds (3, FP64).
 ALU_SLOTS_PER_PAIR = {"mixed": 193, "fp64": 182}
 # Phases of a step as dpd_step's events bracket them.  "integrate" is timed
-# between events 0 and 1 of step k plus events 4 to 5.  In the mixed form
-# without a skin the force pass's row epilogue ends each step (second
+# between events 0 and 1 of step k plus events 4 to 5.  Without a skin the
+# force pass's row epilogue ends each step (second
 # half-kick, and the next step's half-kick and drift), so "forces" holds it
 # and "integrate" only the first step's phase 1 and the statistics' final
 # sums; otherwise one pass over the state ends a step and starts the next
@@ -95,8 +95,8 @@ def force_bytes(n, nnz, n_bond_ends, precision):
 
 
 def vv_bytes(n, steps):
-    """Algorithmic HBM bytes per step of the half-kicks the mixed force
-    pass's row epilogue does (no skin): R v_h 24, x 24, tag, type 5; W
+    """Algorithmic HBM bytes per step of the half-kicks the force pass's row
+    epilogue does (no skin): R v_h 24, x 24, tag, type 5; W
     drifted x, v 48, tag, type 5; the last step of a call only R v 24, W v
     24."""
     return n * (106.0 * (steps - 1) + 48.0) / steps
@@ -108,7 +108,7 @@ def phase_bytes(n, nnz, n_bond_ends, precision, n_cells, steps, fused=False):
     integrate: R x, v, F (72), tag, type (5); W drifted x, v (48), tag, type
     (5) every step, plus the last step's lone second half-kick (R v, F 48, W
     v 24) spread over the steps.  With the half-kicks in the force pass
-    (fused: the mixed form without a skin) the phase is the first step's
+    (fused: either form without a skin) the phase is the first step's
     phase 1 alone, and the forces phase adds vv_bytes.
     reorder: bin R x 24, W key, slot, cell 12; scan ~8 per cell; place R key,
     slot, tag 12, W tag, source 8; finalize R source, key 8, cell bounds 8,
@@ -178,10 +178,9 @@ def run_precision(P, torch, sysd, precision, steps, warmup, skin=0.0):
     n_bond_ends = 0 if sysd.partner is None else int((sysd.partner >= 0).sum())
     pairs = float(r[:, 5].mean())
     ms = total_ms / steps
-    # in the mixed form without a skin the step's half-kicks run in the force
-    # pass's row epilogue: its launch moves their bytes too (the FP64 form
-    # keeps its separate kick-drift pass)
-    fused = skin == 0 and precision == "mixed"
+    # without a skin the step's half-kicks run in the force pass's row
+    # epilogue: its launch moves their bytes too
+    fused = skin == 0
     n_cells = int(np.prod(P.cell_grid(params)))
     pb = phase_bytes(sysd.n, nnz, n_bond_ends, precision, n_cells, steps, fused)
     if skin > 0:
@@ -669,9 +668,9 @@ def main():
     roofline = {"bound": "hbm", "kernel": "forces", "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(head_name),
                 "algorithmic_bytes": fb,
-                # the mixed step's force launch also does the half-kicks (a1, a10)
+                # without a skin the force launch also does the half-kicks (a1, a10)
                 "algorithmic_bytes_half_kicks": head["force_bytes_half_kicks"],
-                "kernel_name": "k_force_mixed<..., kVV = true>" if head_name == "mixed" else "k_force_fp64",
+                "kernel_name": ("k_force_mixed" if head_name == "mixed" else "k_force_fp64") + "<..., kVV = true>",
                 "dominant_phase": dom,
                 # the bound the counters show: VALU issue, against the
                 # algorithmic work of each unique pair evaluated once

@@ -783,14 +783,13 @@ int dpd_step(const dpd_params* p, int32_t precision, dpd_state* st, int32_t n_st
         af.offset = kept_off;
         af.capacity = a.capacity;                        // kept rows are never longer than the list's
     }
-    // Mixed form without a skin: each step's second half-kick (and the next
-    // step's first half-kick and drift) runs in the force pass's row
-    // epilogue, which has the row's force at hand; its statistics follow the
-    // force pass.  The pass reads velocities only from the FP32 copies, never
-    // the state's v, which the last step's epilogue rewrites.  (The FP64
-    // pass keeps the separate kernel: with its operands held through the
-    // chunk it has no registers to spare.)
-    const bool fuse_vv = !skin && !job.bv.kps && mixed;
+    // Without a skin: each step's second half-kick (and the next step's
+    // first half-kick and drift) runs in the force pass's row epilogue, which
+    // has the row's force at hand; its statistics follow the force pass.  The
+    // pass reads velocities only from the reorder's copies (FP32 in the mixed
+    // form, the packed FP64 records in the FP64 form), never the state's v,
+    // which the last step's epilogue rewrites.
+    const bool fuse_vv = !skin && !job.bv.kps;
     for (int32_t k = 0; k < n_steps; ++k) {
         Job jk = job;
         int32_t* g = skin ? gates + (k & 1) : nullptr;

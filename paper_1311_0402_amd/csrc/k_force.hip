@@ -643,10 +643,17 @@ __device__ __forceinline__ bool pair64(const PT& P, const double* A, const doubl
     return true;
 }
 
-template <int kWMode, bool kB, bool kSym>
+template <int kWMode, bool kB, bool kSym, bool kVV = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_force_fp64(KParams kp, BatchView bv, ForceArgs a, int32_t n_chunks)
 {
     __shared__ double s_a[kTab], s_g[kTab], s_s[kTab];
+    // kVV (single systems): the step's half-kicks in the row epilogue, with
+    // their momentum and |v|^2 accumulators per lane
+    static_assert(!(kVV && kB), "the fused half-kick is for single systems");
+    __shared__ double s_vacc[kVV ? 6 * kBlock : 1];
+    if constexpr (kVV) {
+        for (int k = 0; k < 6; ++k) s_vacc[k * kBlock + threadIdx.x] = 0.0;
+    }
     __shared__ int32_t s_rowm[kBlock];                 // per-wave row marks (row_pos)
     // pairs once: the mirrored contributions to the wave's 64 rows
     __shared__ double s_jx[kSym ? kBlock : 1], s_jy[kSym ? kBlock : 1], s_jz[kSym ? kBlock : 1];
@@ -770,9 +777,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             a.f[2 * N + i] = fz;
             if (want_pe) a.pe[i] = pe_row + pe_b;
             if (want_np) a.npair[i] = (int32_t)np_row;
+            if constexpr (kVV) {
+                // (the operands are requested here, not held through the
+                // chunk: the pass has no registers to spare; other waves
+                // cover the wait)
+                const VVIn vin = vv_load(a, N, i);
+                vv_row(kp, a, N, i, vin, fx, fy, fz, s_vacc + threadIdx.x);
+            }
         }
     }
     if (a.fred_part) block_partials2(pe_tot, 0.5 * np_tot, a.fred_part);
+    if constexpr (kVV) vv_partials(s_vacc, a.vv_part);
 }
 
 __device__ __forceinline__ void two_sum_add(float& s, float& c, float v)
@@ -1315,7 +1330,7 @@ int force_blocks(int32_t n, int precision)
     if (cache[dev][pr] == 0) {
         int per_cu = 0, cus = 0;
         const void* f = pr ? reinterpret_cast<const void*>(&k_force_mixed<0, false, false, false>)
-                           : reinterpret_cast<const void*>(&k_force_fp64<0, false, true>);
+                           : reinterpret_cast<const void*>(&k_force_fp64<0, false, true, false>);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kBlock, 0) != hipSuccess || per_cu < 1)
             per_cu = 4;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
@@ -1349,6 +1364,17 @@ void launch_forces_t(const KParams& kp, const BatchView& bv, int precision, cons
     const dim3 grid(force_grid(a)), block(kBlock);
     const int32_t chunks = bv.kps ? bv.n_chunks : ceil_div(a.n, kChunk);
     if (precision == 0) {
+        if constexpr (!kB) {
+            if (a.vv_part) {
+                switch (kp.wmode) {
+                case 0: hipLaunchKernelGGL((k_force_fp64<0, false, kSym, true>), grid, block, 0, s, kp, bv, a, chunks); break;
+                case 1: hipLaunchKernelGGL((k_force_fp64<1, false, kSym, true>), grid, block, 0, s, kp, bv, a, chunks); break;
+                case 2: hipLaunchKernelGGL((k_force_fp64<2, false, kSym, true>), grid, block, 0, s, kp, bv, a, chunks); break;
+                default: hipLaunchKernelGGL((k_force_fp64<3, false, kSym, true>), grid, block, 0, s, kp, bv, a, chunks); break;
+                }
+                return;
+            }
+        }
         switch (kp.wmode) {
         case 0: hipLaunchKernelGGL((k_force_fp64<0, kB, kSym>), grid, block, 0, s, kp, bv, a, chunks); break;
         case 1: hipLaunchKernelGGL((k_force_fp64<1, kB, kSym>), grid, block, 0, s, kp, bv, a, chunks); break;
