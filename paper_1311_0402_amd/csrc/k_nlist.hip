@@ -330,6 +330,9 @@ __device__ __forceinline__ void nlist_lane(const KParams& kp, int32_t i, int32_t
     }
 }
 
+// workgroups of the direct pass (a few per compute unit)
+constexpr int32_t kDirectGrid = 2048;
+
 template <bool kDirect, bool kB, int kW>
 __global__ __launch_bounds__(kW * kWave) void k_nlist_lanes(KParams kp, BatchView bv, int32_t n,
                                                             const double* __restrict__ x,
@@ -343,14 +346,21 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_lanes(KParams kp, BatchVie
                                                             int32_t* __restrict__ flag, Gate gate)
 {
     if (gated_off(gate)) return;
-    const int32_t i = xcd_logical_id(blockIdx.x, gridDim.x) * (kW * kWave) + threadIdx.x;
-    if (i >= n) return;
     if (kDirect && (*flag == 0 || (int64_t)offset[n] > capacity)) return;
-    if constexpr (kB)
-        nlist_lane<kDirect>(bv.kps[bv.sys_of[i]], i, n, x, x32, cell_xyz, cell_start, rank_tab, offset, index,
-                            slab, slab_k, flag);
-    else
-        nlist_lane<kDirect>(kp, i, n, x, x32, cell_xyz, cell_start, rank_tab, offset, index, slab, slab_k, flag);
+    // (the direct pass runs on a capped grid, each lane taking every
+    // gridDim-th group of rows: it is launched for every build and returns
+    // at once unless the slab overflowed)
+    const int32_t g0 = xcd_logical_id(blockIdx.x, gridDim.x);
+    for (int64_t b = g0; b * (kW * kWave) < n; b += kDirect ? gridDim.x : (int64_t)n) {
+        const int32_t i = (int32_t)(b * (kW * kWave)) + (int32_t)threadIdx.x;
+        if (i >= n) return;
+        if constexpr (kB)
+            nlist_lane<kDirect>(bv.kps[bv.sys_of[i]], i, n, x, x32, cell_xyz, cell_start, rank_tab, offset, index,
+                                slab, slab_k, flag);
+        else
+            nlist_lane<kDirect>(kp, i, n, x, x32, cell_xyz, cell_start, rank_tab, offset, index, slab, slab_k,
+                                flag);
+    }
 }
 
 template <bool kDirect, int kW>
@@ -359,7 +369,8 @@ void launch_nlist_lanes(const KParams& kp, const BatchView& bv, int32_t n, const
                         int32_t* offset, int32_t* index, int64_t capacity, int32_t* slab, int32_t slab_k,
                         int32_t* flag, hipStream_t s, Gate gate)
 {
-    const dim3 grid(ceil_div(n, kW * kWave)), block(kW * kWave);
+    const int32_t blocks = ceil_div(n, kW * kWave);
+    const dim3 grid(kDirect && blocks > kDirectGrid ? kDirectGrid : blocks), block(kW * kWave);
     if (bv.kps)
         hipLaunchKernelGGL((k_nlist_lanes<kDirect, true, kW>), grid, block, 0, s, kp, bv, n, x, x32, cell_xyz,
                            cell_start, rank_tab, offset, index, capacity, slab, slab_k, flag, gate);

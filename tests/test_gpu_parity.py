@@ -231,6 +231,42 @@ def test_step_teacher_forced_100():
     assert sim.check_status() == 0
 
 
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision", [P.FP64, P.MIXED])
+def test_overflowing_rows_in_a_large_system(precision):
+    """A dense blob (density ~50: rows of ~200 entries, beyond the slab's
+    width) in a 700,000-particle fluid: the builder's slab is discarded and
+    the direct pass, on its capped grid (more rows than its lanes, so a lane
+    takes a second group), writes every row.  After a 2-step dpd_step call
+    a seeded sample of rows, the blob's and the last ones included, equals
+    the oracle's brute-force rows bit for bit, and their forces match."""
+    side = (700_000 / 3.0) ** (1.0 / 3.0)
+    s = di.clustered_fluid(seed=21, box=(side, side, side), n_cluster=400, n_rest=700_000, size=2.0)
+    sim = _sorted_system(s, precision)
+    sim.step(2)
+    torch.cuda.synchronize()
+    assert sim.check_status() == 0
+    x, v, f, tag, typ = sim.host_state()
+    off, idx = sim.host_nlist()
+    assert np.diff(off).max() > 128
+    blob = np.nonzero(tag < 400)[0]
+    q = np.unique(np.concatenate([np.random.default_rng(5).choice(s.n, 600, replace=False), blob[:200],
+                                  np.arange(s.n - 200, s.n)])).astype(np.int32)
+    off_ref, idx_ref = oracle.neighbors(x, s.box, s.r_c, query=q)
+    for k, i in enumerate(q):
+        np.testing.assert_array_equal(idx[off[i]:off[i + 1]], idx_ref[off_ref[k]:off_ref[k + 1]],
+                                      err_msg=f"row {i}")
+    vh = v - 0.5 * s.dt * f
+    f_ref, _, _, scale = oracle.forces(s, x, vh, tag, typ, 2, nbr=(off_ref, idx_ref), query=q, with_scale=True)
+    if precision == P.FP64:
+        _check_fp64(f[:, q], f_ref, scale)
+    else:
+        rel = np.linalg.norm(f[:, q] - f_ref) / np.linalg.norm(f_ref)
+        assert rel <= MIXED_TOL, rel
+    del sim
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("s_exp", [1.0, 2.0, 0.25])
 @pytest.mark.parametrize("precision", [P.FP64, P.MIXED])
 def test_weight_exponents(s_exp, precision):
