@@ -52,6 +52,8 @@ WsLayout ws_layout(const KParams& kp, int32_t n, bool aos = false);
 
 // ---- reorder (k_reorder.hip) ----
 hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t s, Gate gate = nullptr);
+// three single words set to zero by one launch (null pointers skipped)
+hipError_t launch_zero3(int32_t* a, int32_t* b, int32_t* c, hipStream_t s, Gate gate = nullptr);
 // rank_tab[c_off + cx + nc_x (cy + nc_y cz)] = c_off + Morton rank of the cell
 // (bv.kps == nullptr: one system, c_off = 0, c_tot = its cell count)
 hipError_t launch_rank_table(const KParams& kp, const BatchView& bv, int32_t c_tot, int32_t* rank_tab,

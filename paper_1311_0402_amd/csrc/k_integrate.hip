@@ -320,24 +320,7 @@ __global__ __launch_bounds__(kBlock) void k_drift_skin(KParams kp, int32_t n, Sk
     }
 }
 
-// fixed-order block sum: thread t adds entries t, t + 256, ... of a strided
-// array, then a fixed tree over the block
-__device__ double block_sum_strided(const double* __restrict__ src, int count, int stride, int offset)
-{
-    __shared__ double s[kBlock];
-    double acc = 0.0;
-    for (int m = threadIdx.x; m < count; m += kBlock) acc += src[(int64_t)m * stride + offset];
-    s[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
-        __syncthreads();
-    }
-    const double r = s[0];
-    __syncthreads();
-    return r;
-}
-
+// the step's statistics from the per-workgroup partials, in a fixed order
 __global__ __launch_bounds__(kBlock) void k_reduce_final(int32_t n, const double* __restrict__ red_part,
                                                          int n_red, int red_stride,
                                                          const double* __restrict__ fred_part,
@@ -345,17 +328,43 @@ __global__ __launch_bounds__(kBlock) void k_reduce_final(int32_t n, const double
                                                          double* __restrict__ stats, uint64_t* d_step,
                                                          int32_t* status, const int32_t* __restrict__ rebuilt)
 {
-    double P[3] = {0.0, 0.0, 0.0}, v2 = 0.0, pe = 0.0, pairs = 0.0;
+    // eight columns (the momentum and |v|^2 partials of the three components,
+    // the force pass's PE and pair partials): each thread sums its strided
+    // share of every column in ascending order, then one tree per column
+    // (the same order as one column at a time, with one pass of loads)
+    __shared__ double s[8][kBlock];
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (red_part) {
-        for (int k = 0; k < 3; ++k) {
-            P[k] = block_sum_strided(red_part + 2 * (int64_t)k * red_stride, n_red, 2, 0);
-            v2 += block_sum_strided(red_part + 2 * (int64_t)k * red_stride, n_red, 2, 1);
+        for (int m = threadIdx.x; m < n_red; m += kBlock) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                acc[2 * k] += red_part[2 * ((int64_t)k * red_stride + m)];
+                acc[2 * k + 1] += red_part[2 * ((int64_t)k * red_stride + m) + 1];
+            }
         }
     }
     if (fred_part) {
-        pe = block_sum_strided(fred_part, n_fred, 2, 0);
-        pairs = block_sum_strided(fred_part, n_fred, 2, 1);
+        for (int m = threadIdx.x; m < n_fred; m += kBlock) {
+            acc[6] += fred_part[2 * (int64_t)m];
+            acc[7] += fred_part[2 * (int64_t)m + 1];
+        }
     }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) s[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) s[c][threadIdx.x] += s[c][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    double P[3] = {s[0][0], s[2][0], s[4][0]};
+    double v2 = 0.0;
+    v2 += s[1][0];
+    v2 += s[3][0];
+    v2 += s[5][0];
+    const double pe = s[6][0], pairs = s[7][0];
     if (threadIdx.x == 0) {
         const double nn = (double)n;
         const double kbt = n > 1 ? (v2 - (P[0] * P[0] + P[1] * P[1] + P[2] * P[2]) / nn) / (3.0 * (nn - 1.0)) : 0.0;

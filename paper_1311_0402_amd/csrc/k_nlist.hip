@@ -885,10 +885,8 @@ hipError_t launch_nlist(const KParams& kp, const BatchView& bv, int32_t n_cells,
     hipError_t e;
     const bool tiles = kind == 0 && ranks_fit(cell_xyz, n_cells);
     const bool lanes = tiles || (kind == 2 && ranks_fit(cell_xyz, n_cells));
-    if ((e = launch_fill_i32(offset + n, 1, 0, s, gate)) != hipSuccess) return e;
-    if ((e = launch_fill_i32(flag, 1, 0, s, gate)) != hipSuccess) return e;
+    if ((e = launch_zero3(offset + n, flag, tiles ? tile_rest : nullptr, s, gate)) != hipSuccess) return e;
     if (tiles) {
-        if ((e = launch_fill_i32(tile_rest, 1, 0, s, gate)) != hipSuccess) return e;
         const int tw = nlist_tile_waves(n, n_cells);
         if (bv.kps)
             launch_nlist_tiles<true>(tw, kp, bv, n_tiles, n, x, x32, cell_xyz, cell_start, rank_tab, offset, slab,

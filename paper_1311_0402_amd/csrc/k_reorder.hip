@@ -19,6 +19,20 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t count, int32_t value
     if (i < count) p[i] = value;
 }
 
+__global__ void k_zero3(int32_t* __restrict__ a, int32_t* __restrict__ b, int32_t* __restrict__ c, Gate gate)
+{
+    if (gated_off(gate)) return;
+    if (threadIdx.x == 0 && a) *a = 0;
+    if (threadIdx.x == 1 && b) *b = 0;
+    if (threadIdx.x == 2 && c) *c = 0;
+}
+
+hipError_t launch_zero3(int32_t* a, int32_t* b, int32_t* c, hipStream_t s, Gate gate)
+{
+    hipLaunchKernelGGL(k_zero3, dim3(1), dim3(kWave), 0, s, a, b, c, gate);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t s, Gate gate)
 {
     if (count <= 0) return hipSuccess;
@@ -164,9 +178,19 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const int32_t* __restrict
     __shared__ int32_t s_wave[kBlock / kWave];
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
     int32_t sum = 0;
-    for (int k = threadIdx.x; k < kScanTile; k += kBlock) {
-        const int64_t i = base + k;
-        if (i < count) sum += data[i];
+    if (base + kScanTile <= count && (reinterpret_cast<uintptr_t>(data) & 15) == 0) {
+        // a whole tile: its items as int4 loads, all issued at once
+        const int4* __restrict__ p = reinterpret_cast<const int4*>(data + base);
+#pragma unroll
+        for (int q = 0; q < kScanTile / 4 / kBlock; ++q) {
+            const int4 v = p[threadIdx.x + q * kBlock];
+            sum += (v.x + v.y) + (v.z + v.w);
+        }
+    } else {
+        for (int k = threadIdx.x; k < kScanTile; k += kBlock) {
+            const int64_t i = base + k;
+            if (i < count) sum += data[i];
+        }
     }
     int32_t tot;
     block_excl_scan(sum, s_wave, &tot);
@@ -197,9 +221,21 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(int32_t* __restrict__ dat
     __shared__ int32_t s_tile[kScanTile + kScanTile / kItems];
     __shared__ int32_t s_wave[kBlock / kWave];
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
-    for (int k = threadIdx.x; k < kScanTile; k += kBlock) {
-        const int64_t i = base + k;
-        s_tile[k + k / kItems] = i < count ? data[i] : 0;
+    const bool whole = base + kScanTile <= count && (reinterpret_cast<uintptr_t>(data) & 15) == 0;
+    if (whole) {
+        const int4* __restrict__ p = reinterpret_cast<const int4*>(data + base);
+#pragma unroll
+        for (int q = 0; q < kScanTile / 4 / kBlock; ++q) {
+            const int k = 4 * (threadIdx.x + q * kBlock);     // 4 items of one 16-item run
+            const int4 v = p[threadIdx.x + q * kBlock];
+            const int a = k + k / kItems;
+            s_tile[a] = v.x; s_tile[a + 1] = v.y; s_tile[a + 2] = v.z; s_tile[a + 3] = v.w;
+        }
+    } else {
+        for (int k = threadIdx.x; k < kScanTile; k += kBlock) {
+            const int64_t i = base + k;
+            s_tile[k + k / kItems] = i < count ? data[i] : 0;
+        }
     }
     __syncthreads();
     const int t0 = threadIdx.x * kItems;
@@ -216,9 +252,19 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(int32_t* __restrict__ dat
         ex += v;
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < kScanTile; k += kBlock) {
-        const int64_t i = base + k;
-        if (i < count) data[i] = s_tile[k + k / kItems];
+    if (whole) {
+        int4* __restrict__ p = reinterpret_cast<int4*>(data + base);
+#pragma unroll
+        for (int q = 0; q < kScanTile / 4 / kBlock; ++q) {
+            const int k = 4 * (threadIdx.x + q * kBlock);
+            const int a = k + k / kItems;
+            p[threadIdx.x + q * kBlock] = make_int4(s_tile[a], s_tile[a + 1], s_tile[a + 2], s_tile[a + 3]);
+        }
+    } else {
+        for (int k = threadIdx.x; k < kScanTile; k += kBlock) {
+            const int64_t i = base + k;
+            if (i < count) data[i] = s_tile[k + k / kItems];
+        }
     }
 }
 
