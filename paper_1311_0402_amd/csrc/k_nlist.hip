@@ -650,10 +650,9 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
     // ---- the walk: one lane per particle of the tile ----
     // kStepW candidates of a cell per step (slots k, k + 1, ...; slots past
     // the cell's end idle, and their reads may be the spare slots past the
-    // staged range, never used).  The next step's candidates (and, on a cell
-    // change, the stencil entry after the next) are requested from LDS
-    // before the current ones are tested; two steps per loop turn alternate
-    // the buffers.
+    // staged range, never used).  The next step's candidates and the stencil
+    // entry after the next are requested from LDS before the current ones
+    // are tested; two steps per loop turn alternate the buffers.
     const float lo = P.tile_lo32, hi = P.tile_hi32;
     const int64_t N = n;
     constexpr uint32_t kCodeBits = ~0u << kSlabCodeShift;
