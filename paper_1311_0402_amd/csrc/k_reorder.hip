@@ -331,8 +331,15 @@ __device__ __forceinline__ void finalize_one(const KParams& P, int32_t n, int32_
     const uint8_t ty = g.type_in[src];
     const uint32_t packed = g.cxyz_in[src];
     const int32_t lo = cell_start[c], hi = cell_start[c + 1];
+    // the cell's first four tags are requested together (most cells hold
+    // fewer; reads past the last particle stay inside the array)
     int32_t below = 0;
-    for (int32_t q = lo; q < hi; ++q) below += (tmp_tag[q] < t) ? 1 : 0;
+    uint32_t t4[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) t4[m] = tmp_tag[lo + m < n ? lo + m : n - 1];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) below += (lo + m < hi && t4[m] < t) ? 1 : 0;
+    for (int32_t q = lo + 4; q < hi; ++q) below += (tmp_tag[q] < t) ? 1 : 0;
     const int32_t dst = lo + below;
     g.perm[dst] = src;
     if (g.inv) g.inv[src] = dst;
