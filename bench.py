@@ -27,9 +27,11 @@ if ROOT not in sys.path:
 
 METRIC = "DPD pair-force evals/s & particle-steps/s at 16M, mixed vs FP64, 1 MI355X"
 HBM_PEAK_GBS = 8000.0
-# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz full-rate 32-bit
-# lane operations (non-packed) per second, in units of 1e12
-VALU_PEAK_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12
+# VALU issue peak: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz full-rate 32-bit
+# lane operations (non-packed) per second, in units of 1e12: a SIMD issues
+# one wave64 instruction per two clocks (the FP32 vector peak, 157.3 TFLOP/s,
+# is this rate with an FMA counted as two flops)
+VALU_PEAK_TSLOTS = 256 * 4 * 32 * 2.4e9 / 1e12
 # Algorithmic lane slots of one pair evaluation (full-rate operations count
 # 1; 32-bit integer products and transcendentals, a quarter of the rate,
 # count 4).  Philox4x32-10: 20 products (80) + 40 two-input xors; the
