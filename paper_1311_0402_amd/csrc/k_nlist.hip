@@ -682,22 +682,21 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
         int32_t pn = 1;
         uint32_t ent_n = st[1];
         int32_t k = (int32_t)(cur & 0xFFFu);
-        auto test = [&](const float4& w, uint32_t ent, bool valid) {
+        // the FP32 test of one candidate: hit (inside lo) or band (between
+        // lo and hi, to be decided by the FP64 rule)
+        auto pre = [&](const float4& w, bool valid, bool& band) {
             const float dx = wi.x - w.x, dy = wi.y - w.y, dz = wi.z - w.z;
             const float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
-            const int32_t j = __float_as_int(w.w);
             const bool near = r2 < lo;
-            bool hit = valid && near && j != i;
-            // i itself has r2 = 0 < lo, so the band never holds it; the band
-            // is rare, so the wave branches on its ballot
-            const bool band = valid && !near && r2 < hi;
-            if (__builtin_expect(__ballot(band) != 0ull, 0)) {
-                if (band) hit = exact_hit(P, x, N, i, j);
-            }
+            band = valid && !near && r2 < hi;
+            // i itself has r2 = 0 < lo, so the band never holds it
+            return valid && near && __float_as_int(w.w) != i;
+        };
+        auto store = [&](const float4& w, uint32_t ent, bool hit) {
             // every lane stores: a miss at an offset past the rows' range,
             // which the buffer's range check drops (no branch per candidate)
-            __builtin_amdgcn_raw_buffer_store_b32((int32_t)((ent & kCodeBits) | (uint32_t)j), rows,
-                                                  hit ? rb : kDropOff, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32((int32_t)((ent & kCodeBits) | (uint32_t)__float_as_int(w.w)),
+                                                  rows, hit ? rb : kDropOff, 0, 0);
             rb += hit ? (int32_t)sizeof(int32_t) : 0;
         };
         // one step on the candidates at slots k .. k + kStepW - 1 (those below
@@ -717,9 +716,21 @@ __global__ __launch_bounds__(kW * kWave) void k_nlist_tiles(KParams kp, BatchVie
 #pragma unroll
             for (int m = 0; m < kStepW; ++m) nxt.w[m] = p[m];
             ent_n = st[pn];
-            test(cw.w[0], ent, true);
+            bool hit[kStepW], band[kStepW];
+            bool any_band = false;
 #pragma unroll
-            for (int m = 1; m < kStepW; ++m) test(cw.w[m], ent, m < left);
+            for (int m = 0; m < kStepW; ++m) {
+                hit[m] = pre(cw.w[m], m == 0 || m < left, band[m]);
+                any_band = any_band || band[m];
+            }
+            // the band is rare: the wave branches once per step on its ballot
+            if (__builtin_expect(__ballot(any_band) != 0ull, 0)) {
+#pragma unroll
+                for (int m = 0; m < kStepW; ++m)
+                    if (band[m]) hit[m] = exact_hit(P, x, N, i, __float_as_int(cw.w[m].w));
+            }
+#pragma unroll
+            for (int m = 0; m < kStepW; ++m) store(cw.w[m], ent, hit[m]);
             return pn <= nne;
         };
         StepW s0, s1;
